@@ -1,0 +1,174 @@
+"""Seeded synthetic workloads for QFactor instantiation (inputs only).
+
+This module draws the random arrays that both the FP64 oracle and the GPU
+library consume: Haar-random two-qubit gates, circuit structures (open-chain
+brick-walls, random nearest-neighbour blocks), target unitaries built from
+seeded gates on the same structure, and random initial gates for the
+multistarts.  It holds none of the instantiation method's arithmetic (no
+environment, no SVD update, no cost, no termination logic).
+
+The paper evaluates on partitions of real benchmark circuits; those are not
+available here, so seeded Haar brick-walls of the same qubit counts and gate
+volumes stand in for them (one general U(4) gate is worth about three CNOTs
+plus single-qubit gates).
+
+Conventions shared with the rest of the project:
+  * n qubits, N = 2**n; qubit 0 is the most significant bit of a row/column
+    index; a gate's local index is built from its qubits in the listed order
+    (loc[0] is the local most significant bit).
+  * gates are listed in time order, so the circuit unitary is
+    C = G_p ... G_2 G_1.
+  * random streams come from numpy's PCG64 seeded with
+    SeedSequence([config_id, role, index]); role 0 = target gates,
+    role 1 = initial gates, index = start (or block).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ROLE_TARGET = 0
+ROLE_INIT = 1
+ROLE_STRUCTURE = 2
+
+
+def rng_for(config_id: int, role: int, index: int) -> np.random.Generator:
+    """Independent PCG64 stream for (config, role, index)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([config_id, role, index])))
+
+
+def haar_unitary(rng: np.random.Generator, d: int) -> np.ndarray:
+    """Haar-distributed d x d unitary (QR of a complex Ginibre matrix with the
+    phase correction of Mezzadri, 'How to generate random matrices from the
+    classical compact groups', Notices AMS 54 (2007))."""
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    diag = np.diagonal(r)
+    ph = diag / np.abs(diag)
+    return (q * ph[None, :]).astype(np.complex128)
+
+
+def haar_gates(rng: np.random.Generator, count: int, d: int = 4) -> np.ndarray:
+    """count x d x d stack of Haar unitaries drawn in order from rng."""
+    return np.stack([haar_unitary(rng, d) for _ in range(count)]) if count else np.zeros((0, d, d), np.complex128)
+
+
+def brickwall_locations(n: int, layers: int) -> np.ndarray:
+    """Open-chain brick-wall: even layers act on (0,1),(2,3),...; odd layers on
+    (1,2),(3,4),...  Returns a (p, 2) int32 array in time order."""
+    locs = []
+    for layer in range(layers):
+        start = 0 if layer % 2 == 0 else 1
+        for q in range(start, n - 1, 2):
+            locs.append((q, q + 1))
+    return np.asarray(locs, dtype=np.int32).reshape(-1, 2)
+
+
+def random_nn_locations(rng: np.random.Generator, n: int, count: int) -> np.ndarray:
+    """count nearest-neighbour pairs (q, q+1) with q uniform in [0, n-2]."""
+    qs = rng.integers(0, n - 1, size=count)
+    return np.stack([qs, qs + 1], axis=1).astype(np.int32)
+
+
+def circuit_unitary(gates: np.ndarray, locs: np.ndarray, n: int) -> np.ndarray:
+    """Target construction: C = G_p ... G_1 for two-qubit gates in time order.
+
+    Each gate is applied to the running matrix by viewing its row index as n
+    binary legs (qubit 0 first) and contracting the gate with the two legs it
+    acts on.  Used only to synthesise targets from seeded gates."""
+    N = 1 << n
+    c = np.eye(N, dtype=np.complex128)
+    for u, (a, b) in zip(gates, locs):
+        t = c.reshape((2,) * n + (N,))
+        u4 = np.asarray(u, np.complex128).reshape(2, 2, 2, 2)
+        t = np.tensordot(u4, t, axes=([2, 3], [int(a), int(b)]))
+        t = np.moveaxis(t, [0, 1], [int(a), int(b)])
+        c = np.ascontiguousarray(t.reshape(N, N))
+    return c
+
+
+@dataclass
+class Problem:
+    """One instantiation problem: target V, structure and initial gates."""
+
+    name: str
+    n: int
+    locs: np.ndarray            # (p, 2) int32
+    target_gates: np.ndarray    # (p, 4, 4) complex128, the gates V was built from
+    target: np.ndarray          # (N, N) complex128 (may be None for huge n until built)
+    init_gates: np.ndarray      # (S, p, 4, 4) complex128
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_gates(self) -> int:
+        return int(self.locs.shape[0])
+
+    @property
+    def n_starts(self) -> int:
+        return int(self.init_gates.shape[0])
+
+
+def make_problem(config_id: int, name: str, n: int, locs: np.ndarray, n_starts: int,
+                 build_target: bool = True, block: int = 0) -> Problem:
+    """Target from Haar gates (role 0, index=block) on `locs`; init gates for each
+    start s from stream (role 1, index=block*65536+s)."""
+    p = int(locs.shape[0])
+    tg = haar_gates(rng_for(config_id, ROLE_TARGET, block), p)
+    init = np.stack([haar_gates(rng_for(config_id, ROLE_INIT, block * 65536 + s), p)
+                     for s in range(n_starts)]) if n_starts else np.zeros((0, p, 4, 4), np.complex128)
+    target = circuit_unitary(tg, locs, n) if build_target else None
+    return Problem(name, n, np.asarray(locs, np.int32), tg, target, init)
+
+
+# ---------------------------------------------------------------------------
+# The five evaluation workloads (sizes, structures, starts).
+# ---------------------------------------------------------------------------
+
+C1 = dict(config_id=1, name="n3_p4_c128", n=3, locs=[(0, 1), (1, 2), (0, 1), (1, 2)], starts=1,
+          tol=1e-10, max_iter=1000)
+C2 = dict(config_id=2, name="n6_brickwall6_s32", n=6, layers=6, starts=32, tol=1e-8)
+C3 = dict(config_id=3, name="n10_brickwall10_s16_c64", n=10, layers=10, starts=16, tol=1e-8)
+C4 = dict(config_id=4, name="batch4096_n3n4_s8", blocks=4096, starts=8, tol=1e-8)
+C5 = dict(config_id=5, name="n12_brickwall8_s1_c64", n=12, layers=8, starts=1, tol=1e-8)
+
+
+def config1() -> Problem:
+    locs = np.asarray(C1["locs"], np.int32)
+    return make_problem(C1["config_id"], C1["name"], C1["n"], locs, C1["starts"])
+
+
+def config2(n_starts: int = C2["starts"]) -> Problem:
+    return make_problem(C2["config_id"], C2["name"], C2["n"], brickwall_locations(C2["n"], C2["layers"]), n_starts)
+
+
+def config3(n_starts: int = C3["starts"], build_target: bool = True) -> Problem:
+    return make_problem(C3["config_id"], C3["name"], C3["n"], brickwall_locations(C3["n"], C3["layers"]),
+                        n_starts, build_target=build_target)
+
+
+def config5(n_starts: int = C5["starts"], build_target: bool = True) -> Problem:
+    return make_problem(C5["config_id"], C5["name"], C5["n"], brickwall_locations(C5["n"], C5["layers"]),
+                        n_starts, build_target=build_target)
+
+
+def config4_blocks(n_blocks: int = C4["blocks"], n_starts: int = C4["starts"], build_target: bool = True):
+    """Batched workload: half 3-qubit, half 4-qubit blocks, each a random
+    nearest-neighbour circuit of U{4..20} gates, target from Haar gates on its
+    own structure.  Returns a list of Problems."""
+    probs = []
+    for b in range(n_blocks):
+        rs = rng_for(C4["config_id"], ROLE_STRUCTURE, b)
+        n = 3 if b < n_blocks // 2 else 4
+        count = int(rs.integers(4, 21))
+        locs = random_nn_locations(rs, n, count)
+        probs.append(make_problem(C4["config_id"], f"block{b}", n, locs, n_starts,
+                                  build_target=build_target, block=b))
+    return probs
+
+
+def random_builder(rng: np.random.Generator, n_starts: int, n: int) -> np.ndarray:
+    """Generic complex test matrices (S, N, N) with entries ~ CN(0, 1/N)."""
+    N = 1 << n
+    x = rng.standard_normal((n_starts, N, N)) + 1j * rng.standard_normal((n_starts, N, N))
+    return (x / np.sqrt(2.0 * N)).astype(np.complex128)

@@ -1,0 +1,394 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+None of these re-types the oracle's own formula: each checks it against an
+independent construction (dense Kronecker products, brute-force derivatives,
+closed-form solutions, inequalities, invariants stated in the paper)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import qfinputs as I
+
+RNG = np.random.default_rng(20230613)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def haar(d, rng=RNG):
+    return I.haar_unitary(rng, d)
+
+
+def rand_gates(p, rng=RNG):
+    return np.stack([haar(4, rng) for _ in range(p)])
+
+
+def rand_locs(n, p, rng=RNG):
+    out = []
+    for _ in range(p):
+        a, b = rng.choice(n, size=2, replace=False)
+        out.append((int(a), int(b)))
+    return np.asarray(out, np.int32)
+
+
+def all_pairs(n):
+    return [(a, b) for a in range(n) for b in range(n) if a != b]
+
+
+# ---------------------------------------------------------------- embedding
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_embed_adjacent_is_textbook_kron(n):
+    """Adjacent ascending pair (q, q+1): I_{2^q} (x) u (x) I_{2^(n-q-2)}."""
+    u = haar(4)
+    for q in range(n - 1):
+        ref = np.kron(np.kron(np.eye(1 << q), u), np.eye(1 << (n - q - 2)))
+        assert np.array_equal(O.embed(u, (q, q + 1), n), ref)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_embed_general_pairs_match_swap_network(n):
+    u = haar(4)
+    for loc in all_pairs(n):
+        np.testing.assert_allclose(O.embed(u, loc, n), O.embed_kron(u, loc, n), atol=1e-15)
+
+
+def test_embed_reversed_pair_is_swap_conjugate():
+    """Gate on (1, 0) equals SWAP u SWAP on (0, 1)."""
+    u = haar(4)
+    sw = np.eye(4)[[0, 2, 1, 3]]
+    np.testing.assert_allclose(O.embed(u, (1, 0), 2), sw @ u @ sw, atol=0)
+    np.testing.assert_allclose(O.embed(u, (2, 0), 3), O.embed(sw @ u @ sw, (0, 2), 3), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_structured_apply_equals_dense(n):
+    N = 1 << n
+    X = I.random_builder(RNG, 1, n)[0]
+    for loc in all_pairs(n)[:12]:
+        u = haar(4)
+        G = O.embed(u, loc, n)
+        np.testing.assert_allclose(O.apply_left(X, u, loc, n), G @ X, atol=1e-13)
+        np.testing.assert_allclose(O.apply_right(X, u, loc, n), X @ G, atol=1e-13)
+    # batched, one gate per batch entry
+    Xs = I.random_builder(RNG, 3, n)
+    us = rand_gates(3)
+    loc = (n - 1, 0)
+    out = O.apply_left(Xs, us, loc, n)
+    for s in range(3):
+        np.testing.assert_allclose(out[s], O.embed(us[s], loc, n) @ Xs[s], atol=1e-13)
+    out = O.apply_right(Xs, us, loc, n)
+    for s in range(3):
+        np.testing.assert_allclose(out[s], Xs[s] @ O.embed(us[s], loc, n), atol=1e-13)
+    assert N == Xs.shape[-1]
+
+
+def test_circuit_unitary_dense_structured_and_inputs_agree():
+    n, p = 4, 7
+    g = rand_gates(p)
+    locs = rand_locs(n, p)
+    Cd = O.circuit_unitary(g, locs, n, dense=True)
+    Cs = O.circuit_unitary(g, locs, n)
+    Ci = I.circuit_unitary(g, locs, n)
+    np.testing.assert_allclose(Cs, Cd, atol=1e-13)
+    np.testing.assert_allclose(Ci, Cd, atol=1e-13)
+    np.testing.assert_allclose(Cd.conj().T @ Cd, np.eye(1 << n), atol=1e-13)
+    # time order: C = G_p ... G_1
+    ref = np.eye(1 << n)
+    for u, l in zip(g, locs):
+        ref = O.embed_kron(u, l, n) @ ref
+    np.testing.assert_allclose(Cd, ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------- cost
+
+def test_cost_closed_forms():
+    n = 3
+    V = haar(8)
+    assert abs(1.0 - abs(O.overlap(V, V)) / 8) < 1e-15
+    assert abs(1.0 - abs(O.overlap(V, np.exp(0.7j) * V)) / 8) < 1e-15  # global phase
+    X = np.array([[0, 1], [1, 0]])
+    C = np.kron(X, np.eye(4))                                          # traceless vs I
+    assert abs(1.0 - abs(O.overlap(np.eye(8), C)) / 8 - 1.0) < 1e-15
+
+
+def test_frobenius_identity_eq_cost():
+    """||U - V||^2 = 2^(n+1) (1 - Re Tr(V^dagger U) / 2^n) (Eq. cost)."""
+    for n in (2, 3, 5):
+        N = 1 << n
+        U, V = haar(N), haar(N)
+        lhs = O.frobenius_distance_sq(V, U)
+        rhs = 2 * N * (1 - np.real(O.overlap(V, U)) / N)
+        assert abs(lhs - rhs) < 1e-12 * N
+
+
+# ---------------------------------------------------------------- environment
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_partial_trace_forms_and_identity(n):
+    X = I.random_builder(RNG, 1, n)[0]
+    for loc in all_pairs(n):
+        E = O.partial_trace(X, loc, n)
+        np.testing.assert_allclose(E, O.partial_trace_loops(X, loc, n), atol=1e-14)
+        u = RNG.standard_normal((4, 4)) + 1j * RNG.standard_normal((4, 4))
+        # Tr((u (x) I) X) = Tr(E u) for any u (defines the orientation of E)
+        lhs = np.trace(O.embed(u, loc, n) @ X)
+        assert abs(lhs - np.trace(E @ u)) < 1e-13
+
+
+def _problem(n, p, rng=RNG):
+    locs = rand_locs(n, p, rng)
+    V = haar(1 << n, rng)
+    gates = rand_gates(p, rng)
+    return V, gates, locs
+
+
+@pytest.mark.parametrize("n,p", [(2, 3), (3, 5), (4, 6), (5, 8)])
+def test_trace_invariant_every_gate(n, p):
+    """Tr(E_g u_g) = Tr(V^dagger C) for every gate g (Sec. III)."""
+    V, gates, locs = _problem(n, p)
+    T = O.overlap(V, O.circuit_unitary(gates, locs, n, dense=True))
+    for g in range(p):
+        E = O.environment(V, gates, locs, n, g)
+        assert abs(np.trace(E @ gates[g]) - T) < 1e-12 * (1 << n)
+
+
+@pytest.mark.parametrize("n,p", [(2, 2), (3, 4), (4, 5)])
+def test_environment_is_brute_force_derivative(n, p):
+    """T is linear in u_g, so E_g[i, j] = T(u_g := e_{ji}) exactly, and a
+    central difference of any step reproduces it (dense circuit products)."""
+    V, gates, locs = _problem(n, p)
+
+    def T_with(g, m):
+        gg = [x for x in gates]
+        gg[g] = m
+        C = np.eye(1 << n, dtype=complex)
+        for u, l in zip(gg, locs):
+            C = O.embed(u, l, n) @ C
+        return np.trace(V.conj().T @ C)
+
+    for g in range(p):
+        E = O.environment(V, gates, locs, n, g)
+        brute = np.zeros((4, 4), complex)
+        for i in range(4):
+            for j in range(4):
+                unit = np.zeros((4, 4), complex)
+                unit[j, i] = 1.0
+                brute[i, j] = T_with(g, unit)
+        np.testing.assert_allclose(E, brute, atol=1e-13)
+        # central difference around the current gate, h = 1e-4
+        i, j = 1, 2
+        unit = np.zeros((4, 4), complex)
+        unit[j, i] = 1.0
+        fd = (T_with(g, gates[g] + 1e-4 * unit) - T_with(g, gates[g] - 1e-4 * unit)) / 2e-4
+        assert abs(fd - E[i, j]) < 1e-9
+
+
+# ---------------------------------------------------------------- gate update
+
+def test_update_unitary_and_locally_optimal():
+    """u_new is unitary and maximises Re Tr(E u) over unitaries: the value is
+    the nuclear norm of E and no Haar unitary does better (Sec. III-A-1)."""
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        E = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+        if trial == 0:
+            E[:, 3] = E[:, 0] * 0.5   # rank deficient
+        u = O.optimize_gate(E, haar(4, rng))
+        assert np.abs(u.conj().T @ u - np.eye(4)).max() < 1e-12
+        best = np.real(np.trace(E @ u))
+        assert abs(best - O.nuclear_norm(E)) < 1e-12 * max(1.0, O.nuclear_norm(E))
+        for _ in range(200):
+            W = haar(4, rng)
+            assert np.real(np.trace(E @ W)) <= best + 1e-12
+
+
+def test_update_polar_closed_form():
+    """E = P W with P Hermitian positive definite and W unitary: the maximiser
+    is W^dagger (Re Tr(P W W^dagger) = Tr P = sum of singular values)."""
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        W = haar(4, rng)
+        A = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+        P = A @ A.conj().T + 0.1 * np.eye(4)
+        u = O.optimize_gate(P @ W, haar(4, rng))
+        np.testing.assert_allclose(u, W.conj().T, atol=1e-12)
+        # scaled unitary environment: E = c * w^dagger -> u = w
+        w = haar(4, rng)
+        np.testing.assert_allclose(O.optimize_gate(3.7 * w.conj().T, haar(4, rng)), w, atol=1e-13)
+
+
+def test_beta_limits():
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    u0 = haar(4, rng)
+    np.testing.assert_allclose(O.optimize_gate(E, u0, beta=1.0), u0, atol=1e-13)   # no update
+    np.testing.assert_allclose(O.optimize_gate(E, u0, beta=0.0), O.optimize_gate(E, haar(4, rng)), atol=1e-14)
+    np.testing.assert_array_equal(O.optimize_gate(np.zeros((4, 4)), u0), u0)       # zero env keeps gate
+
+
+def test_single_gate_covering_all_qubits():
+    """n = k = 2, one gate: E = V^dagger, the update returns V, cost 0."""
+    V = haar(4)
+    u0 = haar(4)
+    E = O.environment(V, [u0], [(0, 1)], 2, 0)
+    np.testing.assert_allclose(E, V.conj().T, atol=1e-15)
+    res = O.instantiate(V, u0[None, None], [(0, 1)], 2, tol=1e-12, opt=O.Options(max_iter=3))
+    assert res.costs[0] < 1e-14 and res.sweeps == 1
+    np.testing.assert_allclose(res.gates[0], V, atol=1e-13)
+    # reversed location: the gate equals SWAP V SWAP
+    res = O.instantiate(V, u0[None, None], [(1, 0)], 2, tol=1e-12, opt=O.Options(max_iter=3))
+    sw = np.eye(4)[[0, 2, 1, 3]]
+    np.testing.assert_allclose(res.gates[0], sw @ V @ sw, atol=1e-13)
+
+
+def test_product_target_one_sweep():
+    """V = a (x) b with gates on (0,1) and (2,3): one sweep reaches cost 0
+    (closed form: each update is the polar factor of a scaled unitary)."""
+    rng = np.random.default_rng(3)
+    a, b = haar(4, rng), haar(4, rng)
+    V = np.kron(a, b)
+    init = rand_gates(2, rng)
+    res = O.instantiate(V, init[None], [(0, 1), (2, 3)], 4, tol=1e-13, opt=O.Options(max_iter=5))
+    assert res.sweeps == 1 and res.costs[0] < 1e-13
+    C = O.circuit_unitary(res.gates, [(0, 1), (2, 3)], 4)
+    assert abs(abs(np.trace(V.conj().T @ C)) - 16) < 1e-12
+
+
+# ---------------------------------------------------------------- sweep invariants
+
+def test_fixed_point_of_own_circuit():
+    """Init gates = the target's gates: cost 0, E_g = 2^(n-2) u_g^dagger, and a
+    sweep leaves every gate unchanged."""
+    pr = I.config2(n_starts=1)
+    n = pr.n
+    assert O.cost(pr.target, pr.target_gates, pr.locs, n) < 1e-14
+    for g in (0, 7, pr.n_gates - 1):
+        E = O.environment(pr.target, pr.target_gates, pr.locs, n, g)
+        np.testing.assert_allclose(E, (1 << (n - 2)) * pr.target_gates[g].conj().T, atol=1e-12)
+    new = O.sweep_definition(pr.target, pr.target_gates, pr.locs, n)
+    np.testing.assert_allclose(new, pr.target_gates, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,p", [(3, 4), (4, 7), (5, 9)])
+def test_sweep_monotone_turnaround_and_frobenius(n, p):
+    V, gates, locs = _problem(n, p)
+    N = 1 << n
+    rec = []
+    new = O.sweep_definition(V, gates, locs, n, record=rec)
+    T0 = O.overlap(V, O.circuit_unitary(gates, locs, n))
+    prev = abs(T0)
+    for (g, half, E, u, T) in rec:
+        assert abs(T) >= prev - 1e-13 * N             # never decreases (Sec. III-A)
+        assert abs(T.imag) <= 1e-12 * N and T.real >= 0   # real after a beta=0 update
+        assert np.abs(u.conj().T @ u - np.eye(4)).max() < 1e-12
+        prev = abs(T)
+    # turnaround: the first update of the second half sees the last env of the first half
+    first_half_last = rec[p - 1]
+    second_first = rec[p]
+    assert first_half_last[0] == second_first[0] == 0
+    np.testing.assert_allclose(second_first[3], first_half_last[3], atol=1e-12)
+    # Frobenius identity after the sweep: ||C - V||^2 = 2 N Delta
+    C = O.circuit_unitary(new, locs, n)
+    delta = 1 - abs(O.overlap(V, C)) / N
+    assert abs(O.frobenius_distance_sq(V, C) - 2 * N * delta) < 1e-12 * N
+
+
+@pytest.mark.parametrize("n,p,S", [(3, 5, 2), (5, 8, 3), (7, 6, 2)])
+def test_builder_mode_equals_definition_mode(n, p, S):
+    """Alg. 1's circuit tensor gives the same environments and gates as the
+    from-scratch definition, update by update."""
+    rng = np.random.default_rng(100 + n)
+    V, _, locs = _problem(n, p, rng)
+    starts = np.stack([rand_gates(p, rng) for _ in range(S)])
+    b = O.BuilderOracle(V, starts, locs, n)
+    recb = []
+    b.sweep(record=recb)
+    b.sweep(record=recb)
+    for s in range(S):
+        recd = []
+        g1 = O.sweep_definition(V, starts[s], locs, n, record=recd)
+        O.sweep_definition(V, g1, locs, n, record=recd)
+        assert len(recd) == len(recb)
+        for (gd, hd, Ed, ud, Td), (gb, hb, Eb, ub, Tb) in zip(recd, recb):
+            assert (gd, hd) == (gb, hb)
+            np.testing.assert_allclose(Eb[s], Ed, atol=1e-12 * (1 << n))
+            np.testing.assert_allclose(ub[s], ud, atol=1e-11)
+            assert abs(Tb[s] - Td) < 1e-11 * (1 << n)
+
+
+# ---------------------------------------------------------------- termination
+
+def test_plateau_readings():
+    opt = O.Options()
+    hist = [np.array([1.0]), np.array([0.5])]
+    assert not O.qfactor_oracle._plateau_flags(hist, 1, opt)[0]
+    hist = [np.array([0.5]), np.array([0.5 - 0.5 * 0.9e-5])]       # relative gain < 1e-5
+    assert O.qfactor_oracle._plateau_flags(hist, 1, opt)[0]
+    hist = [np.array([0.5]), np.array([0.5 - 0.5 * 1.1e-5])]       # relative gain > 1e-5
+    assert not O.qfactor_oracle._plateau_flags(hist, 1, opt)[0]
+    # long plateau: 100 sweeps that together gain less than 10 %
+    c = [np.array([1.0 * (0.9991 ** k)]) for k in range(101)]
+    assert O.qfactor_oracle._plateau_flags(c, 100, opt)[0]
+    c = [np.array([1.0 * (0.998 ** k)]) for k in range(101)]
+    assert not O.qfactor_oracle._plateau_flags(c, 100, opt)[0]
+    # tests switched off
+    off = O.Options(diff_tol_r=0.0, long_diff_count=0)
+    hist = [np.array([0.5]), np.array([0.5])]
+    assert not O.qfactor_oracle._plateau_flags(hist, 1, off)[0]
+
+
+def test_multistart_any_converged_stops_and_best_start():
+    pr = I.config1()
+    # start 1 is the target's own gates -> converges in the first sweep
+    init = np.stack([pr.init_gates[0], pr.target_gates])
+    res = O.instantiate(pr.target, init, pr.locs, pr.n, tol=1e-10, opt=O.Options(max_iter=50))
+    assert res.status == O.STATUS_CONVERGED and res.sweeps == 1 and res.best_start == 1
+
+
+def test_max_iter_and_gauge_invariant_comparison():
+    pr = I.config1()
+    res = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-10,
+                        opt=O.Options(max_iter=7, diff_tol_r=0.0, long_diff_count=0))
+    assert res.status == O.STATUS_MAX_ITER and res.sweeps == 7 and res.history.shape == (8, 1)
+    assert np.all(np.diff(res.history[:, 0]) <= 1e-14)
+    # two different converged solutions realise the same unitary up to phase
+    conv = []
+    for s in range(12):
+        init = I.haar_gates(I.rng_for(1, 1, 1000 + s), 4)[None]
+        r = O.instantiate(pr.target, init, pr.locs, pr.n, tol=1e-10,
+                          opt=O.Options(max_iter=300, diff_tol_r=0.0, long_diff_count=0))
+        if r.status == O.STATUS_CONVERGED:
+            conv.append(O.circuit_unitary(r.gates, pr.locs, pr.n))
+        if len(conv) == 2:
+            break
+    assert len(conv) == 2
+    assert abs(np.trace(conv[0].conj().T @ conv[1])) / 8 >= 1 - 4e-10
+
+
+def test_nan_start_is_frozen():
+    pr = I.config1()
+    bad = pr.init_gates[0].copy()
+    bad[2, 1, 1] = np.nan
+    init = np.stack([bad, pr.target_gates])
+    res = O.instantiate(pr.target, init, pr.locs, pr.n, tol=1e-10, opt=O.Options(max_iter=5))
+    assert res.best_start == 1 and res.status == O.STATUS_CONVERGED and not np.isfinite(res.costs[0])
+
+
+def test_default_hyperparameters_match_paper():
+    with open(os.path.join(GOLDEN, "default_hyperparameters.json")) as f:
+        ref = json.load(f)
+    opt = O.Options()
+    for k in ("dist_tol", "diff_tol_a", "diff_tol_r", "long_diff_count", "long_diff_r",
+              "min_iter", "max_iter", "reset_iter", "beta"):
+        assert getattr(opt, k) == ref[k], k
+
+
+def test_inputs_targets_are_their_own_circuits():
+    for pr in (I.config1(), I.config2(n_starts=2)):
+        assert O.cost(pr.target, pr.target_gates, pr.locs, pr.n) < 1e-14
+        assert pr.init_gates.shape == (pr.n_starts, pr.n_gates, 4, 4)
+    assert I.brickwall_locations(6, 6).shape == (15, 2)
+    assert I.brickwall_locations(10, 10).shape == (45, 2)
+    assert I.brickwall_locations(12, 8).shape == (44, 2)
