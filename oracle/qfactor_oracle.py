@@ -65,7 +65,7 @@ __all__ = [
     "overlap", "cost", "partial_trace", "partial_trace_loops", "environment",
     "optimize_gate", "sweep_definition", "BuilderOracle", "instantiate",
     "STATUS_CONVERGED", "STATUS_PLATEAU", "STATUS_MAX_ITER", "STATUS_NUMERIC",
-    "nuclear_norm", "frobenius_distance_sq", "optimize_gate_batched",
+    "nuclear_norm", "frobenius_distance_sq", "optimize_gate_batched", "builder_rows",
 ]
 
 STATUS_CONVERGED = 0
@@ -146,9 +146,10 @@ def embed_kron(u: np.ndarray, loc, n: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def apply_left(X: np.ndarray, u: np.ndarray, loc, n: int) -> np.ndarray:
-    """G X for G = u on loc.  X may carry one leading batch axis (S, N, N) and
-    u may then be (S, 4, 4) (one gate per batch entry) or (4, 4)."""
-    N = 1 << n
+    """G X for G = u on loc.  X is (N, M) (any number M of columns) or carries
+    one leading batch axis (S, N, M); u may then be (S, 4, 4) (one gate per
+    batch entry) or (4, 4)."""
+    M = X.shape[-1]
     a, b = int(loc[0]), int(loc[1])
     batch = X.shape[:-2]
     if u.ndim == 2:
@@ -160,7 +161,7 @@ def apply_left(X: np.ndarray, u: np.ndarray, loc, n: int) -> np.ndarray:
     out_l[a], out_l[b] = 'O', 'P'
     uin = z + 'OP' + lt[a] + lt[b]
     xo = z + ''.join(out_l) + 'Y'
-    Xr = X.reshape(batch + (2,) * n + (N,))
+    Xr = X.reshape(batch + (2,) * n + (M,))
     ur = u.reshape(batch + (2, 2, 2, 2))
     out = np.einsum(f"{uin},{xin}->{xo}", ur, Xr, optimize=True)
     return out.reshape(X.shape)
@@ -193,6 +194,19 @@ def circuit_unitary(gates, locs, n: int, dense: bool = False) -> np.ndarray:
     for u, loc in zip(gates, locs):
         C = embed(u, loc, n) @ C if dense else apply_left(C, u, loc, n)
     return C
+
+
+def builder_rows(V: np.ndarray, gates, locs, n: int, rows) -> np.ndarray:
+    """Selected rows of the circuit tensor X = G_p ... G_1 V^dagger, one by
+    one: row r of C is (C^T e_r)^T with C^T = G_1^T ... G_p^T, and the row of
+    X is that row times V^dagger."""
+    N = 1 << n
+    E = np.zeros((N, len(rows)), dtype=np.complex128)
+    for k, r in enumerate(rows):
+        E[r, k] = 1.0
+    for u, loc in reversed(list(zip(gates, locs))):
+        E = apply_left(E, np.asarray(u).T, loc, n)
+    return E.T @ V.conj().T
 
 
 def overlap(V: np.ndarray, C: np.ndarray) -> complex:
@@ -280,8 +294,16 @@ def optimize_gate(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.nda
 
 
 def optimize_gate_batched(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.ndarray:
-    """optimize_gate over a leading batch axis."""
-    return np.stack([optimize_gate(E[s], u_old[s], beta) for s in range(E.shape[0])])
+    """optimize_gate over a leading batch axis (one stacked LAPACK SVD call;
+    the zero and non-finite guards are applied per entry afterwards)."""
+    M = (1.0 - beta) * E + beta * np.conj(np.swapaxes(u_old, -1, -2))
+    finite = np.all(np.isfinite(M), axis=(-2, -1))
+    zero = np.linalg.norm(np.where(finite[:, None, None], M, 0.0), axis=(-2, -1)) <= 1e-300
+    Ms = np.where((finite & ~zero)[:, None, None], M, np.eye(4))
+    Xs, _, Yh = np.linalg.svd(Ms)
+    out = np.conj(np.swapaxes(Yh, -1, -2)) @ np.conj(np.swapaxes(Xs, -1, -2))
+    out = np.where(zero[:, None, None], u_old, out)
+    return np.where(finite[:, None, None], out, np.nan + 0j)
 
 
 # ---------------------------------------------------------------------------

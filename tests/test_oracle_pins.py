@@ -392,3 +392,29 @@ def test_inputs_targets_are_their_own_circuits():
     assert I.brickwall_locations(6, 6).shape == (15, 2)
     assert I.brickwall_locations(10, 10).shape == (45, 2)
     assert I.brickwall_locations(12, 8).shape == (44, 2)
+
+
+def test_batched_update_matches_single():
+    rng = np.random.default_rng(21)
+    E = rng.standard_normal((6, 4, 4)) + 1j * rng.standard_normal((6, 4, 4))
+    E[2] = 0.0
+    E[4, 1, 1] = np.nan
+    U = np.stack([haar(4, rng) for _ in range(6)])
+    for beta in (0.0, 0.3):
+        B = O.optimize_gate_batched(E, U, beta)
+        for s in range(6):
+            ref = O.optimize_gate(E[s], U[s], beta)
+            if np.all(np.isfinite(ref)):
+                np.testing.assert_allclose(B[s], ref, atol=1e-13)
+            else:
+                assert not np.any(np.isfinite(B[s]))
+
+
+def test_builder_rows_one_by_one():
+    """Rows of G_p ... G_1 V^dagger computed from single basis rows agree with
+    the full dense product."""
+    n, p = 5, 6
+    V, gates, locs = _problem(n, p)
+    X = O.circuit_unitary(gates, locs, n, dense=True) @ V.conj().T
+    rows = [0, 3, 17, 31]
+    np.testing.assert_allclose(O.builder_rows(V, gates, locs, n, rows), X[rows], atol=1e-13)
