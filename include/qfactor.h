@@ -1,0 +1,215 @@
+/*
+ * qfactor.h -- C ABI of the MI355X (gfx950) QFactor instantiation library.
+ *
+ * QFactor (arXiv 2306.08152) instantiates a circuit of p general two-qubit
+ * gates u_1..u_p to an n-qubit target unitary V (N = 2^n) by maximising
+ * |Tr(V^dagger C)|, C = G_p ... G_1 (Sec. II, problem statement).  It keeps
+ * the "circuit tensor" (here: the builder) X with Tr(X) = Tr(V^dagger C),
+ * peels one gate off X, partial-traces the rest into a 4x4 environment E,
+ * replaces the gate by the unitary that maximises Re Tr(E u) (SVD
+ * E = X D Y^dagger -> u = Y X^dagger, Sec. III-A-1) and re-applies it on the
+ * other side, sweeping p..1 and then 1..p (TwoSidedSweep of Alg. 1) until the
+ * cost Delta = 1 - |Tr(V^dagger C)|/N meets a termination test (Sec. III-A-2).
+ *
+ * Conventions (every entry point):
+ *   - complex data is interleaved (re, im); "c128" = two doubles, "c64" = two
+ *     floats; matrices are row-major.
+ *   - qubit 0 is the most significant bit of a row/column index; a gate on
+ *     loc = (a, b) has local index 2*bit(a) + bit(b).
+ *   - gates are listed in time order; C = G_p ... G_1.
+ *   - the builder of one problem is an N x N matrix; a batch of S builders is
+ *     S contiguous N x N matrices (start-major).  Its element type is c128
+ *     (QF_C128) or c64 (QF_C64).
+ *   - pointers documented as "device" must be device memory of the context's
+ *     device; "host" pointers are ordinary host memory.  The caller owns
+ *     every buffer; the library keeps no pointer after a call returns.
+ *   - all device work is enqueued on the context's stream.  qf_instantiate
+ *     returns when its outputs are final; the other calls are
+ *     stream-ordered and asynchronous (synchronise the stream before reading
+ *     their outputs on the host).
+ *   - every call returns a qf_status; invalid arguments are rejected with
+ *     QF_EINVAL before any device work is enqueued; no call throws across
+ *     the ABI.  qf_last_error() gives a message for the last failure on a
+ *     context.
+ */
+#ifndef QFACTOR_MI355X_H
+#define QFACTOR_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qf_ctx qf_ctx;
+
+typedef enum {
+  QF_OK = 0,
+  QF_EINVAL = -1,        /* invalid argument (checked on the host) */
+  QF_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+  QF_EHIP = -3,          /* HIP runtime error */
+  QF_EWORKSPACE = -4,    /* workspace missing or smaller than qf_workspace_size */
+  QF_ENUMERIC = -5,      /* every start produced non-finite values */
+  QF_ETIMEOUT = -6       /* a bounded device-side wait gave up */
+} qf_status;
+
+typedef enum {
+  QF_C128 = 0,  /* builder in complex128; everything in FP64 */
+  QF_C64 = 1    /* builder in complex64; environment sums, SVD/polar step,
+                   termination tests and the final cost in FP64 */
+} qf_precision;
+
+typedef enum {
+  QF_MODE_AUTO = 0,       /* resident for n <= 6, streaming otherwise */
+  QF_MODE_RESIDENT = 1,   /* one workgroup per start, builder in LDS (n <= 6) */
+  QF_MODE_STREAMING = 2   /* builders in HBM, one fused pass per gate update */
+} qf_mode;
+
+typedef enum { QF_LEFT = 0, QF_RIGHT = 1 } qf_side;
+
+typedef enum {
+  QF_CONVERGED = 0,  /* best start's final cost < tol */
+  QF_PLATEAU = 1,    /* every start met a plateau test */
+  QF_MAX_ITER = 2,   /* max_iter sweeps done */
+  QF_NUMERIC = 3     /* every start produced non-finite values */
+} qf_result_status;
+
+/* Hyperparameters of Sec. III-A-2.  qf_options_default() sets the values the
+ * paper recommends: dist_tol 1e-10, diff_tol_a 0, diff_tol_r 1e-5,
+ * long_diff_count 100, long_diff_r 0.1, min_iter 0, max_iter 1e5,
+ * reset_iter 40, beta 0; plus precision QF_C128, mode QF_MODE_AUTO and
+ * recheck_below 1e-6.
+ * Readings of the garbled tests (c_i = cost after sweep i, c_0 = initial):
+ *   short plateau: c_{i-1} - c_i <= diff_tol_a + diff_tol_r * c_i
+ *                  (off when both are 0);
+ *   long plateau:  c_{i-L} - c_i < long_diff_r * c_{i-L}, L = long_diff_count
+ *                  (off when L <= 0);
+ *   stop when any start has cost < tol, or every start has met a plateau
+ *   test at some sweep, or after max_iter sweeps; no test before min_iter.
+ * reset_iter: rebuild the builder from the gates after every reset_iter-th
+ * sweep (0 = never).  beta: the SVD acts on (1-beta) E + beta u_old^dagger.
+ * recheck_below (QF_C64 only): once a start's complex64 cost estimate drops
+ * below this value, its cost is re-evaluated in FP64 from a freshly built
+ * complex128 builder, and the FP64 value is the one the tests see. */
+typedef struct {
+  double dist_tol;
+  double diff_tol_a;
+  double diff_tol_r;
+  int32_t long_diff_count;
+  double long_diff_r;
+  int32_t min_iter;
+  int32_t max_iter;
+  int32_t reset_iter;
+  double beta;
+  int32_t precision;  /* qf_precision */
+  int32_t mode;       /* qf_mode */
+  double recheck_below;
+} qf_options;
+
+/* Outcome of qf_instantiate (host memory). */
+typedef struct {
+  int32_t sweeps;        /* sweeps run (lockstep over starts) */
+  int32_t best_start;    /* start with the smallest final cost, lowest index on ties */
+  int32_t status;        /* qf_result_status */
+  int32_t n_resets;      /* builder rebuilds triggered by reset_iter */
+  int32_t n_rechecks;    /* FP64 re-evaluations (QF_C64) */
+  int32_t mode_used;     /* qf_mode actually run */
+  double best_cost;      /* FP64 cost of the best start's returned gates */
+  double elapsed_ms;     /* wall time from first launch to final outputs */
+  double* cost_history;  /* in, optional (host): rows x n_starts doubles;
+                            row i receives the costs after sweep i (row 0 =
+                            initial gates) for i < cost_history_rows */
+  int32_t cost_history_rows;
+} qf_stats;
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream).  Allocates a few KiB of pinned host
+ * memory for per-sweep cost read-back; no device memory. */
+int qf_create(qf_ctx** ctx, int device, void* hip_stream);
+int qf_destroy(qf_ctx* ctx);
+int qf_set_stream(qf_ctx* ctx, void* hip_stream);
+const char* qf_strerror(int status);
+const char* qf_last_error(const qf_ctx* ctx);
+void qf_options_default(qf_options* opt);
+
+/* Bytes of device workspace qf_instantiate needs for this problem size
+ * (0 on invalid sizes).  opt may be NULL (defaults). */
+size_t qf_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt);
+
+/* InitCircuitTensor (Alg. 1): builder[s] = G_p ... G_1 V^dagger for every
+ * start s, i.e. the target's conjugate transpose followed by every gate
+ * applied on the output legs.  target: device N x N c128.  gates: device
+ * n_starts x n_gates x 4 x 4 c128.  locations: host n_gates x 2 int32, two
+ * distinct qubits in [0, n).  builder: device n_starts x N x N in
+ * `precision`.  2 <= n <= 16. */
+int qf_build(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+             const void* gates, int n_starts, int precision, void* builder);
+
+/* ApplyRight / ApplyLeft of Alg. 1 on a batch of builders: with G = g on loc
+ * (identity elsewhere), side QF_LEFT does X <- G X (output legs, "ApplyRight")
+ * and QF_RIGHT does X <- X G (input legs, "ApplyLeft"); dagger != 0 applies
+ * G^dagger (the inverse, which removes the gate).  gates: device
+ * n_builders x 4 x 4 c128, one gate per builder (rounded to the builder's
+ * precision).  loc: host int32[2]. */
+int qf_apply_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precision,
+                  const int32_t* loc, const void* gates, int side, int dagger);
+
+/* CalcEnvMat of Alg. 1 (Sec. III, Fig. tensors): env[s][i][j] =
+ * sum over the other qubits of X_s[(i, rest), (j, rest)], so that
+ * Tr((u (x) I) X_s) = Tr(env_s u) for every 4x4 u.  Summed in FP64.
+ * env_out: device n_builders x 4 x 4 c128. */
+int qf_environment(qf_ctx* ctx, int n, int n_builders, const void* builder, int precision,
+                   const int32_t* loc, void* env_out);
+
+/* OptimizeGate for general unitaries (Sec. III-A-1, Eq. opt_u, with beta of
+ * Sec. III-A-2): for each of `count` environments E, M = (1-beta) E +
+ * beta u_old^dagger, SVD M = X D Y^dagger, u_new = Y X^dagger (FP64).  A zero
+ * M keeps u_old; a non-finite M gives NaN.  env, u_old, u_new: device
+ * count x 4 x 4 c128 (u_new may alias u_old). */
+int qf_optimize_gate(qf_ctx* ctx, int count, const void* env, const void* u_old, double beta,
+                     void* u_new);
+
+/* One gate update of TwoSidedSweep (Alg. 1), in place, for every builder:
+ * half 0 (first half-sweep): remove G^dagger on the output legs, E = Tr_rest,
+ * optimise, apply the new gate on the input legs; half 1: remove on the input
+ * legs, optimise, apply on the output legs.  The remove and re-apply are one
+ * fused pass over the builder.  gates: device n_builders x 4 x 4 c128, in =
+ * current gate, out = updated gate.  env_out: optional device
+ * n_builders x 4 x 4 c128 receiving E. */
+int qf_update_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precision,
+                   const int32_t* loc, int half, double beta, void* gates, void* env_out);
+
+/* Cost of each builder from its trace, FP64: trace_out[s] = Tr(X_s) (device
+ * c128, optional), cost_out[s] = 1 - |Tr X_s| / N (device double). */
+int qf_cost(qf_ctx* ctx, int n, int n_builders, const void* builder, int precision,
+            double* cost_out, void* trace_out);
+
+/* QFactor (Alg. 1 with the multistart rule of Sec. IV-A): instantiate
+ * n_gates two-qubit gates on `locations` to `target`, from n_starts initial
+ * gate sets run in lockstep; stop when any start's cost < tol, when every
+ * start has plateaued, or after max_iter sweeps.
+ *   target:       device N x N c128 (the unitary V)
+ *   locations:    host n_gates x 2 int32
+ *   init_gates:   device n_starts x n_gates x 4 x 4 c128
+ *   tol:          > 0; replaces opt->dist_tol
+ *   opt:          host, NULL = qf_options_default
+ *   workspace:    device, >= qf_workspace_size(n, n_gates, n_starts, opt) bytes
+ *   out_gates:    device n_gates x 4 x 4 c128: the best start's gates
+ *   out_all_gates:optional device n_starts x n_gates x 4 x 4 c128
+ *   out_costs:    host n_starts doubles: FP64 cost of each start's returned
+ *                 gates, from a fresh complex128 builder
+ *   stats:        optional host qf_stats
+ * Non-convergence is not an error: the call returns QF_OK with status
+ * QF_PLATEAU / QF_MAX_ITER.  A start whose values become non-finite is
+ * frozen; QF_ENUMERIC is returned only when every start is frozen. */
+int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                   const void* init_gates, int n_starts, double tol, const qf_options* opt,
+                   void* workspace, size_t ws_bytes, void* out_gates, void* out_all_gates,
+                   double* out_costs, qf_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFACTOR_MI355X_H */

@@ -1,0 +1,21 @@
+"""MI355X-native QFactor instantiation sweep (arXiv 2306.08152).
+
+The computation lives in the HIP library libqfactor_mi355x.so behind the C ABI
+of include/qfactor.h; this package only marshals torch tensors to it.  There is
+no CPU fallback: the calls raise if the library is not built or no GPU is
+present.
+"""
+from ._native import (  # noqa: F401
+    QF_C128, QF_C64, QF_MODE_AUTO, QF_MODE_RESIDENT, QF_MODE_STREAMING, QF_LEFT, QF_RIGHT,
+    QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC, QfError, QfOptions, QfStats, load,
+)
+from .build import build as build_library, lib_path  # noqa: F401
+
+
+def __getattr__(name):
+    # torch-facing wrappers are imported on first use so that `import
+    # paper_2306_08152_amd` stays cheap on machines without a GPU.
+    from . import api
+    if hasattr(api, name):
+        return getattr(api, name)
+    raise AttributeError(name)

@@ -1,0 +1,211 @@
+"""Torch-facing wrappers over the C ABI.  Tensors supply device memory and the
+stream; every computation runs in the HIP library.
+
+Builders are (S, N, N) complex128 or complex64 CUDA tensors; gates are
+(..., 4, 4) complex128; locations are (p, 2) integer arrays (host)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+_CTX: dict[int, ctypes.c_void_p] = {}
+
+
+def _dev_index(device) -> int:
+    if device is None:
+        return torch.cuda.current_device()
+    if isinstance(device, int):
+        return device
+    d = torch.device(device)
+    return d.index if d.index is not None else torch.cuda.current_device()
+
+
+def _ctx(device: torch.device | int | None = None) -> ctypes.c_void_p:
+    """Library context for the device, bound to torch's current stream."""
+    lib = nat.load()
+    dev = _dev_index(device)
+    ctx = _CTX.get(dev)
+    if ctx is None:
+        ctx = ctypes.c_void_p()
+        nat.check(lib.qf_create(ctypes.byref(ctx), dev, None))
+        _CTX[dev] = ctx
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    nat.check(lib.qf_set_stream(ctx, ctypes.c_void_p(stream)), ctx)
+    return ctx
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _loc(loc) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(loc, dtype=np.int32).reshape(-1))
+    return (ctypes.c_int32 * a.size)(*a.tolist())
+
+
+def _prec(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return nat.QF_C128
+    if t.dtype == torch.complex64:
+        return nat.QF_C64
+    raise TypeError(f"builder dtype must be complex128 or complex64, got {t.dtype}")
+
+
+def _n_of(N: int) -> int:
+    n = N.bit_length() - 1
+    if 1 << n != N:
+        raise ValueError(f"matrix size {N} is not a power of two")
+    return n
+
+
+def _check_builder(b: torch.Tensor) -> tuple[int, int]:
+    if not b.is_cuda or not b.is_contiguous() or b.dim() != 3 or b.shape[1] != b.shape[2]:
+        raise ValueError("builder must be a contiguous CUDA tensor of shape (S, N, N)")
+    return b.shape[0], _n_of(b.shape[1])
+
+
+def _c128(t: torch.Tensor, shape) -> torch.Tensor:
+    if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected a contiguous CUDA complex128 tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    return t
+
+
+def default_options(**kw) -> nat.QfOptions:
+    o = nat.QfOptions()
+    nat.load().qf_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def build(target: torch.Tensor, locs, gates: torch.Tensor, dtype=torch.complex128) -> torch.Tensor:
+    """InitCircuitTensor: (S, N, N) builders G_p ... G_1 V^dagger."""
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 2)
+    S, p = gates.shape[0], gates.shape[1]
+    _c128(target, (N, N))
+    _c128(gates, (S, p, 4, 4))
+    X = torch.empty((S, N, N), dtype=dtype, device=target.device)
+    ctx = _ctx(target.device)
+    nat.check(nat.load().qf_build(ctx, n, _ptr(target), p, _loc(locs), _ptr(gates), S, _prec(X), _ptr(X)), ctx)
+    return X
+
+
+def apply_gate(builder: torch.Tensor, loc, gates: torch.Tensor, side: int, dagger: bool = False) -> torch.Tensor:
+    """In place: X <- G X (side=QF_LEFT) or X G (QF_RIGHT), G^dagger if dagger."""
+    S, n = _check_builder(builder)
+    _c128(gates, (S, 4, 4))
+    ctx = _ctx(builder.device)
+    nat.check(nat.load().qf_apply_gate(ctx, n, S, _ptr(builder), _prec(builder), _loc(loc), _ptr(gates),
+                                       int(side), int(bool(dagger))), ctx)
+    return builder
+
+
+def environment(builder: torch.Tensor, loc) -> torch.Tensor:
+    """(S, 4, 4) complex128: partial trace of each builder over all qubits but loc."""
+    S, n = _check_builder(builder)
+    env = torch.empty((S, 4, 4), dtype=torch.complex128, device=builder.device)
+    ctx = _ctx(builder.device)
+    nat.check(nat.load().qf_environment(ctx, n, S, _ptr(builder), _prec(builder), _loc(loc), _ptr(env)), ctx)
+    return env
+
+
+def optimize_gate(env: torch.Tensor, u_old: torch.Tensor, beta: float = 0.0) -> torch.Tensor:
+    count = env.shape[0]
+    _c128(env, (count, 4, 4))
+    _c128(u_old, (count, 4, 4))
+    out = torch.empty_like(u_old)
+    ctx = _ctx(env.device)
+    nat.check(nat.load().qf_optimize_gate(ctx, count, _ptr(env), _ptr(u_old), float(beta), _ptr(out)), ctx)
+    return out
+
+
+def update_gate(builder: torch.Tensor, loc, half: int, gates: torch.Tensor, beta: float = 0.0,
+                want_env: bool = False):
+    """One TwoSidedSweep update in place; returns (gates, env or None)."""
+    S, n = _check_builder(builder)
+    _c128(gates, (S, 4, 4))
+    env = torch.empty((S, 4, 4), dtype=torch.complex128, device=builder.device) if want_env else None
+    ctx = _ctx(builder.device)
+    nat.check(nat.load().qf_update_gate(ctx, n, S, _ptr(builder), _prec(builder), _loc(loc), int(half),
+                                        float(beta), _ptr(gates), _ptr(env)), ctx)
+    return gates, env
+
+
+def cost(builder: torch.Tensor):
+    """(costs (S,) float64, traces (S,) complex128) from the builders' traces."""
+    S, n = _check_builder(builder)
+    c = torch.empty((S,), dtype=torch.float64, device=builder.device)
+    tr = torch.empty((S,), dtype=torch.complex128, device=builder.device)
+    ctx = _ctx(builder.device)
+    nat.check(nat.load().qf_cost(ctx, n, S, _ptr(builder), _prec(builder),
+                                 ctypes.cast(ctypes.c_void_p(c.data_ptr()), ctypes.POINTER(ctypes.c_double)),
+                                 _ptr(tr)), ctx)
+    return c, tr
+
+
+@dataclass
+class Result:
+    gates: torch.Tensor          # (p, 4, 4) best start
+    all_gates: torch.Tensor      # (S, p, 4, 4)
+    costs: np.ndarray            # (S,) FP64 costs of the returned gates
+    best_start: int
+    sweeps: int
+    status: int
+    n_resets: int
+    n_rechecks: int
+    mode_used: int
+    elapsed_ms: float
+    history: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+
+
+def workspace_size(n: int, p: int, S: int, opt: nat.QfOptions) -> int:
+    return int(nat.load().qf_workspace_size(n, p, S, ctypes.byref(opt)))
+
+
+def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float = 1e-10,
+                options: nat.QfOptions | None = None, history_rows: int = 0,
+                workspace: torch.Tensor | None = None, **kw) -> Result:
+    """QFactor multistart instantiation (qf_instantiate)."""
+    opt = options if options is not None else default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 2)
+    S, p = init_gates.shape[0], init_gates.shape[1]
+    _c128(target, (N, N))
+    _c128(init_gates, (S, p, 4, 4))
+    lib = nat.load()
+    need = int(lib.qf_workspace_size(n, p, S, ctypes.byref(opt)))
+    if need == 0:
+        raise ValueError("invalid problem size or options")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
+    out = torch.empty((p, 4, 4), dtype=torch.complex128, device=target.device)
+    out_all = torch.empty((S, p, 4, 4), dtype=torch.complex128, device=target.device)
+    costs = (ctypes.c_double * S)()
+    st = nat.QfStats()
+    hist = None
+    if history_rows > 0:
+        hist = np.full((history_rows, S), np.nan, dtype=np.float64)
+        st.cost_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st.cost_history_rows = history_rows
+    ctx = _ctx(target.device)
+    rc = lib.qf_instantiate(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
+                            ctypes.byref(opt), _ptr(workspace), need, _ptr(out), _ptr(out_all), costs,
+                            ctypes.byref(st))
+    if rc not in (nat.QF_OK, nat.QF_ENUMERIC):
+        nat.check(rc, ctx)
+    h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
+    return Result(out, out_all, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.n_resets,
+                  st.n_rechecks, st.mode_used, st.elapsed_ms, h)

@@ -1,0 +1,716 @@
+// C-ABI entry points and the host runtime around the kernels: argument
+// validation, workspace layout, the streaming sweep loop (Alg. 1 with the
+// host-side termination test once per sweep), the complex64 FP64 recheck,
+// and dispatch to the LDS-resident kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qf_internal.h"
+#include "qf_termination.h"
+#include "qfactor.h"
+
+struct qf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double* pinned = nullptr;     // host read-back buffer
+  size_t pinned_count = 0;      // doubles
+  void* scratch = nullptr;      // device scratch for the stand-alone calls
+  size_t scratch_bytes = 0;
+  std::string last_error;
+};
+
+namespace {
+
+using namespace qf;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(qf_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return code;
+}
+
+#define QF_HIP(ctx, expr)                                                                     \
+  do {                                                                                        \
+    hipError_t e__ = (expr);                                                                  \
+    if (e__ != hipSuccess) return fail((ctx), QF_EHIP, "%s: %s", #expr, hipGetErrorString(e__)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t elem_bytes(int precision) { return precision == QF_C64 ? 8 : 16; }
+
+bool valid_loc(int n, const int32_t* loc) {
+  return loc && loc[0] >= 0 && loc[0] < n && loc[1] >= 0 && loc[1] < n && loc[0] != loc[1];
+}
+
+int resolve_mode(int n, const qf_options& o) {
+  if (o.mode == QF_MODE_RESIDENT) return QF_MODE_RESIDENT;
+  if (o.mode == QF_MODE_STREAMING) return QF_MODE_STREAMING;
+  return n <= 6 ? QF_MODE_RESIDENT : QF_MODE_STREAMING;
+}
+
+// Workspace layout of qf_instantiate.
+struct Layout {
+  size_t X = 0, R = 0, gates = 0, uold = 0, partials = 0, counters = 0, costs = 0, trace = 0,
+         frozen = 0, locs = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0;
+  size_t total = 0;
+  int ring = 2;
+};
+
+Layout make_layout(int n, int p, int S, const qf_options& o, int mode, int history_rows) {
+  Layout L;
+  const size_t N = (size_t)1 << n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  if (mode == QF_MODE_STREAMING) {
+    L.X = take((size_t)S * N * N * elem_bytes(o.precision));
+    if (o.precision == QF_C64) L.R = take((size_t)S * N * N * 16);
+    L.partials = take((size_t)S * env_workgroups(n) * 16 * 16);
+    L.counters = take((size_t)S * 4);
+    L.uold = take((size_t)S * 16 * 16);
+    L.trace = take((size_t)S * 16);
+    L.frozen = take((size_t)S * 4);
+  }
+  L.gates = take((size_t)S * p * 16 * 16);
+  L.costs = take((size_t)S * 8);
+  L.locs = take((size_t)p * 2 * 4);
+  L.ring = std::max(2, o.long_diff_count + 1);
+  if (mode == QF_MODE_RESIDENT) {
+    L.hist = take((size_t)S * L.ring * 8);
+    L.flags = take((size_t)2 * S * 4);
+    L.cur = take((size_t)S * 8);
+    L.fin = take((size_t)S * 8);
+    L.sync = take(64);
+    L.info = take(64);
+    if (history_rows > 0) L.histo = take((size_t)history_rows * S * 8);
+  }
+  L.total = off;
+  return L;
+}
+
+// The resident kernel records the per-sweep costs of at most this many rows
+// (initial cost + sweeps) in the workspace.
+constexpr int kResidentHistoryCap = 4097;
+int resident_history_rows(int mode, const qf_options& o) {
+  return mode == QF_MODE_RESIDENT ? std::min(o.max_iter + 1, kResidentHistoryCap) : 0;
+}
+
+int validate_options(qf_ctx* ctx, const qf_options& o) {
+  if (!(o.dist_tol > 0) || !std::isfinite(o.dist_tol)) return fail(ctx, QF_EINVAL, "dist_tol must be > 0");
+  if (!(o.diff_tol_a >= 0) || !(o.diff_tol_r >= 0)) return fail(ctx, QF_EINVAL, "diff_tol_a/r must be >= 0");
+  if (!(o.long_diff_r >= 0)) return fail(ctx, QF_EINVAL, "long_diff_r must be >= 0");
+  if (o.long_diff_count > (1 << 20)) return fail(ctx, QF_EINVAL, "long_diff_count too large");
+  if (o.min_iter < 0 || o.max_iter < 0 || o.reset_iter < 0) return fail(ctx, QF_EINVAL, "iteration counts must be >= 0");
+  if (!(o.beta >= 0.0 && o.beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
+  if (o.precision != QF_C128 && o.precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision %d", o.precision);
+  if (o.mode < QF_MODE_AUTO || o.mode > QF_MODE_STREAMING) return fail(ctx, QF_EINVAL, "unknown mode %d", o.mode);
+  if (!(o.recheck_below >= 0) || !std::isfinite(o.recheck_below)) return fail(ctx, QF_EINVAL, "recheck_below must be >= 0");
+  return QF_OK;
+}
+
+int validate_problem(qf_ctx* ctx, int n, int p, const int32_t* locs, int S) {
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (p < 1) return fail(ctx, QF_EINVAL, "n_gates must be >= 1");
+  if (!locs) return fail(ctx, QF_EINVAL, "locations is NULL");
+  for (int g = 0; g < p; ++g)
+    if (!valid_loc(n, locs + 2 * g))
+      return fail(ctx, QF_EINVAL, "gate %d: location (%d, %d) invalid for n=%d", g, locs[2 * g], locs[2 * g + 1], n);
+  if (S < 1) return fail(ctx, QF_EINVAL, "n_starts must be >= 1");
+  return QF_OK;
+}
+
+int ensure_pinned(qf_ctx* ctx, size_t count) {
+  if (ctx->pinned_count >= count) return QF_OK;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_count = 0;
+  QF_HIP(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), count * sizeof(double), hipHostMallocDefault));
+  ctx->pinned_count = count;
+  return QF_OK;
+}
+
+int ensure_scratch(qf_ctx* ctx, size_t bytes) {
+  if (ctx->scratch_bytes >= bytes) return QF_OK;
+  QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  QF_HIP(ctx, hipMalloc(&ctx->scratch, bytes));
+  QF_HIP(ctx, hipMemsetAsync(ctx->scratch, 0, bytes, ctx->stream));
+  ctx->scratch_bytes = bytes;
+  return QF_OK;
+}
+
+// Build X_s = G_p ... G_1 V^dagger on the device (all starts).
+int build_builder(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, const double* gates,
+                  int64_t gstride, int S, int precision, void* X) {
+  QF_HIP(ctx, launch_build_init(ctx->stream, precision, V, X, n, S));
+  for (int g = 0; g < p; ++g) {
+    const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_max_tcols(precision));
+    Operand A{gates + 2 * 16 * (int64_t)g, gstride, 0};
+    Operand B{nullptr, 0, 0};
+    QF_HIP(ctx, launch_pass(ctx->stream, precision, X, S, geo, A, B));
+  }
+  return QF_OK;
+}
+
+__global__ void k_cast_c128_c64(const double2* __restrict__ src, float2* __restrict__ dst, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+int cast_to_c64(qf_ctx* ctx, const void* R, void* X, size_t count) {
+  const unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_cast_c128_c64, dim3(blocks), dim3(256), 0, ctx->stream,
+                     reinterpret_cast<const double2*>(R), reinterpret_cast<float2*>(X), count);
+  QF_HIP(ctx, hipGetLastError());
+  return QF_OK;
+}
+
+int read_costs(qf_ctx* ctx, const double* dev, int S, std::vector<double>& out) {
+  int rc = ensure_pinned(ctx, (size_t)S);
+  if (rc) return rc;
+  QF_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, (size_t)S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  out.assign(ctx->pinned, ctx->pinned + S);
+  return QF_OK;
+}
+
+struct RunOut {
+  int32_t sweeps = 0, decision = kContinue, resets = 0, rechecks = 0;
+  std::vector<double> final_costs;
+  std::vector<int32_t> flags;
+};
+
+// ----------------------------------------------------------------- streaming
+
+int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, int S, double tol,
+                  const qf_options& o, unsigned char* ws, const Layout& L, qf_stats* stats, RunOut& out) {
+  hipStream_t st = ctx->stream;
+  const int prec = o.precision;
+  void* X = ws + L.X;
+  void* R = prec == QF_C64 ? (void*)(ws + L.R) : nullptr;
+  double* gates = reinterpret_cast<double*>(ws + L.gates);
+  double* uold = reinterpret_cast<double*>(ws + L.uold);
+  double* costs = reinterpret_cast<double*>(ws + L.costs);
+  double* trace = reinterpret_cast<double*>(ws + L.trace);
+  int32_t* frozen = reinterpret_cast<int32_t*>(ws + L.frozen);
+  const int64_t gstride = (int64_t)p * 16;
+  const size_t N = (size_t)1 << n;
+
+  QF_HIP(ctx, hipMemsetAsync(ws + L.counters, 0, (size_t)S * 4, st));
+  QF_HIP(ctx, hipMemsetAsync(frozen, 0, (size_t)S * 4, st));
+
+  std::vector<PassGeom> geo(p);
+  for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_max_tcols(prec));
+
+  EnvArgs ea{};
+  ea.n = n;
+  ea.S = S;
+  ea.do_update = 1;
+  ea.beta = o.beta;
+  ea.gates = gates;
+  ea.gstride = gstride;
+  ea.uold = uold;
+  ea.env_out = nullptr;
+  ea.frozen = frozen;
+  ea.partials = reinterpret_cast<double*>(ws + L.partials);
+  ea.counters = reinterpret_cast<int32_t*>(ws + L.counters);
+
+  auto update = [&](int g, int half) -> int {
+    ea.q0 = locs[2 * g];
+    ea.q1 = locs[2 * g + 1];
+    ea.half = half;
+    ea.gidx = g;
+    QF_HIP(ctx, launch_env(st, prec, X, ea));
+    Operand gnew{gates + 2 * 16 * (int64_t)g, gstride, 0};
+    Operand gold{uold, 16, 1};
+    if (half == 0)
+      QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gold, gnew));
+    else
+      QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gnew, gold));
+    return QF_OK;
+  };
+  // FP64 costs of the current gates from a fresh complex128 builder (into
+  // R for complex64, into X itself for complex128).
+  auto fp64_costs = [&](std::vector<double>& c) -> int {
+    void* dst = prec == QF_C64 ? R : X;
+    int rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, QF_C128, dst);
+    if (rc) return rc;
+    QF_HIP(ctx, launch_cost(st, QF_C128, dst, n, S, costs, trace));
+    return read_costs(ctx, costs, S, c);
+  };
+
+  int rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, prec, X);
+  if (rc) return rc;
+  QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
+  std::vector<double> c;
+  rc = read_costs(ctx, costs, S, c);
+  if (rc) return rc;
+
+  bool any_recheck = false;
+  if (prec == QF_C64)
+    for (int s = 0; s < S; ++s) any_recheck = any_recheck || (c[s] < o.recheck_below);
+  if (any_recheck) {
+    std::vector<double> c64v = c;
+    rc = fp64_costs(c);
+    if (rc) return rc;
+    ++out.rechecks;
+    for (int s = 0; s < S; ++s)
+      if (!(c64v[s] < o.recheck_below)) c[s] = c64v[s];
+  }
+
+  std::vector<std::vector<double>> hist;
+  out.flags.assign(S, 0);
+  for (int s = 0; s < S; ++s) {
+    if (!std::isfinite(c[s])) {
+      c[s] = INFINITY;
+      out.flags[s] = kFlagNumeric | kFlagPlateau;
+    }
+  }
+  hist.push_back(c);
+  auto record = [&](int i, const std::vector<double>& cv) {
+    if (stats && stats->cost_history && i < stats->cost_history_rows)
+      for (int s = 0; s < S; ++s) stats->cost_history[(size_t)i * S + s] = cv[s];
+  };
+  record(0, c);
+  std::vector<int32_t> frozen_host(S, 0);
+  auto sync_frozen = [&]() -> int {
+    bool changed = false;
+    for (int s = 0; s < S; ++s) {
+      const int32_t fz = (out.flags[s] & kFlagNumeric) ? 1 : 0;
+      changed = changed || (fz != frozen_host[s]);
+      frozen_host[s] = fz;
+    }
+    if (changed)
+      QF_HIP(ctx, hipMemcpyAsync(frozen, frozen_host.data(), (size_t)S * 4, hipMemcpyHostToDevice, st));
+    return QF_OK;
+  };
+  rc = sync_frozen();
+  if (rc) return rc;
+
+  int32_t i = 0;
+  int32_t decision = o.max_iter <= 0 ? kStopMaxIter : kContinue;
+  while (decision == kContinue) {
+    ++i;
+    for (int g = p - 1; g >= 0; --g)
+      if ((rc = update(g, 0))) return rc;
+    for (int g = 0; g < p; ++g)
+      if ((rc = update(g, 1))) return rc;
+    if (o.reset_iter > 0 && i % o.reset_iter == 0) {
+      if ((rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, prec, X))) return rc;
+      ++out.resets;
+    }
+    QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
+    if ((rc = read_costs(ctx, costs, S, c))) return rc;
+    if (prec == QF_C64) {
+      bool need = false;
+      for (int s = 0; s < S; ++s) need = need || (!(out.flags[s] & kFlagNumeric) && c[s] < o.recheck_below);
+      if (need) {
+        std::vector<double> c64v = c, c64d;
+        if ((rc = fp64_costs(c64d))) return rc;
+        ++out.rechecks;
+        for (int s = 0; s < S; ++s)
+          if (c64v[s] < o.recheck_below) c[s] = c64d[s];
+        if ((rc = cast_to_c64(ctx, R, X, (size_t)S * N * N))) return rc;  // refresh the builder
+      }
+    }
+    const int32_t Lh = o.long_diff_count;
+    for (int s = 0; s < S; ++s) {
+      double ci = std::isfinite(c[s]) ? c[s] : INFINITY;
+      if (out.flags[s] & kFlagNumeric) {
+        c[s] = INFINITY;
+        continue;
+      }
+      const double cprev = hist[i - 1][s];
+      const double cback = (Lh > 0 && i >= Lh) ? hist[i - Lh][s] : 0.0;
+      out.flags[s] = start_flags_after_sweep(o, tol, i, out.flags[s], ci, cprev, cback);
+      c[s] = (out.flags[s] & kFlagNumeric) ? INFINITY : ci;
+    }
+    hist.push_back(c);
+    record(i, c);
+    if ((rc = sync_frozen())) return rc;
+    decision = job_decision(o, i, out.flags.data(), S);
+  }
+  out.sweeps = i;
+  out.decision = decision;
+  rc = fp64_costs(out.final_costs);
+  if (rc) return rc;
+  return QF_OK;
+}
+
+// ----------------------------------------------------------------- resident
+
+int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, const qf_options& o,
+                 unsigned char* ws, const Layout& L, qf_stats* stats, int history_rows, RunOut& out) {
+  hipStream_t st = ctx->stream;
+  ResidentArgs a{};
+  a.n = n;
+  a.p = p;
+  a.S = S;
+  a.precision = o.precision;
+  a.V = reinterpret_cast<const double*>(V);
+  a.locs = reinterpret_cast<const int32_t*>(ws + L.locs);
+  a.gates = reinterpret_cast<double*>(ws + L.gates);
+  a.tol = tol;
+  a.opt = o;
+  a.hist = reinterpret_cast<double*>(ws + L.hist);
+  a.ring = L.ring;
+  a.flags = reinterpret_cast<int32_t*>(ws + L.flags);
+  a.cur_cost = reinterpret_cast<double*>(ws + L.cur);
+  a.final_cost = reinterpret_cast<double*>(ws + L.fin);
+  a.sync = reinterpret_cast<int32_t*>(ws + L.sync);
+  a.out_info = reinterpret_cast<int32_t*>(ws + L.info);
+  a.history_out = history_rows > 0 ? reinterpret_cast<double*>(ws + L.histo) : nullptr;
+  a.history_rows = history_rows;
+  QF_HIP(ctx, hipMemsetAsync(ws + L.sync, 0, 64, st));
+  QF_HIP(ctx, hipMemsetAsync(ws + L.info, 0, 64, st));
+  int ok = 0;
+  QF_HIP(ctx, launch_resident(st, a, &ok));
+  if (!ok) return fail(ctx, QF_EUNSUPPORTED, "resident mode: %d starts do not fit on the device at once", S);
+  int32_t info[8];
+  QF_HIP(ctx, hipMemcpyAsync(info, ws + L.info, sizeof info, hipMemcpyDeviceToHost, st));
+  std::vector<double> fin(S);
+  std::vector<int32_t> fl(2 * (size_t)S);
+  QF_HIP(ctx, hipMemcpyAsync(fin.data(), ws + L.fin, (size_t)S * 8, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipMemcpyAsync(fl.data(), ws + L.flags, (size_t)2 * S * 4, hipMemcpyDeviceToHost, st));
+  std::vector<double> ho;
+  if (history_rows > 0) {
+    ho.resize((size_t)history_rows * S);
+    QF_HIP(ctx, hipMemcpyAsync(ho.data(), ws + L.histo, ho.size() * 8, hipMemcpyDeviceToHost, st));
+  }
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  if (info[4]) return fail(ctx, QF_ETIMEOUT, "resident mode: device barrier wait gave up");
+  out.sweeps = info[0];
+  out.decision = info[1];
+  out.resets = info[2];
+  out.rechecks = info[3];
+  out.final_costs = fin;
+  out.flags.assign(fl.begin() + (size_t)(out.sweeps & 1) * S, fl.begin() + (size_t)(out.sweeps & 1) * S + S);
+  if (out.sweeps == 0) out.flags.assign(S, 0);
+  if (stats && stats->cost_history && history_rows > 0) {
+    const int rows = std::min(std::min(history_rows, out.sweeps + 1), stats->cost_history_rows);
+    if (rows > 0) std::memcpy(stats->cost_history, ho.data(), (size_t)rows * S * 8);
+  }
+  return QF_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char* qf_strerror(int status) {
+  switch (status) {
+    case QF_OK: return "ok";
+    case QF_EINVAL: return "invalid argument";
+    case QF_EUNSUPPORTED: return "unsupported request";
+    case QF_EHIP: return "HIP runtime error";
+    case QF_EWORKSPACE: return "workspace missing or too small";
+    case QF_ENUMERIC: return "every start produced non-finite values";
+    case QF_ETIMEOUT: return "device-side wait timed out";
+    default: return "unknown status";
+  }
+}
+
+const char* qf_last_error(const qf_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+void qf_options_default(qf_options* o) {
+  if (!o) return;
+  o->dist_tol = 1e-10;
+  o->diff_tol_a = 0.0;
+  o->diff_tol_r = 1e-5;
+  o->long_diff_count = 100;
+  o->long_diff_r = 0.1;
+  o->min_iter = 0;
+  o->max_iter = 100000;
+  o->reset_iter = 40;
+  o->beta = 0.0;
+  o->precision = QF_C128;
+  o->mode = QF_MODE_AUTO;
+  o->recheck_below = 1e-6;
+}
+
+int qf_create(qf_ctx** out, int device, void* hip_stream) {
+  if (!out) return QF_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return QF_EINVAL;
+  qf_ctx* ctx = new (std::nothrow) qf_ctx();
+  if (!ctx) return QF_EHIP;
+  ctx->device = device;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  DeviceGuard dg(device);
+  if (ensure_pinned(ctx, 4096) != QF_OK) {
+    delete ctx;
+    return QF_EHIP;
+  }
+  *out = ctx;
+  return QF_OK;
+}
+
+int qf_destroy(qf_ctx* ctx) {
+  if (!ctx) return QF_EINVAL;
+  {
+    DeviceGuard dg(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+  }
+  delete ctx;
+  return QF_OK;
+}
+
+int qf_set_stream(qf_ctx* ctx, void* hip_stream) {
+  if (!ctx) return QF_EINVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return QF_OK;
+}
+
+size_t qf_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt) {
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (n < 2 || n > 16 || n_gates < 1 || n_starts < 1) return 0;
+  if (validate_options(nullptr, o) != QF_OK) return 0;
+  const int mode = resolve_mode(n, o);
+  return make_layout(n, n_gates, n_starts, o, mode, resident_history_rows(mode, o)).total;
+}
+
+int qf_build(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+             const void* gates, int n_starts, int precision, void* builder) {
+  if (!ctx) return QF_EINVAL;
+  int rc = validate_problem(ctx, n, n_gates, locations, n_starts);
+  if (rc) return rc;
+  if (!target || !gates || !builder) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  DeviceGuard dg(ctx->device);
+  return build_builder(ctx, n, target, n_gates, locations, reinterpret_cast<const double*>(gates),
+                       (int64_t)n_gates * 16, n_starts, precision, builder);
+}
+
+int qf_apply_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precision, const int32_t* loc,
+                  const void* gates, int side, int dagger) {
+  if (!ctx) return QF_EINVAL;
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (n_builders < 1) return fail(ctx, QF_EINVAL, "n_builders must be >= 1");
+  if (!valid_loc(n, loc)) return fail(ctx, QF_EINVAL, "invalid gate location");
+  if (!builder || !gates) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (side != QF_LEFT && side != QF_RIGHT) return fail(ctx, QF_EINVAL, "side must be QF_LEFT or QF_RIGHT");
+  DeviceGuard dg(ctx->device);
+  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_max_tcols(precision));
+  Operand G{reinterpret_cast<const double*>(gates), 16, dagger ? 1 : 0};
+  Operand none{nullptr, 0, 0};
+  QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, side == QF_LEFT ? G : none,
+                          side == QF_LEFT ? none : G));
+  return QF_OK;
+}
+
+int qf_environment(qf_ctx* ctx, int n, int n_builders, const void* builder, int precision,
+                   const int32_t* loc, void* env_out) {
+  if (!ctx) return QF_EINVAL;
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (n_builders < 1) return fail(ctx, QF_EINVAL, "n_builders must be >= 1");
+  if (!valid_loc(n, loc)) return fail(ctx, QF_EINVAL, "invalid gate location");
+  if (!builder || !env_out) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  DeviceGuard dg(ctx->device);
+  const size_t part = align_up((size_t)n_builders * env_workgroups(n) * 256);
+  int rc = ensure_scratch(ctx, part + align_up((size_t)n_builders * 4));
+  if (rc) return rc;
+  EnvArgs ea{};
+  ea.n = n;
+  ea.q0 = loc[0];
+  ea.q1 = loc[1];
+  ea.S = n_builders;
+  ea.do_update = 0;
+  ea.env_out = reinterpret_cast<double*>(env_out);
+  ea.partials = reinterpret_cast<double*>(ctx->scratch);
+  ea.counters = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(ctx->scratch) + part);
+  QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
+  return QF_OK;
+}
+
+int qf_optimize_gate(qf_ctx* ctx, int count, const void* env, const void* u_old, double beta, void* u_new) {
+  if (!ctx) return QF_EINVAL;
+  if (count < 1) return fail(ctx, QF_EINVAL, "count must be >= 1");
+  if (!env || !u_old || !u_new) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
+  DeviceGuard dg(ctx->device);
+  QF_HIP(ctx, launch_optimize(ctx->stream, count, reinterpret_cast<const double*>(env),
+                              reinterpret_cast<const double*>(u_old), beta, reinterpret_cast<double*>(u_new)));
+  return QF_OK;
+}
+
+int qf_update_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precision, const int32_t* loc,
+                   int half, double beta, void* gates, void* env_out) {
+  if (!ctx) return QF_EINVAL;
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (n_builders < 1) return fail(ctx, QF_EINVAL, "n_builders must be >= 1");
+  if (!valid_loc(n, loc)) return fail(ctx, QF_EINVAL, "invalid gate location");
+  if (!builder || !gates) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (half != 0 && half != 1) return fail(ctx, QF_EINVAL, "half must be 0 or 1");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
+  DeviceGuard dg(ctx->device);
+  const size_t part = align_up((size_t)n_builders * env_workgroups(n) * 256);
+  const size_t cnt = align_up((size_t)n_builders * 4);
+  const size_t uo = align_up((size_t)n_builders * 256);
+  int rc = ensure_scratch(ctx, part + cnt + uo);
+  if (rc) return rc;
+  unsigned char* sc = reinterpret_cast<unsigned char*>(ctx->scratch);
+  EnvArgs ea{};
+  ea.n = n;
+  ea.q0 = loc[0];
+  ea.q1 = loc[1];
+  ea.S = n_builders;
+  ea.do_update = 1;
+  ea.half = half;
+  ea.beta = beta;
+  ea.gates = reinterpret_cast<double*>(gates);
+  ea.gstride = 16;
+  ea.gidx = 0;
+  ea.uold = reinterpret_cast<double*>(sc + part + cnt);
+  ea.env_out = reinterpret_cast<double*>(env_out);
+  ea.partials = reinterpret_cast<double*>(sc);
+  ea.counters = reinterpret_cast<int32_t*>(sc + part);
+  QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
+  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_max_tcols(precision));
+  Operand gnew{reinterpret_cast<const double*>(gates), 16, 0};
+  Operand gold{ea.uold, 16, 1};
+  if (half == 0)
+    QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, gold, gnew));
+  else
+    QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, gnew, gold));
+  return QF_OK;
+}
+
+int qf_cost(qf_ctx* ctx, int n, int n_builders, const void* builder, int precision, double* cost_out,
+            void* trace_out) {
+  if (!ctx) return QF_EINVAL;
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (n_builders < 1) return fail(ctx, QF_EINVAL, "n_builders must be >= 1");
+  if (!builder || !cost_out) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  DeviceGuard dg(ctx->device);
+  QF_HIP(ctx, launch_cost(ctx->stream, precision, builder, n, n_builders, cost_out,
+                          reinterpret_cast<double*>(trace_out)));
+  return QF_OK;
+}
+
+int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                   const void* init_gates, int n_starts, double tol, const qf_options* opt, void* workspace,
+                   size_t ws_bytes, void* out_gates, void* out_all_gates, double* out_costs, qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, QF_EINVAL, "tol must be finite and > 0");
+  o.dist_tol = tol;
+  int rc = validate_options(ctx, o);
+  if (rc) return rc;
+  rc = validate_problem(ctx, n, n_gates, locations, n_starts);
+  if (rc) return rc;
+  if (!target || !init_gates || !out_gates || !out_costs)
+    return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (stats && stats->cost_history && stats->cost_history_rows < 0)
+    return fail(ctx, QF_EINVAL, "cost_history_rows must be >= 0");
+  const int mode = resolve_mode(n, o);
+  if (mode == QF_MODE_RESIDENT && n > 6) return fail(ctx, QF_EUNSUPPORTED, "resident mode needs n <= 6");
+  const int rows = resident_history_rows(mode, o);
+  const Layout L = make_layout(n, n_gates, n_starts, o, mode, rows);
+  if (!workspace || ws_bytes < L.total)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  hipStream_t st = ctx->stream;
+  const size_t gate_bytes = (size_t)n_starts * n_gates * 256;
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.locs, locations, (size_t)n_gates * 8, hipMemcpyHostToDevice, st));
+
+  RunOut out;
+  if (mode == QF_MODE_RESIDENT)
+    rc = run_resident(ctx, n, target, n_gates, n_starts, tol, o, ws, L, stats, rows, out);
+  else
+    rc = run_streaming(ctx, n, target, n_gates, locations, n_starts, tol, o, ws, L, stats, out);
+  if (rc) return rc;
+
+  int best = 0;
+  bool all_numeric = true;
+  for (int s = 0; s < n_starts; ++s) {
+    double cs = out.final_costs[s];
+    if (!std::isfinite(cs) || (s < (int)out.flags.size() && (out.flags[s] & kFlagNumeric))) cs = INFINITY;
+    out.final_costs[s] = cs;
+    out_costs[s] = cs;
+    all_numeric = all_numeric && !std::isfinite(cs);
+    if (cs < out.final_costs[best]) best = s;
+  }
+  QF_HIP(ctx, hipMemcpyAsync(out_gates, ws + L.gates + (size_t)best * n_gates * 256, (size_t)n_gates * 256,
+                             hipMemcpyDeviceToDevice, st));
+  if (out_all_gates)
+    QF_HIP(ctx, hipMemcpyAsync(out_all_gates, ws + L.gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  int status = QF_MAX_ITER;
+  if (all_numeric)
+    status = QF_NUMERIC;
+  else if (out.final_costs[best] < tol)
+    status = QF_CONVERGED;
+  else if (out.decision == kStopPlateau)
+    status = QF_PLATEAU;
+  if (stats) {
+    stats->sweeps = out.sweeps;
+    stats->best_start = best;
+    stats->status = status;
+    stats->n_resets = out.resets;
+    stats->n_rechecks = out.rechecks;
+    stats->mode_used = mode;
+    stats->best_cost = out.final_costs[best];
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (all_numeric) return fail(ctx, QF_ENUMERIC, "every start produced non-finite values");
+  return QF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal launch interface between the C-ABI/runtime layer and the HIP
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qfactor.h"
+
+namespace qf {
+
+// Geometry of one two-sided pass X <- (A (x) I) X (B (x) I) over S builders
+// for a gate whose local MSB sits at bit b0 and local LSB at bit b1 of the
+// row/column index.  A workgroup owns one "row quad" (the 4 rows that differ
+// only in b0/b1) times TCOLS columns: nseg segments of TC contiguous columns,
+// chosen so that the 4 column variants of every block lie inside the tile.
+struct PassGeom {
+  uint32_t n, N;
+  uint32_t b0, b1, rlo, rhi;
+  uint32_t tc;         // log2 TC
+  uint32_t tcols_log;  // log2 TCOLS
+  uint32_t nseg;       // 1, 2 or 4
+  uint32_t seg_lo, seg_hi;   // column bits split off as segments (insert order)
+  uint32_t seg_off[4];       // column offset of each segment
+  uint32_t tb0, tb1, tblo, tbhi;  // local bit positions inside a tile column index
+  uint32_t col_tiles;        // column tiles per row quad
+  uint32_t tiles_per_start;  // (N/4) * col_tiles
+};
+
+PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols);
+
+// Operand of a pass: per-start 4x4 c128 FP64 matrix (stride in complex
+// entries between starts), optionally conjugate-transposed.
+struct Operand {
+  const double* ptr;  // interleaved c128, nullptr = identity (side skipped)
+  int64_t stride;     // complex entries between consecutive starts
+  int dagger;
+};
+
+hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
+                       Operand B);
+
+hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void* X, int n, int S);
+
+// Partial trace over every qubit but (q0, q1), FP64.  Optionally followed by
+// the sweep's gate update for gate `gidx` (see qf_update_gate): then the
+// environment is E = u_old^dagger P (half 0) or P u_old^dagger (half 1),
+// u_new is written to gates[s*gstride + gidx*16], u_old is saved to uold.
+struct EnvArgs {
+  int n, q0, q1;
+  int S;
+  int do_update;   // 0: env only (env_out = P)
+  int half;
+  double beta;
+  double* gates;   // c128, per start stride gstride complex entries
+  int64_t gstride;
+  int gidx;
+  double* uold;    // c128 S x 16 (update mode)
+  double* env_out; // c128 S x 16, optional
+  const int32_t* frozen;  // optional per-start flag: nonzero keeps the gate
+  double* partials;       // c128 S x env_workgroups(n) x 16 (needed when > 1 workgroup)
+  int32_t* counters;      // S ints, zero before the first launch; left zero
+};
+uint32_t env_workgroups(int n);
+int pass_max_tcols(int precision);
+hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a);
+
+hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int S, double* cost,
+                       double* trace);
+
+hipError_t launch_optimize(hipStream_t st, int count, const double* env, const double* uold,
+                           double beta, double* unew);
+
+// LDS-resident whole instantiation (n <= 6).
+struct ResidentArgs {
+  int n, p, S;
+  int precision;
+  const double* V;        // c128 N x N
+  const int32_t* locs;    // device p x 2
+  double* gates;          // c128 S x p x 16 (in: init, out: final)
+  double tol;
+  qf_options opt;
+  // per-start state (device): costs history ring, flags
+  double* hist;           // S x (ring) doubles
+  int32_t ring;           // ring length (>= long_diff_count + 1)
+  int32_t* flags;         // 2 x S (double-buffered by sweep parity)
+  double* cur_cost;       // S, last cost seen by the tests
+  double* final_cost;     // S, FP64 cost of the final gates
+  int32_t* sync;          // grid barrier words (zeroed by the host)
+  int32_t* out_info;      // [0]=sweeps [1]=decision [2]=resets [3]=rechecks [4]=timeout
+  double* history_out;    // optional (rows x S)
+  int32_t history_rows;
+};
+hipError_t launch_resident(hipStream_t st, const ResidentArgs& a, int* ok_coresident);
+size_t resident_lds_bytes(int n, int precision);
+
+}  // namespace qf

@@ -1,0 +1,499 @@
+// Streaming kernels: builders live in HBM and every gate update is one
+// LDS-staged pass over them.
+//
+//   k_build_init   X_s <- V^dagger (cast to the builder precision)
+//   k_pass         X_s <- (A_s (x) I) X_s (B_s (x) I)   (either side optional)
+//   k_env          P_s = Tr_rest X_s in FP64 over many workgroups; the last
+//                  workgroup of each start finishes the sum in a fixed order
+//                  and, in sweep mode, runs the FP64 gate update
+//   k_cost         Tr X_s and 1 - |Tr X_s| / N in FP64
+//   k_optimize     batched FP64 gate update on given environments
+#include <hip/hip_runtime.h>
+
+#include "qf_device.h"
+#include "qf_internal.h"
+
+namespace qf {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename R>
+struct Vec16;  // 16-byte vector of builder elements
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int elems = 2;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int elems = 1;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> to_r(cd v) {
+  return cx<R>{static_cast<R>(v.re), static_cast<R>(v.im)};
+}
+
+// Load the 4x4 operand of start s (optionally conjugate-transposed) in the
+// builder precision.
+template <typename R>
+__device__ __forceinline__ void load_operand(cx<R> m[16], const Operand& op, uint32_t s) {
+  const cd* src = reinterpret_cast<const cd*>(op.ptr) + (int64_t)s * op.stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cd v = op.dagger ? conj(src[4 * c + r]) : src[4 * r + c];
+      m[4 * r + c] = to_r<R>(v);
+    }
+}
+
+__device__ __forceinline__ uint32_t ilog2u(uint32_t v) { return 31u - __builtin_clz(v); }
+
+// ------------------------------------------------------------------ geometry
+
+PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols) {
+  PassGeom g{};
+  g.n = (uint32_t)n;
+  g.N = 1u << n;
+  g.b0 = (uint32_t)(n - 1 - q0);
+  g.b1 = (uint32_t)(n - 1 - q1);
+  g.rlo = g.b0 < g.b1 ? g.b0 : g.b1;
+  g.rhi = g.b0 < g.b1 ? g.b1 : g.b0;
+  uint32_t tcols = g.N < (uint32_t)max_tcols ? g.N : (uint32_t)max_tcols;
+  uint32_t tl = 0;
+  while ((1u << tl) < tcols) ++tl;
+  g.tcols_log = tl;
+  if (g.rhi < tl) {  // both local column bits inside one contiguous segment
+    g.nseg = 1;
+    g.tc = tl;
+    g.tb0 = g.b0;
+    g.tb1 = g.b1;
+    g.seg_lo = g.seg_hi = 0;
+  } else if (g.rlo + 1 < tl) {  // high bit split off as two segments
+    g.nseg = 2;
+    g.tc = tl - 1;
+    g.seg_lo = g.seg_hi = g.rhi;
+    if (g.b0 == g.rhi) {
+      g.tb0 = g.tc;
+      g.tb1 = g.b1;
+    } else {
+      g.tb1 = g.tc;
+      g.tb0 = g.b0;
+    }
+  } else {  // both bits split off: four segments, one per local column index
+    g.nseg = 4;
+    g.tc = tl - 2;
+    g.seg_lo = g.rlo;
+    g.seg_hi = g.rhi;
+    g.tb0 = g.tc + 1;
+    g.tb1 = g.tc;
+  }
+  for (uint32_t sgi = 0; sgi < 4; ++sgi) {
+    if (g.nseg == 4)
+      g.seg_off[sgi] = local_off(sgi, g.b0, g.b1);
+    else if (g.nseg == 2)
+      g.seg_off[sgi] = (sgi & 1u) << g.rhi;
+    else
+      g.seg_off[sgi] = 0;
+  }
+  g.tblo = g.tb0 < g.tb1 ? g.tb0 : g.tb1;
+  g.tbhi = g.tb0 < g.tb1 ? g.tb1 : g.tb0;
+  g.col_tiles = g.N >> tl;
+  g.tiles_per_start = (g.N >> 2) * g.col_tiles;
+  return g;
+}
+
+// ------------------------------------------------------------------ k_pass
+
+// One workgroup = one row quad x TCOLS columns (4*TCOLS elements), one
+// thread per 4x4 block.  The tile is loaded with 16-byte coalesced loads into
+// LDS, every thread transforms its block in registers and writes it back,
+// and the tile is stored with the same coalesced pattern.
+template <typename R, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g, Operand A,
+                                              Operand B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* tile = reinterpret_cast<cx<R>*>(smem_raw);
+  using V = typename Vec16<R>::type;
+  constexpr uint32_t VE = Vec16<R>::elems;
+
+  const uint32_t TCOLS = 1u << g.tcols_log;
+  const uint32_t NT = TCOLS >> 2;
+  const uint32_t t = threadIdx.x;
+  const uint32_t bid = blockIdx.x;
+  const uint32_t s = bid / g.tiles_per_start;
+  const uint32_t rem = bid - s * g.tiles_per_start;
+  const uint32_t rq = rem / g.col_tiles;
+  const uint32_t ct = rem - rq * g.col_tiles;
+  const uint32_t base_row = insert00(rq, g.rlo, g.rhi);
+  uint32_t base_col = ct << g.tc;
+  if (g.nseg == 2)
+    base_col = insert0(base_col, g.seg_hi);
+  else if (g.nseg == 4)
+    base_col = insert00(base_col, g.seg_lo, g.seg_hi);
+  cx<R>* Xs = X + (size_t)s * g.N * g.N;
+  const uint32_t tcmask = (1u << g.tc) - 1u;
+  const uint32_t nvec = (4u << g.tcols_log) / VE;
+
+  auto gaddr = [&](uint32_t e) -> cx<R>* {
+    const uint32_t i = e >> g.tcols_log;
+    const uint32_t tcol = e & (TCOLS - 1u);
+    const uint32_t seg = tcol >> g.tc;
+    const uint32_t segoff = (g.nseg == 4) ? local_off(seg, g.b0, g.b1)
+                                          : ((g.nseg == 2) ? (seg << g.seg_hi) : 0u);
+    const size_t row = base_row + local_off(i, g.b0, g.b1);
+    const size_t col = base_col + segoff + (tcol & tcmask);
+    return Xs + row * g.N + col;
+  };
+
+  for (uint32_t v = t; v < nvec; v += NT) {
+    const uint32_t e = v * VE;
+    *reinterpret_cast<V*>(tile + e) = *reinterpret_cast<const V*>(gaddr(e));
+  }
+
+  cx<R> a[16], b[16];
+  if (HA) load_operand<R>(a, A, s);
+  if (HB) load_operand<R>(b, B, s);
+  __syncthreads();
+
+  {
+    const uint32_t cb = insert00(t, g.tblo, g.tbhi);
+    uint32_t col[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) col[j] = cb + local_off(j, g.tb0, g.tb1);
+    cx<R> x[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) x[4 * i + j] = tile[i * TCOLS + col[j]];
+    if (HA) {  // x <- A x
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cx<R> r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cmac(acc, a[4 * i + k], x[4 * k + j]);
+          r[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * i + j] = r[i];
+      }
+    }
+    if (HB) {  // x <- x B
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        cx<R> r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) cmac(acc, x[4 * i + l], b[4 * l + j]);
+          r[j] = acc;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = r[j];
+      }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) tile[i * TCOLS + col[j]] = x[4 * i + j];
+  }
+  __syncthreads();
+
+  for (uint32_t v = t; v < nvec; v += NT) {
+    const uint32_t e = v * VE;
+    *reinterpret_cast<V*>(gaddr(e)) = *reinterpret_cast<const V*>(tile + e);
+  }
+}
+
+int pass_max_tcols(int precision) { return precision == QF_C64 ? 1024 : 512; }
+
+template <typename R>
+static hipError_t launch_pass_t(hipStream_t st, void* X, int S, const PassGeom& g, Operand A,
+                                Operand B) {
+  const uint32_t TCOLS = 1u << g.tcols_log;
+  const dim3 block(TCOLS >> 2);
+  const dim3 grid((uint32_t)S * g.tiles_per_start);
+  const size_t lds = 4u * TCOLS * sizeof(cx<R>);
+  cx<R>* x = reinterpret_cast<cx<R>*>(X);
+  if (A.ptr && B.ptr)
+    hipLaunchKernelGGL((k_pass<R, true, true>), grid, block, lds, st, x, g, A, B);
+  else if (A.ptr)
+    hipLaunchKernelGGL((k_pass<R, true, false>), grid, block, lds, st, x, g, A, B);
+  else if (B.ptr)
+    hipLaunchKernelGGL((k_pass<R, false, true>), grid, block, lds, st, x, g, A, B);
+  else
+    return hipSuccess;
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
+                       Operand B) {
+  if (precision == QF_C64) return launch_pass_t<float>(st, X, S, g, A, B);
+  return launch_pass_t<double>(st, X, S, g, A, B);
+}
+
+// Rests handled by one k_env workgroup: 256 threads = 16 (i,j) pairs x 16,
+// four rests each.
+constexpr uint32_t kEnvRestsPerWG = 64;
+
+// ------------------------------------------------------------------ k_build_init
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_build_init(const cd* __restrict__ V, cx<R>* __restrict__ X,
+                                                    uint32_t N, uint32_t S) {
+  __shared__ cd tile[32][33];
+  const uint32_t tilesx = (N + 31) / 32;
+  const uint32_t bx = blockIdx.x % tilesx, by = blockIdx.x / tilesx;
+  const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // read V rows by*32.., cols bx*32..
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t r = by * 32 + ty + 8 * k, c = bx * 32 + tx;
+    if (r < N && c < N) tile[ty + 8 * k][tx] = V[(size_t)r * N + c];
+  }
+  __syncthreads();
+  // X[c][r] = conj(V[r][c])
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t xr = bx * 32 + ty + 8 * k, xc = by * 32 + tx;
+    if (xr < N && xc < N) {
+      const cx<R> v = to_r<R>(conj(tile[tx][ty + 8 * k]));
+      for (uint32_t s = 0; s < S; ++s) X[((size_t)s * N + xr) * N + xc] = v;
+    }
+  }
+}
+
+hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void* X, int n, int S) {
+  const uint32_t N = 1u << n;
+  const uint32_t tiles = (N + 31) / 32;
+  const dim3 grid(tiles * tiles), block(256);
+  if (precision == QF_C64)
+    hipLaunchKernelGGL(k_build_init<float>, grid, block, 0, st, reinterpret_cast<const cd*>(V),
+                       reinterpret_cast<cf*>(X), N, (uint32_t)S);
+  else
+    hipLaunchKernelGGL(k_build_init<double>, grid, block, 0, st, reinterpret_cast<const cd*>(V),
+                       reinterpret_cast<cd*>(X), N, (uint32_t)S);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_env
+
+struct EnvDev {
+  EnvArgs a;
+  uint32_t N, nrest, b0, b1, rlo, rhi, nwg;
+};
+
+// Finish one start: P (16 FP64 complex) -> env_out and/or gate update.
+__device__ inline void env_finish(const EnvDev& d, uint32_t s, const cd* P) {
+  const EnvArgs& a = d.a;
+  if (!a.do_update) {
+    if (a.env_out) {
+      cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
+      for (int e = 0; e < 16; ++e) eo[e] = P[e];
+    }
+    return;
+  }
+  cd* gp = reinterpret_cast<cd*>(a.gates) + (int64_t)s * a.gstride + 16 * (int64_t)a.gidx;
+  cd uold[16], e[16], unew[16];
+  for (int k = 0; k < 16; ++k) uold[k] = gp[k];
+  // E = u_old^dagger P (half 0) or P u_old^dagger (half 1): the removal of the
+  // old gate commutes with the partial trace.
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      cd acc = mk(0.0, 0.0);
+      for (int k = 0; k < 4; ++k) {
+        if (a.half == 0)
+          cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
+        else
+          cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
+      }
+      e[4 * r + c] = acc;
+    }
+  if (a.env_out) {
+    cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
+    for (int k = 0; k < 16; ++k) eo[k] = e[k];
+  }
+  if (a.frozen && a.frozen[s]) {
+    for (int k = 0; k < 16; ++k) unew[k] = uold[k];
+  } else {
+    optimize_gate_f64(e, uold, a.beta, unew);
+  }
+  cd* uo = reinterpret_cast<cd*>(a.uold) + 16 * (size_t)s;
+  for (int k = 0; k < 16; ++k) {
+    uo[k] = uold[k];
+    gp[k] = unew[k];
+  }
+}
+
+// Grid: S x nwg workgroups of 256 threads.  Thread t sums entry (i,j) = t%16
+// over four 'rest' values; the workgroup reduces to 16 FP64 sums in a fixed
+// tree; with nwg > 1 each workgroup writes its 16 partials and the last one
+// to arrive (device-scope counter) adds them in workgroup order.
+template <typename R>
+__global__ __launch_bounds__(256) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
+  __shared__ cd red[256];
+  __shared__ int last;
+  const uint32_t t = threadIdx.x;
+  const uint32_t s = blockIdx.x / d.nwg;
+  const uint32_t w = blockIdx.x - s * d.nwg;
+  const uint32_t ij = t & 15u, i = ij >> 2, j = ij & 3u;
+  const uint32_t ro = local_off(i, d.b0, d.b1), co = local_off(j, d.b0, d.b1);
+  const cx<R>* Xs = X + (size_t)s * d.N * d.N;
+  cx<R> v[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t rest = w * kEnvRestsPerWG + (t >> 4) + 16u * k;
+    v[k] = mk<R>(0, 0);
+    if (rest < d.nrest) {
+      const uint32_t base = insert00(rest, d.rlo, d.rhi);
+      v[k] = Xs[(size_t)(base + ro) * d.N + (base + co)];
+    }
+  }
+  cd acc = mk(0.0, 0.0);
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
+  red[t] = acc;
+  __syncthreads();
+  for (uint32_t stride = 128; stride >= 16; stride >>= 1) {
+    if (t < stride) red[t] = red[t] + red[t + stride];
+    __syncthreads();
+  }
+  if (d.nwg == 1) {
+    if (t == 0) env_finish(d, s, red);
+    return;
+  }
+  cd* part = reinterpret_cast<cd*>(d.a.partials) + ((size_t)s * d.nwg + w) * 16;
+  if (t < 16) {
+    part[t] = red[t];
+    __threadfence();
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int old =
+        __hip_atomic_fetch_add(&d.a.counters[s], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (old == (int)d.nwg - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (t < 16) {
+    const cd* ps = reinterpret_cast<const cd*>(d.a.partials) + (size_t)s * d.nwg * 16;
+    cd sum = mk(0.0, 0.0);
+    for (uint32_t k = 0; k < d.nwg; ++k) {
+      const double* q = reinterpret_cast<const double*>(&ps[k * 16 + t]);
+      const double re = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double im = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sum = sum + mk(re, im);
+    }
+    red[t] = sum;
+  }
+  __syncthreads();
+  if (t == 0) {
+    __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    env_finish(d, s, red);
+  }
+}
+
+uint32_t env_workgroups(int n) {
+  const uint32_t nrest = (1u << n) >> 2;
+  return (nrest + kEnvRestsPerWG - 1) / kEnvRestsPerWG;
+}
+
+hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a) {
+  EnvDev d{};
+  d.a = a;
+  d.N = 1u << a.n;
+  d.nrest = d.N >> 2;
+  d.b0 = (uint32_t)(a.n - 1 - a.q0);
+  d.b1 = (uint32_t)(a.n - 1 - a.q1);
+  d.rlo = d.b0 < d.b1 ? d.b0 : d.b1;
+  d.rhi = d.b0 < d.b1 ? d.b1 : d.b0;
+  d.nwg = env_workgroups(a.n);
+  if (d.nwg > 1 && (!a.partials || !a.counters)) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)a.S * d.nwg), block(256);
+  if (precision == QF_C64)
+    hipLaunchKernelGGL(k_env<float>, grid, block, 0, st, reinterpret_cast<const cf*>(X), d);
+  else
+    hipLaunchKernelGGL(k_env<double>, grid, block, 0, st, reinterpret_cast<const cd*>(X), d);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_cost
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cost(const cx<R>* __restrict__ X, uint32_t N, double* cost,
+                                              double* trace) {
+  __shared__ cd red[256];
+  const uint32_t t = threadIdx.x, s = blockIdx.x;
+  const cx<R>* Xs = X + (size_t)s * N * N;
+  cd acc = mk(0.0, 0.0);
+  for (uint32_t r0 = 0; r0 < N; r0 += 256u * 8u) {
+    cx<R> v[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint32_t r = r0 + t + 256u * k;
+      v[k] = r < N ? Xs[(size_t)r * N + r] : mk<R>(0, 0);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (uint32_t stride = 128; stride >= 1; stride >>= 1) {
+    if (t < stride) red[t] = red[t] + red[t + stride];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const cd tr = red[0];
+    if (trace) {
+      trace[2 * s] = tr.re;
+      trace[2 * s + 1] = tr.im;
+    }
+    cost[s] = 1.0 - sqrt(norm2(tr)) / (double)N;
+  }
+}
+
+hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int S, double* cost,
+                       double* trace) {
+  const uint32_t N = 1u << n;
+  if (precision == QF_C64)
+    hipLaunchKernelGGL(k_cost<float>, dim3(S), dim3(256), 0, st, reinterpret_cast<const cf*>(X), N,
+                       cost, trace);
+  else
+    hipLaunchKernelGGL(k_cost<double>, dim3(S), dim3(256), 0, st, reinterpret_cast<const cd*>(X), N,
+                       cost, trace);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_optimize
+
+__global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict__ env,
+                                                 const cd* __restrict__ uold, double beta,
+                                                 cd* __restrict__ unew) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= count) return;
+  cd e[16], u[16], un[16];
+  for (int k = 0; k < 16; ++k) {
+    e[k] = env[16 * s + k];
+    u[k] = uold[16 * s + k];
+  }
+  optimize_gate_f64(e, u, beta, un);
+  for (int k = 0; k < 16; ++k) unew[16 * s + k] = un[k];
+}
+
+hipError_t launch_optimize(hipStream_t st, int count, const double* env, const double* uold,
+                           double beta, double* unew) {
+  const int threads = 64;
+  hipLaunchKernelGGL(k_optimize, dim3((count + threads - 1) / threads), dim3(threads), 0, st, count,
+                     reinterpret_cast<const cd*>(env), reinterpret_cast<const cd*>(uold), beta,
+                     reinterpret_cast<cd*>(unew));
+  return hipGetLastError();
+}
+
+}  // namespace qf

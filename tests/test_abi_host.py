@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/qfactor.h declares, and its host-only logic
+(defaults, workspace sizing, argument validation) behaves as documented."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import paper_2306_08152_amd as pkg
+from paper_2306_08152_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qfactor.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pkg.lib_path()):
+        pkg.build_library()
+    return nat.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding_list():
+    assert declared_functions() == sorted(nat.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_options_default_match_paper(lib):
+    with open(os.path.join(ROOT, "tests", "golden", "default_hyperparameters.json")) as f:
+        ref = json.load(f)
+    o = nat.QfOptions()
+    lib.qf_options_default(ctypes.byref(o))
+    for k in ("dist_tol", "diff_tol_a", "diff_tol_r", "long_diff_count", "long_diff_r", "min_iter",
+              "max_iter", "reset_iter", "beta"):
+        assert getattr(o, k) == ref[k], k
+    assert o.precision == nat.QF_C128 and o.mode == nat.QF_MODE_AUTO
+
+
+def test_strerror(lib):
+    assert lib.qf_strerror(nat.QF_OK) == b"ok"
+    assert lib.qf_strerror(nat.QF_EINVAL) == b"invalid argument"
+    assert lib.qf_strerror(12345) == b"unknown status"
+
+
+def _opts(lib, **kw):
+    o = nat.QfOptions()
+    lib.qf_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_size_layout(lib):
+    # streaming, complex64: S builders of N^2 complex64 plus one complex128
+    # recheck copy each, plus small per-start state
+    o = _opts(lib, precision=nat.QF_C64, mode=nat.QF_MODE_STREAMING)
+    n, p, S = 10, 45, 16
+    N = 1 << n
+    ws = lib.qf_workspace_size(n, p, S, ctypes.byref(o))
+    assert S * N * N * (8 + 16) <= ws <= S * N * N * (8 + 16) + (8 << 20)
+    o = _opts(lib, precision=nat.QF_C128, mode=nat.QF_MODE_STREAMING)
+    ws128 = lib.qf_workspace_size(n, p, S, ctypes.byref(o))
+    assert S * N * N * 16 <= ws128 <= S * N * N * 16 + (8 << 20)
+    # resident mode keeps builders in LDS: small workspace
+    o = _opts(lib, mode=nat.QF_MODE_AUTO)
+    assert 0 < lib.qf_workspace_size(6, 15, 32, ctypes.byref(o)) < (4 << 20)
+    # invalid sizes -> 0
+    assert lib.qf_workspace_size(1, 4, 1, None) == 0
+    assert lib.qf_workspace_size(17, 4, 1, None) == 0
+    assert lib.qf_workspace_size(4, 0, 1, None) == 0
+    assert lib.qf_workspace_size(4, 3, 0, None) == 0
+    assert lib.qf_workspace_size(4, 3, 1, ctypes.byref(_opts(lib, beta=1.5))) == 0
+
+
+def test_null_context_is_rejected_before_device_work(lib):
+    locs = (ctypes.c_int32 * 2)(0, 1)
+    assert lib.qf_instantiate(None, 2, None, 1, locs, None, 1, 1e-8, None, None, 0, None, None, None,
+                              None) == nat.QF_EINVAL
+    assert lib.qf_apply_gate(None, 2, 1, None, 0, locs, None, 0, 0) == nat.QF_EINVAL
+    assert lib.qf_environment(None, 2, 1, None, 0, locs, None) == nat.QF_EINVAL
+    assert lib.qf_destroy(None) == nat.QF_EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.qf_create(None, 0, None) == nat.QF_EINVAL
+    assert lib.qf_create(ctypes.byref(ctx), -1, None) == nat.QF_EINVAL

@@ -1,0 +1,330 @@
+"""GPU parity: every step of the HIP path, called through the C ABI, against
+the FP64 oracle on the same seeded inputs.
+
+Tolerances: complex128 results agree with the oracle to 1e-10 (north-star
+bar; entries here are O(1), rounding differences are ~1e-14); complex64
+builder entries to 1e-5 relative to the largest entry; FP64 environments and
+gate updates computed from the same complex64 values to 1e-12; final costs of
+complex64 runs are FP64 re-evaluations and agree with the oracle's cost of the
+returned gates to 1e-12."""
+import numpy as np
+import pytest
+
+import oracle as O
+import qfinputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def pairs(n):
+    return [(a, b) for a in range(n) for b in range(n) if a != b]
+
+
+C128_TOL = 1e-10
+C64_REL = 1e-5
+
+
+# --------------------------------------------------------------- apply / build
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 10, 11])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_apply_gate_every_pair(qf, n, dtype):
+    """Every ordered qubit pair exercises every tile geometry (local bits
+    inside one segment, split into two segments, or four segments)."""
+    rng = np.random.default_rng(1000 + n)
+    S = 2
+    X0 = I.random_builder(rng, S, n)
+    if dtype == "c64":
+        X0 = X0.astype(np.complex64).astype(np.complex128)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    prs = pairs(n)
+    if n >= 10:
+        prs = prs[::3] + [(0, 1), (1, 0), (n - 1, n - 2), (n - 2, n - 1), (0, n - 1), (n - 1, 0)]
+    for k, loc in enumerate(prs):
+        u = np.stack([I.haar_unitary(rng, 4) for _ in range(S)])
+        side = k % 2
+        dag = (k // 2) % 2
+        X = dev(X0).to(tdt)
+        qf.apply_gate(X, loc, dev(u), side, bool(dag))
+        got = host(X).astype(np.complex128)
+        uu = np.conj(np.swapaxes(u, -1, -2)) if dag else u
+        ref = O.apply_left(X0, uu, loc, n) if side == 0 else O.apply_right(X0, uu, loc, n)
+        scale = np.abs(ref).max()
+        tol = C128_TOL * scale if dtype == "c128" else C64_REL * scale
+        assert np.abs(got - ref).max() <= tol, (loc, side, dag)
+
+
+@pytest.mark.parametrize("n,S", [(3, 1), (6, 3), (10, 2)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_build_matches_oracle_builder(qf, n, S, dtype):
+    rng = np.random.default_rng(7 + n)
+    p = 9
+    locs = np.asarray([tuple(rng.choice(n, 2, replace=False)) for _ in range(p)], np.int32)
+    V = I.haar_unitary(rng, 1 << n)
+    gates = np.stack([I.haar_gates(rng, p) for _ in range(S)])
+    X = qf.build(dev(V), locs, dev(gates), torch.complex128 if dtype == "c128" else torch.complex64)
+    got = host(X).astype(np.complex128)
+    ref = O.BuilderOracle(V, gates, locs, n).X
+    tol = C128_TOL if dtype == "c128" else C64_REL * np.abs(ref).max()
+    assert np.abs(got - ref).max() <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_build_n12_sampled_rows(qf, dtype):
+    """Full-size builder (n = 12, 44 gates): rows sampled one by one by the
+    oracle."""
+    pr = I.config5(n_starts=1, build_target=False)
+    rng = np.random.default_rng(12)
+    V = I.haar_unitary(rng, 1 << 12)  # a generic unitary stands in for the target here
+    X = qf.build(dev(V), pr.locs, dev(pr.init_gates), torch.complex128 if dtype == "c128" else torch.complex64)
+    rows = [0, 1, 777, 2048, 4095]
+    got = host(X[0, rows]).astype(np.complex128)
+    ref = O.builder_rows(V, pr.init_gates[0], pr.locs, 12, rows)
+    tol = C128_TOL if dtype == "c128" else C64_REL * np.abs(ref).max()
+    assert np.abs(got - ref).max() <= tol
+
+
+# --------------------------------------------------------------- environment
+
+@pytest.mark.parametrize("n", [2, 4, 7, 10, 12])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_environment(qf, n, dtype):
+    rng = np.random.default_rng(50 + n)
+    S = 3 if n < 12 else 1
+    X0 = I.random_builder(rng, S, n)
+    if dtype == "c64":
+        X0 = X0.astype(np.complex64).astype(np.complex128)
+    X = dev(X0).to(torch.complex128 if dtype == "c128" else torch.complex64)
+    prs = pairs(n) if n <= 4 else [(0, 1), (1, 0), (0, n - 1), (n - 1, 0), (n - 2, n - 1), (n // 2, 1)]
+    for loc in prs:
+        got = host(qf.environment(X, loc))
+        ref = O.partial_trace(X0, loc, n)
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), loc
+
+
+# --------------------------------------------------------------- gate update
+
+def test_optimize_gate_vs_lapack(qf):
+    rng = np.random.default_rng(99)
+    envs = []
+    for k in range(64):
+        E = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+        if k % 8 == 1:
+            E = 3.0 * I.haar_unitary(rng, 4)                   # scaled unitary
+        if k % 8 == 2:
+            E[:, 2] = 0.3 * E[:, 0] - 1j * E[:, 1]              # rank 3
+        if k % 8 == 3:
+            d = np.diag([1.0, 1e-3, 1e-6, 1e-9])
+            E = I.haar_unitary(rng, 4) @ d @ I.haar_unitary(rng, 4)  # ill conditioned
+        if k % 8 == 4:
+            E = 1e-200 * E                                       # tiny scale
+        envs.append(E)
+    E = np.stack(envs)
+    U0 = np.stack([I.haar_unitary(rng, 4) for _ in range(64)])
+    for beta in (0.0, 0.25):
+        got = host(qf.optimize_gate(dev(E), dev(U0), beta))
+        M = (1 - beta) * E + beta * np.conj(np.swapaxes(U0, -1, -2))
+        for k in range(64):
+            ref = O.optimize_gate(E[k], U0[k], beta)
+            assert np.abs(got[k].conj().T @ got[k] - np.eye(4)).max() < 1e-12
+            sv = np.linalg.svd(M[k], compute_uv=False)
+            if sv[-1] > 1e-10 * sv[0]:
+                assert np.abs(got[k] - ref).max() < 1e-10, k        # unique polar factor
+            # the attained value is the nuclear norm in every case
+            val = np.real(np.trace(M[k] @ got[k]))
+            assert abs(val - sv.sum()) <= 1e-12 * sv.sum(), k
+    # zero environment keeps the gate; NaN gives NaN
+    Z = np.zeros((2, 4, 4), complex)
+    Z[1, 0, 0] = np.nan
+    got = host(qf.optimize_gate(dev(Z), dev(U0[:2]), 0.0))
+    np.testing.assert_array_equal(got[0], U0[0])
+    assert np.all(np.isnan(got[1]))
+
+
+@pytest.mark.parametrize("n", [3, 7, 10])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_update_gate_steps(qf, n, dtype):
+    """A run of single TwoSidedSweep updates through qf_update_gate against
+    the oracle's builder mode, update by update."""
+    rng = np.random.default_rng(300 + n)
+    S, p = 2, 6
+    locs = np.asarray([tuple(rng.choice(n, 2, replace=False)) for _ in range(p)], np.int32)
+    V = I.haar_unitary(rng, 1 << n)
+    gates = np.stack([I.haar_gates(rng, p) for _ in range(S)])
+    ob = O.BuilderOracle(V, gates, locs, n)
+    X = qf.build(dev(V), locs, dev(gates), torch.complex128 if dtype == "c128" else torch.complex64)
+    G = dev(gates.copy())
+    steps = [(g, 0) for g in range(p - 1, -1, -1)] + [(g, 1) for g in range(p)]
+    for g, half in steps:
+        rec = []
+        Xb = X.to(torch.complex128) if dtype == "c64" else None
+        if dtype == "c64":
+            # the oracle starts each step from the GPU's complex64 builder
+            ob.X = host(Xb)
+            ob.gates = host(G).copy()
+        ob.update(g, half, record=rec)
+        gcol = G[:, g].contiguous()
+        _, env = qf.update_gate(X, tuple(locs[g]), half, gcol, 0.0, want_env=True)
+        G[:, g] = gcol
+        E_ref, u_ref = rec[0][2], rec[0][3]
+        assert np.abs(host(env) - E_ref).max() <= 1e-10 * max(1.0, np.abs(E_ref).max()), (g, half)
+        assert np.abs(host(gcol) - u_ref).max() <= 1e-9, (g, half)
+        tol = C128_TOL if dtype == "c128" else C64_REL * np.abs(ob.X).max()
+        assert np.abs(host(X).astype(np.complex128) - ob.X).max() <= tol, (g, half)
+
+
+def test_cost_kernel(qf):
+    rng = np.random.default_rng(5)
+    X0 = I.random_builder(rng, 4, 9)
+    c, tr = qf.cost(dev(X0))
+    ref_tr = np.trace(X0, axis1=1, axis2=2)
+    assert np.abs(host(tr) - ref_tr).max() < 1e-12
+    assert np.abs(host(c) - (1 - np.abs(ref_tr) / 512)).max() < 1e-14
+
+
+# --------------------------------------------------------------- instantiation
+
+def _oracle_opts(**kw):
+    return O.Options(**kw)
+
+
+def _run_both(qf, pr, tol, mode, precision, max_iter=100000, plateau=True, starts=None, hist_rows=2000):
+    init = pr.init_gates if starts is None else pr.init_gates[:starts]
+    kw = {} if plateau else dict(diff_tol_r=0.0, long_diff_count=0)
+    res = qf.instantiate(dev(pr.target), pr.locs, dev(init), tol=tol, mode=mode, precision=precision,
+                         max_iter=max_iter, history_rows=hist_rows, **kw)
+    ref = O.instantiate(pr.target, init, pr.locs, pr.n, tol=tol, opt=_oracle_opts(max_iter=max_iter, **kw))
+    return res, ref
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_config1_c128(qf, mode):
+    """n = 3, four U(4) gates, one start, c128, stop at 1e-10 or 1000 sweeps."""
+    pr = I.config1()
+    res, ref = _run_both(qf, pr, 1e-10, mode, 0, max_iter=1000, plateau=False, hist_rows=1001)
+    assert res.sweeps == ref.sweeps and res.status == ref.status
+    assert np.abs(res.history - ref.history[: res.history.shape[0]]).max() <= C128_TOL
+    assert abs(res.costs[0] - ref.costs[0]) <= C128_TOL
+    assert np.abs(host(res.gates) - ref.gates).max() <= 1e-8
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_config1_converging_start(qf, mode):
+    pr = I.config1()
+    pr.init_gates = I.haar_gates(I.rng_for(1, 1, 1000), 4)[None]
+    res, ref = _run_both(qf, pr, 1e-10, mode, 0, max_iter=1000, plateau=False)
+    assert ref.status == O.STATUS_CONVERGED
+    assert res.status == 0 and res.sweeps == ref.sweeps
+    assert res.costs[0] < 1e-10
+    assert np.abs(res.history - ref.history[: res.history.shape[0]]).max() <= C128_TOL
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_config2_c128(qf, mode):
+    """n = 6 brick-wall, 15 gates, 32 starts, tol 1e-8, default plateau tests."""
+    pr = I.config2()
+    res, ref = _run_both(qf, pr, 1e-8, mode, 0)
+    assert res.sweeps == ref.sweeps and res.status == ref.status and res.best_start == ref.best_start
+    assert np.abs(res.history - ref.history[: res.history.shape[0]]).max() <= C128_TOL
+    assert np.abs(res.costs - ref.costs).max() <= C128_TOL
+    assert res.costs[res.best_start] < 1e-8
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_config2_c64(qf, mode):
+    """Complex64 builder with FP64 gate updates, tests and final cost: the
+    returned costs are FP64 and equal the oracle's cost of the returned gates;
+    the best start reaches the tolerance."""
+    pr = I.config2()
+    res = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, mode=mode, precision=1,
+                         history_rows=2000)
+    allg = host(res.all_gates)
+    for s in range(pr.n_starts):
+        c = O.cost(pr.target, allg[s], pr.locs, pr.n)
+        assert abs(c - res.costs[s]) <= 1e-12, s
+        assert np.abs(np.conj(np.swapaxes(allg[s], -1, -2)) @ allg[s] - np.eye(4)).max() < 1e-12
+    assert res.status == 0 and res.costs[res.best_start] < 1e-8
+    # the first sweep tracks the FP64 trajectory to complex64 accuracy
+    ref = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-8, opt=O.Options(max_iter=1))
+    assert np.abs(res.history[1] - ref.history[1]).max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_n10_streaming_two_sweeps(qf, precision):
+    """Full-size n = 10 brick-wall (45 gates), two starts, two sweeps."""
+    pr = I.config3(n_starts=2)
+    res, ref = _run_both(qf, pr, 1e-8, 2, precision, max_iter=2, plateau=False)
+    assert res.sweeps == 2 and ref.sweeps == 2
+    tol = C128_TOL if precision == 0 else 1e-5
+    assert np.abs(res.history - ref.history).max() <= tol
+    assert np.abs(res.costs - ref.costs).max() <= (C128_TOL if precision == 0 else 1e-5)
+    if precision == 0:
+        assert np.abs(host(res.all_gates) - ref.all_gates).max() <= 1e-8
+
+
+def test_n12_one_sweep_properties(qf):
+    """n = 12 (44 gates), complex64, one sweep: the returned gates are
+    unitary, the cost does not increase, and the FP64 cost of the returned
+    gates matches a complex128 rebuild's trace."""
+    pr = I.config5(n_starts=1, build_target=False)
+    rng = np.random.default_rng(120)
+    # target: a random circuit on the same structure (built on the CPU)
+    tg = I.haar_gates(rng, pr.n_gates)
+    V = I.circuit_unitary(tg, pr.locs, 12)
+    res = qf.instantiate(dev(V), pr.locs, dev(pr.init_gates), tol=1e-8, mode=2, precision=1, max_iter=1,
+                         diff_tol_r=0.0, long_diff_count=0, history_rows=2)
+    g = host(res.all_gates)[0]
+    assert np.abs(np.conj(np.swapaxes(g, -1, -2)) @ g - np.eye(4)).max() < 1e-12
+    assert res.history[1, 0] <= res.history[0, 0] + 1e-6
+    X = qf.build(dev(V), pr.locs, dev(g[None]), torch.complex128)
+    c, _ = qf.cost(X)
+    assert abs(host(c)[0] - res.costs[0]) < 1e-12
+    # sampled rows of the complex128 rebuild against the oracle
+    rows = [5, 3000]
+    ref = O.builder_rows(V, g, pr.locs, 12, rows)
+    assert np.abs(host(X[0, rows]) - ref).max() < C128_TOL
+
+
+def test_determinism(qf):
+    pr = I.config2(n_starts=8)
+    a = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, max_iter=30)
+    b = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, max_iter=30)
+    assert np.array_equal(host(a.all_gates), host(b.all_gates))
+    pr3 = I.config3(n_starts=1)
+    a = qf.instantiate(dev(pr3.target), pr3.locs, dev(pr3.init_gates), tol=1e-8, max_iter=1, precision=1)
+    b = qf.instantiate(dev(pr3.target), pr3.locs, dev(pr3.init_gates), tol=1e-8, max_iter=1, precision=1)
+    assert np.array_equal(host(a.all_gates), host(b.all_gates))
+
+
+def test_nan_start_frozen(qf):
+    pr = I.config1()
+    bad = pr.init_gates[0].copy()
+    bad[2, 1, 1] = np.nan
+    init = np.stack([bad, pr.target_gates])
+    for mode in (1, 2):
+        res = qf.instantiate(dev(pr.target), pr.locs, dev(init), tol=1e-10, mode=mode, max_iter=5)
+        assert res.best_start == 1 and res.status == 0 and not np.isfinite(res.costs[0])
+
+
+def test_invalid_arguments_rejected(qf):
+    from paper_2306_08152_amd import QfError
+    pr = I.config1()
+    with pytest.raises(QfError):
+        qf.instantiate(dev(pr.target), [(0, 0)] * 4, dev(pr.init_gates), tol=1e-8)
+    with pytest.raises(QfError):
+        qf.instantiate(dev(pr.target), [(0, 3)] * 4, dev(pr.init_gates), tol=1e-8)
+    with pytest.raises(QfError):
+        qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=-1.0)
+    with pytest.raises(QfError):
+        qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, mode=1, beta=2.0)
