@@ -283,13 +283,16 @@ def environment(V: np.ndarray, gates, locs, n: int, g: int) -> np.ndarray:
 
 def optimize_gate(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.ndarray:
     """argmax over unitary u of Re Tr(M u) for M = (1-beta) E + beta u_old^dagger:
-    SVD M = X D Y^dagger gives u = Y X^dagger.  A zero M keeps u_old (Q15)."""
+    SVD M = X D Y^dagger gives u = Y X^dagger.  A zero M (largest entry below
+    1e-300) keeps u_old (Q15)."""
     M = (1.0 - beta) * E + beta * u_old.conj().T
     if not np.all(np.isfinite(M)):
         return np.full_like(u_old, np.nan)
-    if np.linalg.norm(M) <= 1e-300:
+    scale = np.max(np.abs(M))
+    if scale < 1e-300:
         return u_old.copy()
-    Xs, _, Yh = np.linalg.svd(M)
+    # the maximiser is unchanged by a positive scaling of M: normalise first
+    Xs, _, Yh = np.linalg.svd(M / scale)
     return Yh.conj().T @ Xs.conj().T
 
 
@@ -298,8 +301,9 @@ def optimize_gate_batched(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -
     the zero and non-finite guards are applied per entry afterwards)."""
     M = (1.0 - beta) * E + beta * np.conj(np.swapaxes(u_old, -1, -2))
     finite = np.all(np.isfinite(M), axis=(-2, -1))
-    zero = np.linalg.norm(np.where(finite[:, None, None], M, 0.0), axis=(-2, -1)) <= 1e-300
-    Ms = np.where((finite & ~zero)[:, None, None], M, np.eye(4))
+    scale = np.max(np.abs(np.where(finite[:, None, None], M, 0.0)), axis=(-2, -1))
+    zero = scale < 1e-300
+    Ms = np.where((finite & ~zero)[:, None, None], M / np.where(zero, 1.0, scale)[:, None, None], np.eye(4))
     Xs, _, Yh = np.linalg.svd(Ms)
     out = np.conj(np.swapaxes(Yh, -1, -2)) @ np.conj(np.swapaxes(Xs, -1, -2))
     out = np.where(zero[:, None, None], u_old, out)

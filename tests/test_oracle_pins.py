@@ -418,3 +418,17 @@ def test_builder_rows_one_by_one():
     X = O.circuit_unitary(gates, locs, n, dense=True) @ V.conj().T
     rows = [0, 3, 17, 31]
     np.testing.assert_allclose(O.builder_rows(V, gates, locs, n, rows), X[rows], atol=1e-13)
+
+
+def test_update_scale_invariance():
+    """The maximiser does not depend on a positive scale of the environment,
+    down to tiny and up to huge magnitudes; only a zero environment keeps the
+    old gate."""
+    rng = np.random.default_rng(31)
+    E = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    u0 = haar(4, rng)
+    ref = O.optimize_gate(E, u0)
+    for c in (1e-200, 1e-100, 1e100, 1e200):
+        np.testing.assert_allclose(O.optimize_gate(c * E, u0), ref, atol=1e-13)
+        np.testing.assert_allclose(O.optimize_gate_batched((c * E)[None], u0[None])[0], ref, atol=1e-13)
+    np.testing.assert_array_equal(O.optimize_gate(1e-305 * E, u0), u0)
