@@ -1,0 +1,249 @@
+"""Benchmark of the QFactor instantiation sweep on one MI355X.
+
+One JSON line on stdout.  The headline workload is the n = 10 open-chain
+brick-wall of depth 10 (45 general two-qubit gates, 1024 x 1024 builders),
+16 multistarts, complex64 builder with the FP64 SVD step, FP64 tests and FP64
+final cost.  A "step" is one TwoSidedSweep of every start (the whole hot path:
+environment + SVD step + fused remove/re-apply per gate, cost, termination
+test).  `value` is start-sweeps per second over the whole timed
+qf_instantiate call (builder construction, the K sweeps, the per-sweep cost
+read-back and the final FP64 re-evaluation included), inputs resident in HBM.
+
+Extra workloads are reported in the same line: the complex128 form of the same
+problem, n = 12 (44 gates, one start, 4096 x 4096 builder) in both precisions,
+and full n = 6 / n = 3 instantiations (converged instantiations per second).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+                       [--probe copy]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--probe", choices=["copy"], default=None,
+                    help="run only a plain device copy of known size (traffic-counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def brickwall_problem(qf, torch, cfg_id, n, layers, starts, build_on_gpu):
+    """Seeded Haar brick-wall problem.  For large n the target V = C(target
+    gates) is formed on the GPU by the library's own builder with V = I."""
+    import qfinputs as I
+    locs = I.brickwall_locations(n, layers)
+    pr = I.make_problem(cfg_id, f"n{n}", n, locs, starts, build_target=not build_on_gpu)
+    init = torch.from_numpy(pr.init_gates).to("cuda")
+    if build_on_gpu:
+        eye = torch.eye(1 << n, dtype=torch.complex128, device="cuda")
+        tg = torch.from_numpy(pr.target_gates[None]).to("cuda")
+        V = qf.build(eye, locs, tg, torch.complex128)[0].contiguous()
+    else:
+        V = torch.from_numpy(pr.target).to("cuda")
+    torch.cuda.synchronize()
+    return pr, V, init
+
+
+def timed_sweeps(qf, torch, V, locs, init, precision, sweeps, warmup, timing=False):
+    """Wall time of one qf_instantiate call running exactly `sweeps` sweeps
+    (plateau tests off, tolerance unreachable)."""
+    kw = dict(tol=1e-300, precision=precision, mode=2, diff_tol_r=0.0, long_diff_count=0)
+    if warmup > 0:
+        qf.instantiate(V, locs, init, max_iter=warmup, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = qf.instantiate(V, locs, init, max_iter=sweeps, timing=timing, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+def copy_probe(torch):
+    """Plain device copy of 256 MiB, 10 times (calibrates the HBM traffic
+    counters against a known byte count)."""
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"probe": "copy", "bytes_per_launch": n, "launches": 10,
+                      "GBps_read_plus_write": 2 * n * 10 / dt / 1e9}), flush=True)
+
+
+def cpu_baseline(n_sweeps=3):
+    """The FP64 oracle (builder mode) on the host: 3 sweeps of one start of the
+    n = 10 headline problem."""
+    import oracle as O
+    import qfinputs as I
+    from threadpoolctl import threadpool_info
+    pr = I.config3(n_starts=1)
+    t0 = time.perf_counter()
+    b = O.BuilderOracle(pr.target, pr.init_gates, pr.locs, pr.n)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(n_sweeps):
+        b.sweep()
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {"value": n_sweeps / dt, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"n=10 brick-wall depth 10 (45 gates), 1 start, {n_sweeps} sweeps of the FP64 NumPy "
+                      f"builder-mode oracle ({dt:.1f} s; builder construction {t_init:.1f} s not counted); "
+                      f"CPU: {cpu_model()}",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the multistart and block dimensions shard "
+                                   "across GPUs only by running independent processes, which this benchmark "
+                                   "does not do; run with --gpus 1"}), flush=True)
+        sys.exit(2)
+    import torch
+    import paper_2306_08152_amd as qf
+    qf.load()  # fails loudly when the HIP library is missing
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU")
+    torch.cuda.set_device(0)
+    if args.probe == "copy":
+        copy_probe(torch)
+        return
+
+    K, W = max(1, args.steps), max(0, args.warmup)
+    n, layers, S = 10, 10, 16
+    pr, V, init = brickwall_problem(qf, torch, 3, n, layers, S, build_on_gpu=False)
+    N = 1 << n
+
+    # ---- headline: complex64 builder + FP64 SVD step / tests / final cost
+    dt, res = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, W)
+    value = S * K / dt
+    # ---- dominant kernel (fused remove/re-apply pass), HIP events in the library
+    _, rt = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, 0, timing=True)
+    tm = rt.timing
+    pass_bytes = 2 * S * N * N * 8          # read + write of every builder, complex64
+    pass_avg_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+    achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
+    env_avg_us = 1e3 * tm["env_ms"] / max(1, tm["env_launches"])
+    sweep_loop_rate = S * K / (tm["sweep_ms"] * 1e-3) if tm["sweep_ms"] > 0 else None
+
+    out = {
+        "metric": "sweeps/sec (n=10,12) + converged instantiations/sec; % of HBM roofline",
+        "value": round(value, 2),
+        "unit": "start-sweeps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * dt / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 builder (fp32 complex) + f64 SVD step, tests and final cost",
+        "data": "synthetic: seeded Haar-random U(4) brick-wall targets and Haar initial gates",
+        "config": {"workload": "n10_brickwall10_p45_s16_c64", "n_qubits": n, "n_gates": pr.n_gates,
+                   "starts": S, "builder": "1024x1024 complex64 per start", "parallelism": "multistarts"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_pass<float,true,true> (fused remove + re-apply, one read + one write of "
+                               "all 16 builders per launch)",
+                     "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
+                     "launches_timed": tm["pass_launches"]},
+        "breakdown": {"pass_avg_us": round(1e3 * pass_avg_ms, 2), "env_svd_avg_us": round(env_avg_us, 2),
+                      "sweep_loop_start_sweeps_per_s": round(sweep_loop_rate, 2) if sweep_loop_rate else None,
+                      "final_best_cost": float(np.min(res.costs))},
+    }
+
+    if not args.no_extra:
+        extra = {}
+        # complex128 form of the same problem
+        K2 = max(2, K // 2)
+        dt128, _ = timed_sweeps(qf, torch, V, pr.locs, init, 0, K2, 1)
+        extra["n10_c128_start_sweeps_per_s"] = round(S * K2 / dt128, 2)
+        extra["n10_c64_over_c128_speedup"] = round(value / (S * K2 / dt128), 3)
+        # n = 12, one start
+        pr12, V12, init12 = brickwall_problem(qf, torch, 5, 12, 8, 1, build_on_gpu=True)
+        K3 = max(2, K // 4)
+        d12, r12 = timed_sweeps(qf, torch, V12, pr12.locs, init12, 1, K3, 1, timing=True)
+        t12 = r12.timing
+        b12 = 2 * (1 << 24) * 8
+        a12 = b12 / (t12["pass_ms"] / max(1, t12["pass_launches"]) * 1e-3) / 1e9
+        extra["n12_c64_sweeps_per_s"] = round(K3 / d12, 3)
+        extra["n12_c64_pass_GBps"] = round(a12, 1)
+        d12b, _ = timed_sweeps(qf, torch, V12, pr12.locs, init12, 0, K3, 1)
+        extra["n12_c128_sweeps_per_s"] = round(K3 / d12b, 3)
+        del V12, init12
+        # n = 6 and n = 3 full instantiations (resident mode)
+        import qfinputs as I
+        p2 = I.config2()
+        V6 = torch.from_numpy(p2.target).to("cuda")
+        i6 = torch.from_numpy(p2.init_gates).to("cuda")
+        for prec, tag in ((0, "c128"), (1, "c64")):
+            qf.instantiate(V6, p2.locs, i6, tol=1e-8, precision=prec)   # warm-up
+            times, conv, sw = [], 0, 0
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r6 = qf.instantiate(V6, p2.locs, i6, tol=1e-8, precision=prec)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                conv += int(r6.costs[r6.best_start] < 1e-8)
+                sw = r6.sweeps
+            extra[f"n6_s32_{tag}_converged_inst_per_s"] = round(conv / sum(times), 3)
+            extra[f"n6_s32_{tag}_ms_per_inst"] = round(1e3 * float(np.median(times)), 3)
+            extra[f"n6_s32_{tag}_sweeps"] = sw
+        p1 = I.config1()
+        V3 = torch.from_numpy(p1.target).to("cuda")
+        i3 = torch.from_numpy(p1.init_gates).to("cuda")
+        qf.instantiate(V3, p1.locs, i3, tol=1e-10, max_iter=1000, diff_tol_r=0.0, long_diff_count=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r3 = qf.instantiate(V3, p1.locs, i3, tol=1e-10, max_iter=1000, diff_tol_r=0.0, long_diff_count=0)
+        torch.cuda.synchronize()
+        d3 = time.perf_counter() - t0
+        extra["n3_p4_c128_sweeps_per_s"] = round(r3.sweeps / d3, 1)
+        extra["n3_p4_c128_status"] = int(r3.status)
+        out["extra"] = extra
+
+    if not args.no_cpu:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["value"] = round(cb["value"], 4)
+        out["cpu_baseline"]["unit"] = "start-sweeps/s"
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -121,11 +121,23 @@ typedef struct {
                             row i receives the costs after sweep i (row 0 =
                             initial gates) for i < cost_history_rows */
   int32_t cost_history_rows;
+  int32_t timing;        /* in: nonzero records HIP events around every
+                            kernel of the streaming sweep loop */
+  int32_t pass_launches; /* out (timing): fused builder passes in the sweeps */
+  int32_t env_launches;  /* out (timing): environment + SVD-step launches */
+  double pass_ms;        /* out (timing): summed durations of those passes */
+  double env_ms;         /* out (timing): summed durations of those launches */
+  double sweep_ms;       /* out (timing): device time of the sweep loop */
 } qf_stats;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
  * NULL = the device's null stream).  Allocates a few KiB of pinned host
- * memory for per-sweep cost read-back; no device memory. */
+ * memory for per-sweep cost read-back.  qf_instantiate works in the caller's
+ * workspace; the stand-alone step calls (qf_environment, qf_update_gate) use
+ * a small device scratch owned by the context (partial sums of the
+ * environment, a few KiB per builder), allocated on first use and grown on
+ * demand; qf_destroy frees it.  A context may be used by one host thread at
+ * a time. */
 int qf_create(qf_ctx** ctx, int device, void* hip_stream);
 int qf_destroy(qf_ctx* ctx);
 int qf_set_stream(qf_ctx* ctx, void* hip_stream);

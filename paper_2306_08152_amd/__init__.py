@@ -5,17 +5,21 @@ of include/qfactor.h; this package only marshals torch tensors to it.  There is
 no CPU fallback: the calls raise if the library is not built or no GPU is
 present.
 """
+import importlib
+
 from ._native import (  # noqa: F401
     QF_C128, QF_C64, QF_MODE_AUTO, QF_MODE_RESIDENT, QF_MODE_STREAMING, QF_LEFT, QF_RIGHT,
     QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC, QfError, QfOptions, QfStats, load,
 )
-from .build import build as build_library, lib_path  # noqa: F401
+from .hipbuild import build as build_library, lib_path  # noqa: F401
+
+_API = ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "cost", "instantiate",
+        "default_options", "workspace_size", "Result")
 
 
 def __getattr__(name):
-    # torch-facing wrappers are imported on first use so that `import
-    # paper_2306_08152_amd` stays cheap on machines without a GPU.
-    from . import api
-    if hasattr(api, name):
-        return getattr(api, name)
+    # torch-facing wrappers are imported on first use so that importing the
+    # package stays cheap on machines without a GPU.
+    if name in _API:
+        return getattr(importlib.import_module(__name__ + ".api"), name)
     raise AttributeError(name)

@@ -5,7 +5,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-from .build import lib_path
+from .hipbuild import lib_path
 
 QF_OK, QF_EINVAL, QF_EUNSUPPORTED, QF_EHIP, QF_EWORKSPACE, QF_ENUMERIC, QF_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 QF_C128, QF_C64 = 0, 1
@@ -49,6 +49,12 @@ class QfStats(ctypes.Structure):
         ("elapsed_ms", ctypes.c_double),
         ("cost_history", ctypes.POINTER(ctypes.c_double)),
         ("cost_history_rows", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("pass_launches", ctypes.c_int32),
+        ("env_launches", ctypes.c_int32),
+        ("pass_ms", ctypes.c_double),
+        ("env_ms", ctypes.c_double),
+        ("sweep_ms", ctypes.c_double),
     ]
 
 
@@ -87,7 +93,7 @@ def load(path: str | None = None):
         return _lib
     p = path or lib_path()
     if not os.path.exists(p):
-        raise RuntimeError(f"HIP library not built: {p} is missing (run paper_2306_08152_amd.build.build())")
+        raise RuntimeError(f"HIP library not built: {p} is missing (run paper_2306_08152_amd.hipbuild.build())")
     lib = ctypes.CDLL(p)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -166,6 +166,7 @@ class Result:
     mode_used: int
     elapsed_ms: float
     history: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+    timing: dict = field(default_factory=dict)
 
 
 def workspace_size(n: int, p: int, S: int, opt: nat.QfOptions) -> int:
@@ -174,7 +175,7 @@ def workspace_size(n: int, p: int, S: int, opt: nat.QfOptions) -> int:
 
 def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float = 1e-10,
                 options: nat.QfOptions | None = None, history_rows: int = 0,
-                workspace: torch.Tensor | None = None, **kw) -> Result:
+                workspace: torch.Tensor | None = None, timing: bool = False, **kw) -> Result:
     """QFactor multistart instantiation (qf_instantiate)."""
     opt = options if options is not None else default_options()
     for k, v in kw.items():
@@ -188,7 +189,8 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
     lib = nat.load()
     need = int(lib.qf_workspace_size(n, p, S, ctypes.byref(opt)))
     if need == 0:
-        raise ValueError("invalid problem size or options")
+        # invalid sizes or options: let the library reject them with its message
+        need = 1
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
     out = torch.empty((p, 4, 4), dtype=torch.complex128, device=target.device)
@@ -200,6 +202,7 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
         hist = np.full((history_rows, S), np.nan, dtype=np.float64)
         st.cost_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         st.cost_history_rows = history_rows
+    st.timing = 1 if timing else 0
     ctx = _ctx(target.device)
     rc = lib.qf_instantiate(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
                             ctypes.byref(opt), _ptr(workspace), need, _ptr(out), _ptr(out_all), costs,
@@ -207,5 +210,7 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
     if rc not in (nat.QF_OK, nat.QF_ENUMERIC):
         nat.check(rc, ctx)
     h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
+    tm = dict(pass_ms=st.pass_ms, pass_launches=st.pass_launches, env_ms=st.env_ms,
+              env_launches=st.env_launches, sweep_ms=st.sweep_ms) if timing else {}
     return Result(out, out_all, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.n_resets,
-                  st.n_rechecks, st.mode_used, st.elapsed_ms, h)
+                  st.n_rechecks, st.mode_used, st.elapsed_ms, h, tm)

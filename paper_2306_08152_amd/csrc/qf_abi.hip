@@ -211,6 +211,62 @@ int read_costs(qf_ctx* ctx, const double* dev, int S, std::vector<double>& out) 
   return QF_OK;
 }
 
+// Optional per-kernel timing of the streaming sweeps with HIP events on the
+// context stream (pairs recorded around each launch, summed after the
+// per-sweep synchronisation).
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs
+  std::vector<int> kind;       // 0 = pass, 1 = env
+  size_t used = 0;
+  double pass_ms = 0, env_ms = 0, sweep_ms = 0;
+  int pass_n = 0, env_n = 0;
+  hipEvent_t s0 = nullptr, s1 = nullptr;
+  ~KernelTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (s0) (void)hipEventDestroy(s0);
+    if (s1) (void)hipEventDestroy(s1);
+  }
+  hipError_t init(size_t pairs) {
+    on = true;
+    ev.resize(2 * pairs, nullptr);
+    kind.resize(pairs, 0);
+    for (auto& e : ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+    hipError_t r = hipEventCreate(&s0);
+    if (r != hipSuccess) return r;
+    return hipEventCreate(&s1);
+  }
+  hipError_t begin(hipStream_t st, int k) {
+    if (!on || used >= kind.size()) return hipSuccess;
+    kind[used] = k;
+    return hipEventRecord(ev[2 * used], st);
+  }
+  hipError_t end(hipStream_t st) {
+    if (!on || used >= kind.size()) return hipSuccess;
+    return hipEventRecord(ev[2 * used++ + 1], st);
+  }
+  // after a stream synchronisation: fold the recorded pairs into the sums
+  hipError_t collect() {
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0.f;
+      hipError_t r = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+      if (r != hipSuccess) return r;
+      if (kind[i] == 0) {
+        pass_ms += ms;
+        ++pass_n;
+      } else {
+        env_ms += ms;
+        ++env_n;
+      }
+    }
+    used = 0;
+    return hipSuccess;
+  }
+};
+
 struct RunOut {
   int32_t sweeps = 0, decision = kContinue, resets = 0, rechecks = 0;
   std::vector<double> final_costs;
@@ -233,8 +289,8 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   const int64_t gstride = (int64_t)p * 16;
   const size_t N = (size_t)1 << n;
 
-  QF_HIP(ctx, hipMemsetAsync(ws + L.counters, 0, (size_t)S * 4, st));
-  QF_HIP(ctx, hipMemsetAsync(frozen, 0, (size_t)S * 4, st));
+  QF_HIP(ctx, launch_fill_i32(st, reinterpret_cast<int32_t*>(ws + L.counters), 0, (uint32_t)S));
+  QF_HIP(ctx, launch_fill_i32(st, frozen, 0, (uint32_t)S));
 
   std::vector<PassGeom> geo(p);
   for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_max_tcols(prec));
@@ -252,18 +308,25 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   ea.partials = reinterpret_cast<double*>(ws + L.partials);
   ea.counters = reinterpret_cast<int32_t*>(ws + L.counters);
 
+  KernelTimer timer;
+  if (stats && stats->timing) QF_HIP(ctx, timer.init((size_t)4 * p));
+
   auto update = [&](int g, int half) -> int {
     ea.q0 = locs[2 * g];
     ea.q1 = locs[2 * g + 1];
     ea.half = half;
     ea.gidx = g;
+    QF_HIP(ctx, timer.begin(st, 1));
     QF_HIP(ctx, launch_env(st, prec, X, ea));
+    QF_HIP(ctx, timer.end(st));
     Operand gnew{gates + 2 * 16 * (int64_t)g, gstride, 0};
     Operand gold{uold, 16, 1};
+    QF_HIP(ctx, timer.begin(st, 0));
     if (half == 0)
       QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gold, gnew));
     else
       QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gnew, gold));
+    QF_HIP(ctx, timer.end(st));
     return QF_OK;
   };
   // FP64 costs of the current gates from a fresh complex128 builder (into
@@ -326,6 +389,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
 
   int32_t i = 0;
   int32_t decision = o.max_iter <= 0 ? kStopMaxIter : kContinue;
+  if (timer.on) QF_HIP(ctx, hipEventRecord(timer.s0, st));
   while (decision == kContinue) {
     ++i;
     for (int g = p - 1; g >= 0; --g)
@@ -338,6 +402,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     }
     QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
     if ((rc = read_costs(ctx, costs, S, c))) return rc;
+    if (timer.on) QF_HIP(ctx, timer.collect());
     if (prec == QF_C64) {
       bool need = false;
       for (int s = 0; s < S; ++s) need = need || (!(out.flags[s] & kFlagNumeric) && c[s] < o.recheck_below);
@@ -366,6 +431,17 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     record(i, c);
     if ((rc = sync_frozen())) return rc;
     decision = job_decision(o, i, out.flags.data(), S);
+  }
+  if (timer.on) {
+    QF_HIP(ctx, hipEventRecord(timer.s1, st));
+    QF_HIP(ctx, hipEventSynchronize(timer.s1));
+    float ms = 0.f;
+    QF_HIP(ctx, hipEventElapsedTime(&ms, timer.s0, timer.s1));
+    stats->pass_ms = timer.pass_ms;
+    stats->env_ms = timer.env_ms;
+    stats->pass_launches = timer.pass_n;
+    stats->env_launches = timer.env_n;
+    stats->sweep_ms = ms;
   }
   out.sweeps = i;
   out.decision = decision;
@@ -398,8 +474,8 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
   a.out_info = reinterpret_cast<int32_t*>(ws + L.info);
   a.history_out = history_rows > 0 ? reinterpret_cast<double*>(ws + L.histo) : nullptr;
   a.history_rows = history_rows;
-  QF_HIP(ctx, hipMemsetAsync(ws + L.sync, 0, 64, st));
-  QF_HIP(ctx, hipMemsetAsync(ws + L.info, 0, 64, st));
+  QF_HIP(ctx, launch_fill_i32(st, a.sync, 0, 16));
+  QF_HIP(ctx, launch_fill_i32(st, a.out_info, 0, 16));
   int ok = 0;
   QF_HIP(ctx, launch_resident(st, a, &ok));
   if (!ok) return fail(ctx, QF_EUNSUPPORTED, "resident mode: %d starts do not fit on the device at once", S);
@@ -566,6 +642,8 @@ int qf_environment(qf_ctx* ctx, int n, int n_builders, const void* builder, int 
   ea.env_out = reinterpret_cast<double*>(env_out);
   ea.partials = reinterpret_cast<double*>(ctx->scratch);
   ea.counters = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(ctx->scratch) + part);
+  // the scratch layout depends on (n, n_builders): clear the arrival counters
+  QF_HIP(ctx, launch_fill_i32(ctx->stream, ea.counters, 0, (uint32_t)n_builders));
   QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
   return QF_OK;
 }
@@ -613,6 +691,7 @@ int qf_update_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precis
   ea.env_out = reinterpret_cast<double*>(env_out);
   ea.partials = reinterpret_cast<double*>(sc);
   ea.counters = reinterpret_cast<int32_t*>(sc + part);
+  QF_HIP(ctx, launch_fill_i32(ctx->stream, ea.counters, 0, (uint32_t)n_builders));
   QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
   const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_max_tcols(precision));
   Operand gnew{reinterpret_cast<const double*>(gates), 16, 0};
@@ -670,6 +749,10 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
   QF_HIP(ctx, hipMemcpyAsync(ws + L.gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
   QF_HIP(ctx, hipMemcpyAsync(ws + L.locs, locations, (size_t)n_gates * 8, hipMemcpyHostToDevice, st));
 
+  if (stats) {
+    stats->pass_launches = stats->env_launches = 0;
+    stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
+  }
   RunOut out;
   if (mode == QF_MODE_RESIDENT)
     rc = run_resident(ctx, n, target, n_gates, n_starts, tol, o, ws, L, stats, rows, out);

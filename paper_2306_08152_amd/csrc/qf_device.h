@@ -78,11 +78,11 @@ __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 // Y = Yacc.  Plain single-thread FP64; `m` is overwritten.
 // Returns the number of Jacobi sweeps used (0 for the zero/NaN guards).
 __device__ inline int nearest_unitary_f64(cd m[16], const cd uold[16], cd unew[16]) {
-  double fro = 0.0;
+  double amax = 0.0;  // largest |component|, free of under/overflow
   bool ok = true;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    fro += norm2(m[e]);
+    amax = fmax(amax, fmax(fabs(m[e].re), fabs(m[e].im)));
     ok = ok && finite_d(m[e].re) && finite_d(m[e].im);
   }
   if (!ok) {
@@ -91,10 +91,17 @@ __device__ inline int nearest_unitary_f64(cd m[16], const cd uold[16], cd unew[1
     for (int e = 0; e < 16; ++e) unew[e] = mk(nan, nan);
     return 0;
   }
-  if (!(fro > 1e-300)) {  // zero environment: keep the gate
+  if (!(amax >= 1e-300)) {  // zero environment: keep the gate
 #pragma unroll
     for (int e = 0; e < 16; ++e) unew[e] = uold[e];
     return 0;
+  }
+  // The maximiser does not change under a positive scaling of M; normalise
+  // so that the squared column norms below neither underflow nor overflow.
+  {
+    const double inv = 1.0 / amax;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) m[e] = scale(m[e], inv);
   }
   cd y[16];
 #pragma unroll

@@ -63,6 +63,9 @@ struct EnvArgs {
   int32_t* counters;      // S ints, zero before the first launch; left zero
 };
 uint32_t env_workgroups(int n);
+// Small fill kernel (used instead of hipMemsetAsync so the enqueued work can
+// be captured in a HIP graph).
+hipError_t launch_fill_i32(hipStream_t st, int32_t* p, int32_t v, uint32_t count);
 int pass_max_tcols(int precision);
 hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a);
 

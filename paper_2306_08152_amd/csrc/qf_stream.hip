@@ -424,6 +424,17 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
   return hipGetLastError();
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_i32(hipStream_t st, int32_t* p, int32_t v, uint32_t count) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ k_cost
 
 template <typename R>

@@ -1,6 +1,6 @@
 """Build the HIP library (gfx950) in-tree: paper_2306_08152_amd/lib/libqfactor_mi355x.so.
 
-Usage: python -m paper_2306_08152_amd.build  (or call build()).
+Usage: python -m paper_2306_08152_amd.hipbuild  (or call build()).
 """
 from __future__ import annotations
 

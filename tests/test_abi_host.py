@@ -94,3 +94,13 @@ def test_null_context_is_rejected_before_device_work(lib):
     ctx = ctypes.c_void_p()
     assert lib.qf_create(None, 0, None) == nat.QF_EINVAL
     assert lib.qf_create(ctypes.byref(ctx), -1, None) == nat.QF_EINVAL
+
+
+def test_package_api_resolves_to_functions():
+    for name in ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "cost",
+                 "instantiate", "default_options", "workspace_size"):
+        assert callable(getattr(pkg, name)), name
+    from paper_2306_08152_amd import api
+    assert pkg.build is api.build and pkg.instantiate is api.instantiate
+    opt = pkg.default_options(precision=1, max_iter=7)
+    assert opt.precision == 1 and opt.max_iter == 7 and opt.reset_iter == 40
