@@ -122,7 +122,10 @@ typedef struct {
                             initial gates) for i < cost_history_rows */
   int32_t cost_history_rows;
   int32_t timing;        /* in: nonzero records HIP events around every
-                            kernel of the streaming sweep loop */
+                            kernel of the streaming sweep loop; the starts
+                            then run as one group (no overlap of two
+                            groups' kernels), so each duration is the
+                            kernel's own */
   int32_t pass_launches; /* out (timing): fused builder passes in the sweeps */
   int32_t env_launches;  /* out (timing): environment + SVD-step launches */
   double pass_ms;        /* out (timing): summed durations of those passes */

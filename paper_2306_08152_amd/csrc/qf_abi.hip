@@ -20,6 +20,10 @@
 struct qf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // Two streams of the context (default priority) that run the sweeps of
+  // two halves of the starts concurrently, joined to `stream` by events.
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
   double* pinned = nullptr;     // host read-back buffer
   size_t pinned_count = 0;      // doubles
   void* scratch = nullptr;      // device scratch for the stand-alone calls
@@ -160,6 +164,16 @@ int ensure_pinned(qf_ctx* ctx, size_t count) {
   return QF_OK;
 }
 
+int ensure_aux_streams(qf_ctx* ctx) {
+  if (ctx->aux[0]) return QF_OK;
+  for (int i = 0; i < 2; ++i) {
+    QF_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+    QF_HIP(ctx, hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming));
+  }
+  QF_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  return QF_OK;
+}
+
 int ensure_scratch(qf_ctx* ctx, size_t bytes) {
   if (ctx->scratch_bytes >= bytes) return QF_OK;
   QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -295,38 +309,85 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   std::vector<PassGeom> geo(p);
   for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_max_tcols(prec));
 
-  EnvArgs ea{};
-  ea.n = n;
-  ea.S = S;
-  ea.do_update = 1;
-  ea.beta = o.beta;
-  ea.gates = gates;
-  ea.gstride = gstride;
-  ea.uold = uold;
-  ea.env_out = nullptr;
-  ea.frozen = frozen;
-  ea.partials = reinterpret_cast<double*>(ws + L.partials);
-  ea.counters = reinterpret_cast<int32_t*>(ws + L.counters);
+  // The starts split into G groups whose sweeps run on separate streams:
+  // while one group's latency-bound environment + SVD step runs, the other
+  // group's pass keeps HBM busy.  Groups share nothing but the join.
+  // (Per-kernel timing runs the starts as one group so that every measured
+  // kernel duration is the kernel's own, not shared with a concurrent one.)
+  const int G = (S >= 2 && !(stats && stats->timing)) ? 2 : 1;
+  if (G > 1) {
+    int rc0 = ensure_aux_streams(ctx);
+    if (rc0) return rc0;
+  }
+  struct Group {
+    int s0 = 0, ns = 0;
+    hipStream_t st = nullptr;
+    void* X = nullptr;
+    EnvArgs ea{};
+  };
+  Group grp[2];
+  const uint32_t nwg = env_workgroups(n);
+  for (int gi = 0; gi < G; ++gi) {
+    Group& q = grp[gi];
+    q.s0 = gi * S / G;
+    q.ns = (gi + 1) * S / G - q.s0;
+    q.st = G > 1 ? ctx->aux[gi] : st;
+    q.X = reinterpret_cast<unsigned char*>(X) + (size_t)q.s0 * N * N * elem_bytes(prec);
+    EnvArgs& ea = q.ea;
+    ea.n = n;
+    ea.S = q.ns;
+    ea.do_update = 1;
+    ea.beta = o.beta;
+    ea.gates = gates + (size_t)q.s0 * gstride * 2;
+    ea.gstride = gstride;
+    ea.uold = uold + (size_t)q.s0 * 32;
+    ea.env_out = nullptr;
+    ea.frozen = frozen + q.s0;
+    ea.partials = reinterpret_cast<double*>(ws + L.partials) + (size_t)q.s0 * nwg * 32;
+    ea.counters = reinterpret_cast<int32_t*>(ws + L.counters) + q.s0;
+  }
 
   KernelTimer timer;
-  if (stats && stats->timing) QF_HIP(ctx, timer.init((size_t)4 * p));
+  if (stats && stats->timing) QF_HIP(ctx, timer.init((size_t)4 * p * G));
 
-  auto update = [&](int g, int half) -> int {
+  auto update = [&](Group& q, int g, int half) -> int {
+    EnvArgs& ea = q.ea;
     ea.q0 = locs[2 * g];
     ea.q1 = locs[2 * g + 1];
     ea.half = half;
     ea.gidx = g;
-    QF_HIP(ctx, timer.begin(st, 1));
-    QF_HIP(ctx, launch_env(st, prec, X, ea));
-    QF_HIP(ctx, timer.end(st));
-    Operand gnew{gates + 2 * 16 * (int64_t)g, gstride, 0};
-    Operand gold{uold, 16, 1};
-    QF_HIP(ctx, timer.begin(st, 0));
+    QF_HIP(ctx, timer.begin(q.st, 1));
+    QF_HIP(ctx, launch_env(q.st, prec, q.X, ea));
+    QF_HIP(ctx, timer.end(q.st));
+    Operand gnew{ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
+    Operand gold{ea.uold, 16, 1};
+    QF_HIP(ctx, timer.begin(q.st, 0));
     if (half == 0)
-      QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gold, gnew));
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gold, gnew));
     else
-      QF_HIP(ctx, launch_pass(st, prec, X, S, geo[g], gnew, gold));
-    QF_HIP(ctx, timer.end(st));
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gnew, gold));
+    QF_HIP(ctx, timer.end(q.st));
+    return QF_OK;
+  };
+  // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved.
+  auto sweep = [&]() -> int {
+    if (G > 1) {
+      QF_HIP(ctx, hipEventRecord(ctx->fork, st));
+      for (int gi = 0; gi < G; ++gi) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->fork, 0));
+    }
+    int rc1;
+    for (int g = p - 1; g >= 0; --g)
+      for (int gi = 0; gi < G; ++gi)
+        if ((rc1 = update(grp[gi], g, 0))) return rc1;
+    for (int g = 0; g < p; ++g)
+      for (int gi = 0; gi < G; ++gi)
+        if ((rc1 = update(grp[gi], g, 1))) return rc1;
+    if (G > 1) {
+      for (int gi = 0; gi < G; ++gi) {
+        QF_HIP(ctx, hipEventRecord(ctx->join[gi], grp[gi].st));
+        QF_HIP(ctx, hipStreamWaitEvent(st, ctx->join[gi], 0));
+      }
+    }
     return QF_OK;
   };
   // FP64 costs of the current gates from a fresh complex128 builder (into
@@ -392,10 +453,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   if (timer.on) QF_HIP(ctx, hipEventRecord(timer.s0, st));
   while (decision == kContinue) {
     ++i;
-    for (int g = p - 1; g >= 0; --g)
-      if ((rc = update(g, 0))) return rc;
-    for (int g = 0; g < p; ++g)
-      if ((rc = update(g, 1))) return rc;
+    if ((rc = sweep())) return rc;
     if (o.reset_iter > 0 && i % o.reset_iter == 0) {
       if ((rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, prec, X))) return rc;
       ++out.resets;
@@ -566,6 +624,14 @@ int qf_destroy(qf_ctx* ctx) {
   {
     DeviceGuard dg(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < 2; ++i) {
+      if (ctx->aux[i]) {
+        (void)hipStreamSynchronize(ctx->aux[i]);
+        (void)hipStreamDestroy(ctx->aux[i]);
+      }
+      if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
   }

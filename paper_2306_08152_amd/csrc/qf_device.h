@@ -171,25 +171,38 @@ __device__ inline int nearest_unitary_f64(cd m[16], const cd uold[16], cd unew[1
     // other columns completes X (that direction does not change Re Tr(M u)).
     // Gram-Schmidt of e_0..e_3 against the accepted columns; with at most
     // three accepted orthonormal columns some e_k keeps a residual >= 1/4.
+    // (Fully unrolled, flag-driven: every array index is a constant.)
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (accepted[j]) continue;
-      for (int k = 0; k < 4; ++k) {
-        cd v[4];
-        for (int r = 0; r < 4; ++r) v[r] = mk(r == k ? 1.0 : 0.0, 0.0);
-        for (int jj = 0; jj < 4; ++jj) {
-          if (!accepted[jj]) continue;
-          cd d = mk(0.0, 0.0);
-          for (int r = 0; r < 4; ++r) cmac_cj(d, m[4 * r + jj], v[r]);
-          for (int r = 0; r < 4; ++r) v[r] = v[r] - m[4 * r + jj] * d;
+      if (!accepted[j]) {
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cd v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = mk(r == k ? 1.0 : 0.0, 0.0);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            if (accepted[jj]) {
+              cd d = mk(0.0, 0.0);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) cmac_cj(d, m[4 * r + jj], v[r]);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) v[r] = v[r] - m[4 * r + jj] * d;
+            }
+          }
+          double nv = 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) nv += norm2(v[r]);
+          const bool take = !found && nv >= 0.25;
+          if (take) {
+            const double inv = 1.0 / sqrt(nv);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) m[4 * r + j] = scale(v[r], inv);
+          }
+          found = found || take;
         }
-        double nv = 0.0;
-        for (int r = 0; r < 4; ++r) nv += norm2(v[r]);
-        if (nv >= 0.25) {
-          const double inv = 1.0 / sqrt(nv);
-          for (int r = 0; r < 4; ++r) m[4 * r + j] = scale(v[r], inv);
-          accepted[j] = true;
-          break;
-        }
+        accepted[j] = true;
       }
     }
   }

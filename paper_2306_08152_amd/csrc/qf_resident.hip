@@ -248,13 +248,17 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
       lds_ptrace<R>(L.X, n, b0, b1, L.red);
       if (t == 0) {
         cd uold[16], e[16], unew[16], P[16];
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
           uold[k] = gates[16 * g + k];
           P[k] = L.red[k];
         }
+#pragma unroll
         for (int r = 0; r < 4; ++r)
+#pragma unroll
           for (int c = 0; c < 4; ++c) {
             cd acc = mk(0.0, 0.0);
+#pragma unroll
             for (int k = 0; k < 4; ++k) {
               if (half == 0)
                 cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
@@ -264,13 +268,17 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
             e[4 * r + c] = acc;
           }
         if (frozen) {
+#pragma unroll
           for (int k = 0; k < 16; ++k) unew[k] = uold[k];
         } else {
           optimize_gate_f64(e, uold, o.beta, unew);
         }
+#pragma unroll
         for (int k = 0; k < 16; ++k) gates[16 * g + k] = unew[k];
         // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored
+#pragma unroll
         for (int r = 0; r < 4; ++r)
+#pragma unroll
           for (int c = 0; c < 4; ++c) {
             const cd ud = conj(uold[4 * c + r]);
             const cd un = unew[4 * r + c];

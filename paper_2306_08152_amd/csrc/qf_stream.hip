@@ -295,18 +295,23 @@ __device__ inline void env_finish(const EnvDev& d, uint32_t s, const cd* P) {
   if (!a.do_update) {
     if (a.env_out) {
       cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
+#pragma unroll
       for (int e = 0; e < 16; ++e) eo[e] = P[e];
     }
     return;
   }
   cd* gp = reinterpret_cast<cd*>(a.gates) + (int64_t)s * a.gstride + 16 * (int64_t)a.gidx;
   cd uold[16], e[16], unew[16];
+#pragma unroll
   for (int k = 0; k < 16; ++k) uold[k] = gp[k];
   // E = u_old^dagger P (half 0) or P u_old^dagger (half 1): the removal of the
   // old gate commutes with the partial trace.
+#pragma unroll
   for (int r = 0; r < 4; ++r)
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       cd acc = mk(0.0, 0.0);
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (a.half == 0)
           cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
@@ -317,14 +322,17 @@ __device__ inline void env_finish(const EnvDev& d, uint32_t s, const cd* P) {
     }
   if (a.env_out) {
     cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
-    for (int k = 0; k < 16; ++k) eo[k] = e[k];
+  #pragma unroll
+  for (int k = 0; k < 16; ++k) eo[k] = e[k];
   }
   if (a.frozen && a.frozen[s]) {
-    for (int k = 0; k < 16; ++k) unew[k] = uold[k];
+  #pragma unroll
+  for (int k = 0; k < 16; ++k) unew[k] = uold[k];
   } else {
     optimize_gate_f64(e, uold, a.beta, unew);
   }
   cd* uo = reinterpret_cast<cd*>(a.uold) + 16 * (size_t)s;
+#pragma unroll
   for (int k = 0; k < 16; ++k) {
     uo[k] = uold[k];
     gp[k] = unew[k];
@@ -490,11 +498,13 @@ __global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= count) return;
   cd e[16], u[16], un[16];
+#pragma unroll
   for (int k = 0; k < 16; ++k) {
     e[k] = env[16 * s + k];
     u[k] = uold[16 * s + k];
   }
   optimize_gate_f64(e, u, beta, un);
+#pragma unroll
   for (int k = 0; k < 16; ++k) unew[16 * s + k] = un[k];
 }
 
