@@ -78,8 +78,8 @@ typedef enum {
 /* Hyperparameters of Sec. III-A-2.  qf_options_default() sets the values the
  * paper recommends: dist_tol 1e-10, diff_tol_a 0, diff_tol_r 1e-5,
  * long_diff_count 100, long_diff_r 0.1, min_iter 0, max_iter 1e5,
- * reset_iter 40, beta 0; plus precision QF_C128, mode QF_MODE_AUTO and
- * recheck_below 1e-6.
+ * reset_iter 40, beta 0; plus precision QF_C128, mode QF_MODE_AUTO,
+ * recheck_below 1e-6 and stream_groups 0 (automatic).
  * Readings of the garbled tests (c_i = cost after sweep i, c_0 = initial):
  *   short plateau: c_{i-1} - c_i <= diff_tol_a + diff_tol_r * c_i
  *                  (off when both are 0);
@@ -105,6 +105,11 @@ typedef struct {
   int32_t precision;  /* qf_precision */
   int32_t mode;       /* qf_mode */
   double recheck_below;
+  int32_t stream_groups; /* streaming mode: starts are split into this many
+                            groups whose sweeps run on separate streams,
+                            staggered so one group's environment + SVD step
+                            runs under another's pass (0 = automatic; at most
+                            4 and at most n_starts) */
 } qf_options;
 
 /* Outcome of qf_instantiate (host memory). */

@@ -34,6 +34,7 @@ class QfOptions(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("mode", ctypes.c_int32),
         ("recheck_below", ctypes.c_double),
+        ("stream_groups", ctypes.c_int32),
     ]
 
 

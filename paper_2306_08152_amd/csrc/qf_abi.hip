@@ -17,13 +17,15 @@
 #include "qf_termination.h"
 #include "qfactor.h"
 
+constexpr int kMaxGroups = 4;
+
 struct qf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  // Two streams of the context (default priority) that run the sweeps of
-  // two halves of the starts concurrently, joined to `stream` by events.
-  hipStream_t aux[2] = {nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+  // Streams of the context (default priority) that run the sweeps of groups
+  // of starts concurrently, forked from and joined to `stream` by events.
+  hipStream_t aux[kMaxGroups] = {};
+  hipEvent_t fork = nullptr, join[kMaxGroups] = {}, stagger[kMaxGroups] = {};
   double* pinned = nullptr;     // host read-back buffer
   size_t pinned_count = 0;      // doubles
   void* scratch = nullptr;      // device scratch for the stand-alone calls
@@ -140,6 +142,7 @@ int validate_options(qf_ctx* ctx, const qf_options& o) {
   if (o.precision != QF_C128 && o.precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision %d", o.precision);
   if (o.mode < QF_MODE_AUTO || o.mode > QF_MODE_STREAMING) return fail(ctx, QF_EINVAL, "unknown mode %d", o.mode);
   if (!(o.recheck_below >= 0) || !std::isfinite(o.recheck_below)) return fail(ctx, QF_EINVAL, "recheck_below must be >= 0");
+  if (o.stream_groups < 0 || o.stream_groups > kMaxGroups) return fail(ctx, QF_EINVAL, "stream_groups must be in [0, 4]");
   return QF_OK;
 }
 
@@ -166,13 +169,15 @@ int ensure_pinned(qf_ctx* ctx, size_t count) {
 
 int ensure_aux_streams(qf_ctx* ctx) {
   if (ctx->aux[0]) return QF_OK;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kMaxGroups; ++i) {
     QF_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
     QF_HIP(ctx, hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming));
+    QF_HIP(ctx, hipEventCreateWithFlags(&ctx->stagger[i], hipEventDisableTiming));
   }
   QF_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
   return QF_OK;
 }
+
 
 int ensure_scratch(qf_ctx* ctx, size_t bytes) {
   if (ctx->scratch_bytes >= bytes) return QF_OK;
@@ -314,7 +319,9 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   // group's pass keeps HBM busy.  Groups share nothing but the join.
   // (Per-kernel timing runs the starts as one group so that every measured
   // kernel duration is the kernel's own, not shared with a concurrent one.)
-  const int G = (S >= 2 && !(stats && stats->timing)) ? 2 : 1;
+  int G = o.stream_groups > 0 ? o.stream_groups : 2;
+  G = std::min(std::min(G, kMaxGroups), S);
+  if (stats && stats->timing) G = 1;
   if (G > 1) {
     int rc0 = ensure_aux_streams(ctx);
     if (rc0) return rc0;
@@ -325,7 +332,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     void* X = nullptr;
     EnvArgs ea{};
   };
-  Group grp[2];
+  Group grp[kMaxGroups];
   const uint32_t nwg = env_workgroups(n);
   for (int gi = 0; gi < G; ++gi) {
     Group& q = grp[gi];
@@ -350,7 +357,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   KernelTimer timer;
   if (stats && stats->timing) QF_HIP(ctx, timer.init((size_t)4 * p * G));
 
-  auto update = [&](Group& q, int g, int half) -> int {
+  auto update = [&](Group& q, int g, int half, hipEvent_t after_env) -> int {
     EnvArgs& ea = q.ea;
     ea.q0 = locs[2 * g];
     ea.q1 = locs[2 * g + 1];
@@ -359,6 +366,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     QF_HIP(ctx, timer.begin(q.st, 1));
     QF_HIP(ctx, launch_env(q.st, prec, q.X, ea));
     QF_HIP(ctx, timer.end(q.st));
+    if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
     Operand gnew{ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
     Operand gold{ea.uold, 16, 1};
     QF_HIP(ctx, timer.begin(q.st, 0));
@@ -369,27 +377,35 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     QF_HIP(ctx, timer.end(q.st));
     return QF_OK;
   };
-  // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved.
-  auto sweep = [&]() -> int {
+  // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved,
+  // forked from and joined back to stream `home`.
+  auto sweep_on = [&](hipStream_t home) -> int {
     if (G > 1) {
-      QF_HIP(ctx, hipEventRecord(ctx->fork, st));
+      QF_HIP(ctx, hipEventRecord(ctx->fork, home));
       for (int gi = 0; gi < G; ++gi) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->fork, 0));
     }
+    // Stagger: group k starts once group k-1's first environment + SVD step
+    // is done, so the groups' latency-bound steps fall under each other's
+    // passes instead of running in lockstep.
     int rc1;
     for (int g = p - 1; g >= 0; --g)
-      for (int gi = 0; gi < G; ++gi)
-        if ((rc1 = update(grp[gi], g, 0))) return rc1;
+      for (int gi = 0; gi < G; ++gi) {
+        const bool first = (g == p - 1);
+        if (first && gi > 0) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->stagger[gi - 1], 0));
+        if ((rc1 = update(grp[gi], g, 0, (first && gi + 1 < G) ? ctx->stagger[gi] : nullptr))) return rc1;
+      }
     for (int g = 0; g < p; ++g)
       for (int gi = 0; gi < G; ++gi)
-        if ((rc1 = update(grp[gi], g, 1))) return rc1;
+        if ((rc1 = update(grp[gi], g, 1, nullptr))) return rc1;
     if (G > 1) {
       for (int gi = 0; gi < G; ++gi) {
         QF_HIP(ctx, hipEventRecord(ctx->join[gi], grp[gi].st));
-        QF_HIP(ctx, hipStreamWaitEvent(st, ctx->join[gi], 0));
+        QF_HIP(ctx, hipStreamWaitEvent(home, ctx->join[gi], 0));
       }
     }
     return QF_OK;
   };
+  auto sweep = [&]() -> int { return sweep_on(st); };
   // FP64 costs of the current gates from a fresh complex128 builder (into
   // R for complex64, into X itself for complex128).
   auto fp64_costs = [&](std::vector<double>& c) -> int {
@@ -599,6 +615,7 @@ void qf_options_default(qf_options* o) {
   o->precision = QF_C128;
   o->mode = QF_MODE_AUTO;
   o->recheck_below = 1e-6;
+  o->stream_groups = 0;
 }
 
 int qf_create(qf_ctx** out, int device, void* hip_stream) {
@@ -624,12 +641,13 @@ int qf_destroy(qf_ctx* ctx) {
   {
     DeviceGuard dg(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kMaxGroups; ++i) {
       if (ctx->aux[i]) {
         (void)hipStreamSynchronize(ctx->aux[i]);
         (void)hipStreamDestroy(ctx->aux[i]);
       }
       if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+      if (ctx->stagger[i]) (void)hipEventDestroy(ctx->stagger[i]);
     }
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);

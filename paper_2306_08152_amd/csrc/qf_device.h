@@ -50,6 +50,14 @@ __host__ __device__ __forceinline__ void cmac_cj(cx<R>& acc, cx<R> a, cx<R> b) {
 using cd = cx<double>;
 using cf = cx<float>;
 
+// c ? a : b for complex values, component-wise.  (A conditional operator on
+// the struct itself is lowered to a select of addresses plus a copy, which
+// sends both operands to scratch memory.)
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> sel(bool c, cx<R> a, cx<R> b) {
+  return cx<R>{c ? a.re : b.re, c ? a.im : b.im};
+}
+
 // ---------------------------------------------------------------- qubit bits
 
 // Insert a zero bit at position p of v (bits >= p move up by one).
@@ -70,168 +78,270 @@ __host__ __device__ __forceinline__ uint32_t local_off(uint32_t i, uint32_t b0, 
 
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
-// Nearest unitary to an environment (Sec. III-A-1): with M = X D Y^dagger,
-// the maximiser of Re Tr(M u) over unitary u is u = Y X^dagger.  The SVD is a
-// one-sided (Hestenes) Jacobi iteration on the columns of M: complex Jacobi
-// rotations J accumulate in Yacc until the columns of M Yacc are mutually
-// orthogonal, so M Yacc = X D with X's columns the normalised results and
-// Y = Yacc.  Plain single-thread FP64; `m` is overwritten.
-// Returns the number of Jacobi sweeps used (0 for the zero/NaN guards).
-__device__ inline int nearest_unitary_f64(cd m[16], const cd uold[16], cd unew[16]) {
-  double amax = 0.0;  // largest |component|, free of under/overflow
-  bool ok = true;
+// FP64 reciprocal and reciprocal square root for the SVD step's rotations:
+// the hardware estimate refined by two Newton steps, y <- y (2 - x y) and
+// y <- y (3 - x y^2) / 2, each FMA-based; about 1 ulp for normal arguments
+// (the arguments here are column norms of a matrix scaled to entries <= 1).
+// Far shorter dependent chains than IEEE division and square root.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Entry (k, r) of a 4x4 row-major array for a runtime r, by a select chain
+// (keeps the array in registers).
+__device__ __forceinline__ cd at_kr(const cd u[16], int k, int r) {
+  cd v = u[4 * k];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    amax = fmax(amax, fmax(fabs(m[e].re), fabs(m[e].im)));
-    ok = ok && finite_d(m[e].re) && finite_d(m[e].im);
+  for (int rr = 1; rr < 4; ++rr) v = sel(r == rr, u[4 * k + rr], v);
+  return v;
+}
+
+// Entry (r, k) of a 4x4 row-major array for a runtime row r.
+__device__ __forceinline__ cd at_rk(const cd u[16], int r, int k) {
+  cd v = u[k];
+#pragma unroll
+  for (int rr = 1; rr < 4; ++rr) v = sel(r == rr, u[4 * rr + k], v);
+  return v;
+}
+
+// ---------------------------------------------------------------- quad form
+
+// The same nearest-unitary step spread over the 4 lanes of a quad (lanes
+// 4k..4k+3 of a wavefront, all active): lane r owns row r of M and of the
+// accumulated rotation Y.  A Jacobi sweep is three rounds of two disjoint
+// column pairs ((0,1),(2,3)), ((0,2),(1,3)), ((0,3),(1,2)); each lane adds its
+// row's share of the pair's column norms and inner product and a two-step
+// butterfly completes the sums, so every lane holds bitwise-identical sums
+// and takes identical rotation decisions.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 4);
+  return v + __shfl_xor(v, 2, 4);
+}
+__device__ __forceinline__ double quad_max(double v) {
+  v = fmax(v, __shfl_xor(v, 1, 4));
+  return fmax(v, __shfl_xor(v, 2, 4));
+}
+
+// Jacobi rotation of columns (p, q) given the summed norms a, b and inner
+// product g; applies to this lane's row of M and Y.  The rotation angle
+// follows the symmetric 2x2 Schur step (Golub and Van Loan): with
+// zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = c t, after the phase of g is moved onto column q.
+// Returns 1 if it rotated, 0 if the pair is orthogonal to round-off.
+__device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, double a, double b, cd g) {
+  const double tol2 = 1.6e-31;  // (4e-16)^2: |g| <= 4e-16 sqrt(a b) counts as orthogonal
+  const double g2 = norm2(g);
+  if (!(g2 > tol2 * (a * b))) return 0.0;
+  const double rg = rsqrt_nr(g2);              // 1 / |g|
+  const double zeta = 0.5 * (b - a) * rg;
+  const double az = fabs(zeta);
+  double t;
+  if (az < 1e150) {
+    const double q2 = fma(zeta, zeta, 1.0);
+    t = rcp_nr(az + q2 * rsqrt_nr(q2));        // 1 / (|zeta| + sqrt(1 + zeta^2))
+  } else {
+    t = 0.5 * rcp_nr(az);
   }
-  if (!ok) {
+  t = zeta >= 0.0 ? t : -t;
+  const double c = rsqrt_nr(fma(t, t, 1.0));
+  const double s = c * t;
+  const cd ph = mk(g.re * rg, -g.im * rg);     // e^{-i arg g}
+  const cd xp = m[p], xq = ph * m[q];
+  m[p] = scale(xp, c) - scale(xq, s);
+  m[q] = scale(xp, s) + scale(xq, c);
+  const cd yp = y[p], yq = ph * y[q];
+  y[p] = scale(yp, c) - scale(yq, s);
+  y[q] = scale(yp, s) + scale(yq, c);
+  return 1.0;
+}
+
+template <int P0, int Q0, int P1, int Q1>
+__device__ __forceinline__ double quad_round(cd m[4], cd y[4]) {
+  double v[8];
+  v[0] = norm2(m[P0]);
+  v[1] = norm2(m[Q0]);
+  const cd g0 = conj(m[P0]) * m[Q0];
+  v[2] = g0.re;
+  v[3] = g0.im;
+  v[4] = norm2(m[P1]);
+  v[5] = norm2(m[Q1]);
+  const cd g1 = conj(m[P1]) * m[Q1];
+  v[6] = g1.re;
+  v[7] = g1.im;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = quad_sum(v[k]);
+  const double r0 = quad_rotate(m, y, P0, Q0, v[0], v[1], mk(v[2], v[3]));
+  const double r1 = quad_rotate(m, y, P1, Q1, v[4], v[5], mk(v[6], v[7]));
+  return fmax(r0, r1);
+}
+
+// mrow: this lane's row r of M (overwritten); keep_row: row r of the result
+// to return for a zero M; returns row r of the maximiser of Re Tr(M u).
+// Result: 0 = computed, 1 = zero M (keep_row returned), 2 = non-finite M.
+__device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4], int r, cd unew_row[4]) {
+  double amax = 0.0, bad = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    amax = fmax(amax, fmax(fabs(mrow[j].re), fabs(mrow[j].im)));
+    bad = (finite_d(mrow[j].re) && finite_d(mrow[j].im)) ? bad : 1.0;
+  }
+  amax = quad_max(amax);
+  bad = quad_max(bad);
+  if (bad != 0.0) {
     const double nan = __builtin_nan("");
 #pragma unroll
-    for (int e = 0; e < 16; ++e) unew[e] = mk(nan, nan);
-    return 0;
+    for (int j = 0; j < 4; ++j) unew_row[j] = mk(nan, nan);
+    return 2;
   }
-  if (!(amax >= 1e-300)) {  // zero environment: keep the gate
+  if (!(amax >= 1e-300)) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) unew[e] = uold[e];
-    return 0;
+    for (int j = 0; j < 4; ++j) unew_row[j] = keep_row[j];
+    return 1;
   }
-  // The maximiser does not change under a positive scaling of M; normalise
-  // so that the squared column norms below neither underflow nor overflow.
-  {
-    const double inv = 1.0 / amax;
+  const double inv = rcp_nr(amax);  // any positive scale serves
 #pragma unroll
-    for (int e = 0; e < 16; ++e) m[e] = scale(m[e], inv);
+  for (int j = 0; j < 4; ++j) mrow[j] = scale(mrow[j], inv);
+  cd y[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) y[j] = mk(j == r ? 1.0 : 0.0, 0.0);
+  // Cyclic sweeps until a sweep finds no pair above round-off.
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double rel = quad_round<0, 1, 2, 3>(mrow, y);
+    rel = fmax(rel, quad_round<0, 2, 1, 3>(mrow, y));
+    rel = fmax(rel, quad_round<0, 3, 1, 2>(mrow, y));
+    if (!(rel > 0.0)) break;
   }
-  cd y[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) y[e] = mk((e % 5 == 0) ? 1.0 : 0.0, 0.0);
-
-  const double tol = 4.0e-16;
-  int sweep = 0;
-  for (; sweep < 30; ++sweep) {
-    bool rotated = false;
-#pragma unroll
-    for (int pair = 0; pair < 6; ++pair) {
-      const int p = (pair < 3) ? 0 : (pair < 5 ? 1 : 2);
-      const int q = (pair < 3) ? pair + 1 : (pair < 5 ? pair - 1 : 3);
-      double a = 0.0, b = 0.0;
-      cd g = mk(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a += norm2(m[4 * r + p]);
-        b += norm2(m[4 * r + q]);
-        cmac_cj(g, m[4 * r + p], m[4 * r + q]);
-      }
-      const double ag = sqrt(norm2(g));
-      if (!(ag > tol * sqrt(a * b))) continue;
-      rotated = true;
-      const double zeta = (b - a) / (2.0 * ag);
-      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double c = 1.0 / sqrt(1.0 + t * t);
-      const double s = c * t;
-      const cd ph = mk(g.re / ag, -g.im / ag);  // e^{-i arg g}
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const cd xp = m[4 * r + p], xq = ph * m[4 * r + q];
-        m[4 * r + p] = scale(xp, c) - scale(xq, s);
-        m[4 * r + q] = scale(xp, s) + scale(xq, c);
-        const cd yp = y[4 * r + p], yq = ph * y[4 * r + q];
-        y[4 * r + p] = scale(yp, c) - scale(yq, s);
-        y[4 * r + q] = scale(yp, s) + scale(yq, c);
-      }
-    }
-    if (!rotated) break;
-  }
-  // X = normalised columns of m; complete any exactly vanishing column.
-  double sig[4];
-  double smax = 0.0;
+  double sig2[4], smax2 = 0.0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    double s2 = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) s2 += norm2(m[4 * r + j]);
-    sig[j] = sqrt(s2);
-    smax = fmax(smax, sig[j]);
+    sig2[j] = quad_sum(norm2(mrow[j]));
+    smax2 = fmax(smax2, sig2[j]);
   }
-  bool accepted[4];
-  bool any_missing = false;
+  bool acc[4];
+  bool singular = false;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    accepted[j] = sig[j] > smax * 1e-290;
-    any_missing = any_missing || !accepted[j];
-    if (accepted[j]) {
-      const double inv = 1.0 / sig[j];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) m[4 * r + j] = scale(m[4 * r + j], inv);
-    }
+    acc[j] = sig2[j] > smax2 * 1e-290;  // singular value above 1e-145 of the largest
+    singular = singular || !acc[j];
   }
-  if (any_missing) {
-    // A singular value is exactly zero: any unit vector orthogonal to the
-    // other columns completes X (that direction does not change Re Tr(M u)).
-    // Gram-Schmidt of e_0..e_3 against the accepted columns; with at most
-    // three accepted orthonormal columns some e_k keeps a residual >= 1/4.
-    // (Fully unrolled, flag-driven: every array index is a constant.)
+  cd x[4];  // row r of X
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = sel(acc[j], scale(mrow[j], rsqrt_nr(acc[j] ? sig2[j] : 1.0)), mk(0.0, 0.0));
+  if (singular) {
+    // An exactly vanishing singular direction: complete X by Gram-Schmidt
+    // of e_0..e_3 against the accepted columns (any completion attains the
+    // same Re Tr(M u)); lane r holds component r of each vector.
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (!accepted[j]) {
+      if (!acc[j]) {
         bool found = false;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          cd v[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = mk(r == k ? 1.0 : 0.0, 0.0);
+          cd v = mk(r == k ? 1.0 : 0.0, 0.0);
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
-            if (accepted[jj]) {
-              cd d = mk(0.0, 0.0);
-#pragma unroll
-              for (int r = 0; r < 4; ++r) cmac_cj(d, m[4 * r + jj], v[r]);
-#pragma unroll
-              for (int r = 0; r < 4; ++r) v[r] = v[r] - m[4 * r + jj] * d;
+            if (acc[jj]) {
+              const cd pr = conj(x[jj]) * v;
+              const cd d = mk(quad_sum(pr.re), quad_sum(pr.im));
+              v = v - x[jj] * d;
             }
           }
-          double nv = 0.0;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) nv += norm2(v[r]);
+          const double nv = quad_sum(norm2(v));
           const bool take = !found && nv >= 0.25;
-          if (take) {
-            const double inv = 1.0 / sqrt(nv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) m[4 * r + j] = scale(v[r], inv);
-          }
+          if (take) x[j] = scale(v, rsqrt_nr(nv));
           found = found || take;
         }
-        accepted[j] = true;
+        acc[j] = true;
       }
     }
   }
-  // u_new = Y X^dagger
+  // u_new[r][c] = sum_j Y[r][j] conj(X[c][j]); rows of X from the quad
+  const int base = (int)(threadIdx.x & ~3u);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int c = 0; c < 4; ++c) {
+    cd acc = mk(0.0, 0.0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      cd acc = mk(0.0, 0.0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) cmac(acc, y[4 * r + j], conj(m[4 * c + j]));
-      unew[4 * r + c] = acc;
+    for (int j = 0; j < 4; ++j) {
+      const cd xc = mk(__shfl(x[j].re, base + c), __shfl(x[j].im, base + c));
+      cmac(acc, y[j], conj(xc));
     }
+    unew_row[c] = acc;
   }
-  return sweep + 1;
+  return 0;
 }
 
-// Full OptimizeGate for a general unitary: M = (1-beta) E + beta u_old^dagger,
-// then the nearest unitary.  E, uold, unew: 16 entries row-major.
-__device__ inline int optimize_gate_f64(const cd e[16], const cd uold[16], double beta, cd unew[16]) {
-  cd m[16];
+// Quad form of OptimizeGate (Sec. III-A-1, Eq. opt_u; beta of Sec. III-A-2).
+// Lane r passes row r of E and the whole u_old (16 entries) and receives row
+// r of u_new.  The maximiser of Re Tr(M u), M = (1-beta) E + beta u_old^dagger,
+// is found as u_new = u_old w* with w* the maximiser of Re Tr(M u_old w):
+// substituting u = u_old w is exact (w ranges over all unitaries), and once
+// the gates change slowly M u_old = (1-beta) E u_old + beta I is close to a
+// positive multiple of the identity, where the Jacobi iteration needs one or
+// two sweeps.
+__device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[16], int r, double beta,
+                                              cd unew_row[4]) {
+  cd m[4], one[4];
+  const double we = 1.0 - beta;  // exact 1 for beta = 0
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int c = 0; c < 4; ++c) {
+    cd acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cmac(acc, e_row[k], uold[4 * k + c]);
+    m[c] = scale(acc, we);
+    m[c].re += (c == r) ? beta : 0.0;  // + beta I
+    one[c] = mk(c == r ? 1.0 : 0.0, 0.0);
+  }
+  cd w[4];
+  const int st = nearest_unitary_f64_quad(m, one, r, w);  // row r of w*
+  if (st == 1) {  // zero M: keep u_old exactly (uniform over the quad)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unew_row[c] = at_rk(uold, r, c);
+    return;
+  }
+  // u_new row r = sum_k u_old[r][k] w*[k][.]; rows of w* from the quad
+  const int base = (int)(threadIdx.x & ~3u);
+  cd urow[4], v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) urow[k] = at_rk(uold, r, k);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = mk(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const cd ud = conj(uold[4 * c + r]);
-      m[4 * r + c] = (beta == 0.0) ? e[4 * r + c] : scale(e[4 * r + c], 1.0 - beta) + scale(ud, beta);
+      const cd wk = mk(__shfl(w[c].re, base + k), __shfl(w[c].im, base + k));
+      cmac(v[c], urow[k], wk);
     }
-  return nearest_unitary_f64(m, uold, unew);
+  }
+  // u_old w* carries u_old's own distance from unitarity; one Newton-Schulz
+  // step u <- u (3I - u^dagger u) / 2 squares that distance, so the returned
+  // gate is unitary to round-off whatever the history.  (NaN passes through.)
+  cd g[16];  // u^dagger u from every lane's row: g[i][j] = sum_k conj(u[k][i]) u[k][j]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cd pr = conj(v[i]) * v[j];
+      g[4 * i + j] = mk(quad_sum(pr.re), quad_sum(pr.im));
+    }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cd acc = scale(v[c], 3.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = acc - v[k] * g[4 * k + c];
+    unew_row[c] = scale(acc, 0.5);
+  }
 }
 
 }  // namespace qf

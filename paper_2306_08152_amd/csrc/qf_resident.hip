@@ -246,46 +246,46 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
       const int g = half == 0 ? a.p - 1 - step : step - a.p;
       const uint32_t b0 = n - 1 - a.locs[2 * g], b1 = n - 1 - a.locs[2 * g + 1];
       lds_ptrace<R>(L.X, n, b0, b1, L.red);
-      if (t == 0) {
-        cd uold[16], e[16], unew[16], P[16];
+      if (t < 4) {  // FP64 gate update on one quad, lane r = row r
+        const int r = (int)t;
+        cd uold[16], erow[4], urow[4], unew[4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          uold[k] = gates[16 * g + k];
-          P[k] = L.red[k];
-        }
+        for (int k = 0; k < 16; ++k) uold[k] = gates[16 * g + k];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          cd acc = mk(0.0, 0.0);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cd acc = mk(0.0, 0.0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              if (half == 0)
-                cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
-              else
-                cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
-            }
-            e[4 * r + c] = acc;
+          for (int k = 0; k < 4; ++k) {
+            if (half == 0)
+              cmac(acc, conj(at_kr(uold, k, r)), L.red[4 * k + c]);
+            else
+              cmac(acc, L.red[4 * r + k], conj(uold[4 * c + k]));
           }
+          erow[c] = acc;
+          cd v = uold[c];
+#pragma unroll
+          for (int rr = 1; rr < 4; ++rr) v = sel(r == rr, uold[4 * rr + c], v);
+          urow[c] = v;
+        }
         if (frozen) {
 #pragma unroll
-          for (int k = 0; k < 16; ++k) unew[k] = uold[k];
+          for (int c = 0; c < 4; ++c) unew[c] = urow[c];
         } else {
-          optimize_gate_f64(e, uold, o.beta, unew);
+          optimize_gate_f64_quad(erow, uold, r, o.beta, unew);
         }
+        // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored.
+        // Row r of u_old^dagger is conj(column r of u_old).
 #pragma unroll
-        for (int k = 0; k < 16; ++k) gates[16 * g + k] = unew[k];
-        // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored
+        for (int c = 0; c < 4; ++c) {
+          gates[16 * g + 4 * r + c] = unew[c];
+          cd udc = uold[c * 4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const cd ud = conj(uold[4 * c + r]);
-            const cd un = unew[4 * r + c];
-            const cd Av = half == 0 ? ud : un, Bv = half == 0 ? un : ud;
-            L.opsR[4 * r + c] = cx<R>{(R)Av.re, (R)Av.im};
-            L.opsR[16 + 4 * r + c] = cx<R>{(R)Bv.re, (R)Bv.im};
-          }
+          for (int rr = 1; rr < 4; ++rr) udc = sel(r == rr, uold[4 * c + rr], udc);
+          udc = conj(udc);
+          const cd Av = sel(half == 0, udc, unew[c]), Bv = sel(half == 0, unew[c], udc);
+          L.opsR[4 * r + c] = cx<R>{(R)Av.re, (R)Av.im};
+          L.opsR[16 + 4 * r + c] = cx<R>{(R)Bv.re, (R)Bv.im};
+        }
       }
       __syncthreads();
       lds_pass<R, true, true>(L.X, n, b0, b1, L.opsR, L.opsR + 16);

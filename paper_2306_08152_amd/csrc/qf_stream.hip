@@ -238,9 +238,11 @@ hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const Pass
   return launch_pass_t<double>(st, X, S, g, A, B);
 }
 
-// Rests handled by one k_env workgroup: 256 threads = 16 (i,j) pairs x 16,
-// four rests each.
-constexpr uint32_t kEnvRestsPerWG = 64;
+// k_env: 512 threads = 16 (i,j) pairs x 32 rest lanes; one workgroup covers
+// up to kEnvRestsPerWG rests (every n <= 14 in one workgroup per start, so no
+// cross-workgroup step is needed there).
+constexpr uint32_t kEnvThreads = 512;
+constexpr uint32_t kEnvRestsPerWG = 4096;
 
 // ------------------------------------------------------------------ k_build_init
 
@@ -289,63 +291,72 @@ struct EnvDev {
   uint32_t N, nrest, b0, b1, rlo, rhi, nwg;
 };
 
-// Finish one start: P (16 FP64 complex) -> env_out and/or gate update.
-__device__ inline void env_finish(const EnvDev& d, uint32_t s, const cd* P) {
+// Finish one start on the 4 lanes of a quad (lane r = row r): P (16 FP64
+// complex, LDS) -> env_out and/or the gate update.
+__device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P, int r) {
   const EnvArgs& a = d.a;
   if (!a.do_update) {
     if (a.env_out) {
       cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) eo[e] = P[e];
+      for (int c = 0; c < 4; ++c) eo[4 * r + c] = P[4 * r + c];
     }
     return;
   }
   cd* gp = reinterpret_cast<cd*>(a.gates) + (int64_t)s * a.gstride + 16 * (int64_t)a.gidx;
-  cd uold[16], e[16], unew[16];
+  cd uold[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) uold[k] = gp[k];
   // E = u_old^dagger P (half 0) or P u_old^dagger (half 1): the removal of the
-  // old gate commutes with the partial trace.
+  // old gate commutes with the partial trace.  Row r of E:
+  cd erow[4], urow[4], unew[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int c = 0; c < 4; ++c) {
+    cd acc = mk(0.0, 0.0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      cd acc = mk(0.0, 0.0);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (a.half == 0)
-          cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
-        else
-          cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
-      }
-      e[4 * r + c] = acc;
+    for (int k = 0; k < 4; ++k) {
+      if (a.half == 0)
+        cmac(acc, conj(at_kr(uold, k, r)), P[4 * k + c]);
+      else
+        cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
     }
+    erow[c] = acc;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cd v = uold[c];
+#pragma unroll
+    for (int rr = 1; rr < 4; ++rr) v = sel(r == rr, uold[4 * rr + c], v);
+    urow[c] = v;
+  }
   if (a.env_out) {
     cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
-  #pragma unroll
-  for (int k = 0; k < 16; ++k) eo[k] = e[k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) eo[4 * r + c] = erow[c];
   }
-  if (a.frozen && a.frozen[s]) {
-  #pragma unroll
-  for (int k = 0; k < 16; ++k) unew[k] = uold[k];
+  const bool frozen = a.frozen && a.frozen[s];
+  if (frozen) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unew[c] = urow[c];
   } else {
-    optimize_gate_f64(e, uold, a.beta, unew);
+    optimize_gate_f64_quad(erow, uold, r, a.beta, unew);
   }
   cd* uo = reinterpret_cast<cd*>(a.uold) + 16 * (size_t)s;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    uo[k] = uold[k];
-    gp[k] = unew[k];
+  for (int c = 0; c < 4; ++c) {
+    uo[4 * r + c] = urow[c];
+    gp[4 * r + c] = unew[c];
   }
 }
 
-// Grid: S x nwg workgroups of 256 threads.  Thread t sums entry (i,j) = t%16
-// over four 'rest' values; the workgroup reduces to 16 FP64 sums in a fixed
-// tree; with nwg > 1 each workgroup writes its 16 partials and the last one
-// to arrive (device-scope counter) adds them in workgroup order.
+// Grid: S x nwg workgroups of 512 threads.  Thread t sums entry (i,j) = t%16
+// over its rests (eight loads in flight at a time); the workgroup reduces to
+// 16 FP64 sums in a fixed tree.  With nwg > 1 (n >= 15) each workgroup writes
+// its 16 partials and the last one to arrive (device-scope counter) adds them
+// in workgroup order.
 template <typename R>
-__global__ __launch_bounds__(256) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
-  __shared__ cd red[256];
+__global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
+  __shared__ cd red[kEnvThreads];
   __shared__ int last;
   const uint32_t t = threadIdx.x;
   const uint32_t s = blockIdx.x / d.nwg;
@@ -353,27 +364,32 @@ __global__ __launch_bounds__(256) void k_env(const cx<R>* __restrict__ X, EnvDev
   const uint32_t ij = t & 15u, i = ij >> 2, j = ij & 3u;
   const uint32_t ro = local_off(i, d.b0, d.b1), co = local_off(j, d.b0, d.b1);
   const cx<R>* Xs = X + (size_t)s * d.N * d.N;
-  cx<R> v[4];
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t rest = w * kEnvRestsPerWG + (t >> 4) + 16u * k;
-    v[k] = mk<R>(0, 0);
-    if (rest < d.nrest) {
-      const uint32_t base = insert00(rest, d.rlo, d.rhi);
-      v[k] = Xs[(size_t)(base + ro) * d.N + (base + co)];
-    }
-  }
+  const uint32_t r_begin = w * kEnvRestsPerWG;
+  const uint32_t r_end = min(d.nrest, r_begin + kEnvRestsPerWG);
+  constexpr uint32_t kLanes = kEnvThreads / 16;
   cd acc = mk(0.0, 0.0);
+  for (uint32_t r0 = r_begin + (t >> 4); r0 < r_end; r0 += 8 * kLanes) {
+    cx<R> v[8];
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint32_t rest = r0 + k * kLanes;
+      v[k] = mk<R>(0, 0);
+      if (rest < r_end) {
+        const uint32_t base = insert00(rest, d.rlo, d.rhi);
+        v[k] = Xs[(size_t)(base + ro) * d.N + (base + co)];
+      }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
+  }
   red[t] = acc;
   __syncthreads();
-  for (uint32_t stride = 128; stride >= 16; stride >>= 1) {
+  for (uint32_t stride = kEnvThreads / 2; stride >= 16; stride >>= 1) {
     if (t < stride) red[t] = red[t] + red[t + stride];
     __syncthreads();
   }
   if (d.nwg == 1) {
-    if (t == 0) env_finish(d, s, red);
+    if (t < 4) env_finish_quad(d, s, red, (int)t);
     return;
   }
   cd* part = reinterpret_cast<cd*>(d.a.partials) + ((size_t)s * d.nwg + w) * 16;
@@ -402,10 +418,8 @@ __global__ __launch_bounds__(256) void k_env(const cx<R>* __restrict__ X, EnvDev
     red[t] = sum;
   }
   __syncthreads();
-  if (t == 0) {
-    __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    env_finish(d, s, red);
-  }
+  if (t == 0) __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t < 4) env_finish_quad(d, s, red, (int)t);
 }
 
 uint32_t env_workgroups(int n) {
@@ -424,7 +438,7 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
   d.rhi = d.b0 < d.b1 ? d.b1 : d.b0;
   d.nwg = env_workgroups(a.n);
   if (d.nwg > 1 && (!a.partials || !a.counters)) return hipErrorInvalidValue;
-  const dim3 grid((uint32_t)a.S * d.nwg), block(256);
+  const dim3 grid((uint32_t)a.S * d.nwg), block(kEnvThreads);
   if (precision == QF_C64)
     hipLaunchKernelGGL(k_env<float>, grid, block, 0, st, reinterpret_cast<const cf*>(X), d);
   else
@@ -457,7 +471,7 @@ __global__ __launch_bounds__(256) void k_cost(const cx<R>* __restrict__ X, uint3
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
       const uint32_t r = r0 + t + 256u * k;
-      v[k] = r < N ? Xs[(size_t)r * N + r] : mk<R>(0, 0);
+      v[k] = r < N ? Xs[(size_t)r * N + r] : mk<R>(0, 0);  // scalar-pair load, no array select
     }
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
@@ -492,27 +506,29 @@ hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int 
 
 // ------------------------------------------------------------------ k_optimize
 
+// Four lanes (one quad) per environment: lane r owns row r.
 __global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict__ env,
                                                  const cd* __restrict__ uold, double beta,
                                                  cd* __restrict__ unew) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= count) return;
-  cd e[16], u[16], un[16];
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = gt >> 2, r = gt & 3;
+  if (s >= count) return;  // whole quads leave together
+  cd e[4], u[16], un[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    e[k] = env[16 * s + k];
-    u[k] = uold[16 * s + k];
-  }
-  optimize_gate_f64(e, u, beta, un);
+  for (int c = 0; c < 4; ++c) e[c] = env[16 * s + 4 * r + c];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) unew[16 * s + k] = un[k];
+  for (int k = 0; k < 16; ++k) u[k] = uold[16 * s + k];
+  optimize_gate_f64_quad(e, u, r, beta, un);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) unew[16 * s + 4 * r + c] = un[c];
 }
 
 hipError_t launch_optimize(hipStream_t st, int count, const double* env, const double* uold,
                            double beta, double* unew) {
   const int threads = 64;
-  hipLaunchKernelGGL(k_optimize, dim3((count + threads - 1) / threads), dim3(threads), 0, st, count,
-                     reinterpret_cast<const cd*>(env), reinterpret_cast<const cd*>(uold), beta,
+  const long long lanes = 4ll * count;
+  hipLaunchKernelGGL(k_optimize, dim3((unsigned)((lanes + threads - 1) / threads)), dim3(threads), 0, st,
+                     count, reinterpret_cast<const cd*>(env), reinterpret_cast<const cd*>(uold), beta,
                      reinterpret_cast<cd*>(unew));
   return hipGetLastError();
 }

@@ -345,3 +345,36 @@ def test_invalid_arguments_rejected(qf):
         qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=-1.0)
     with pytest.raises(QfError):
         qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, mode=1, beta=2.0)
+
+
+def test_environment_n15_multi_workgroup(qf):
+    """n = 15 (environment summed by several workgroups per start): a sparse
+    complex64 builder (random diagonal plus entries that couple the gate's
+    local indices) whose partial trace is known entry by entry."""
+    n, N = 15, 1 << 15
+    rng = np.random.default_rng(1515)
+    loc = (2, 11)
+    b0, b1 = n - 1 - loc[0], n - 1 - loc[1]
+    X = torch.zeros((1, N, N), dtype=torch.complex64, device="cuda")
+    d = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    X[0].diagonal().copy_(torch.from_numpy(d).to("cuda"))
+    ref = np.zeros((4, 4), np.complex128)
+    idx = np.arange(N)
+    li = (((idx >> b0) & 1) << 1) | ((idx >> b1) & 1)
+    for i in range(4):
+        ref[i, i] += d[li == i].astype(np.complex128).sum()
+    # off-diagonal couplings: rows and columns that differ only in the gate bits
+    for _ in range(64):
+        rest = int(rng.integers(0, N)) & ~((1 << b0) | (1 << b1))
+        i, j = rng.integers(0, 4, size=2)
+        if i == j:
+            continue
+        r = rest | (int(i >> 1) << b0) | (int(i & 1) << b1)
+        c = rest | (int(j >> 1) << b0) | (int(j & 1) << b1)
+        v = np.complex64(rng.standard_normal() + 1j * rng.standard_normal())
+        X[0, r, c] += torch.tensor(v, device="cuda")
+        ref[i, j] += complex(v)
+    got = host(qf.environment(X, loc))[0]
+    assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+    del X
+    torch.cuda.empty_cache()
