@@ -32,6 +32,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_pass_n10_s16_c64_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since the
+    counters were taken (SHA-256 recorded beside them)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for p in rec["source_files"]:
+            with open(os.path.join(ROOT, p), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -176,11 +196,13 @@ def main():
         "config": {"workload": "n10_brickwall10_p45_s16_c64", "n_qubits": n, "n_gates": pr.n_gates,
                    "starts": S, "builder": "1024x1024 complex64 per start", "parallelism": "multistarts"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_pass<float,true,true> (fused remove + re-apply, one read + one write of "
                                "all 16 builders per launch)",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
-                     "launches_timed": tm["pass_launches"]},
+                     "launches_timed": tm["pass_launches"], "tile_columns": tm.get("pass_tcols"),
+                     "traffic_source": "profiles/k_pass_n10_s16_c64_traffic.json (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
+                                       "scaled by a 256 MiB copy)"},
         "breakdown": {"pass_avg_us": round(1e3 * pass_avg_ms, 2), "env_svd_avg_us": round(env_avg_us, 2),
                       "sweep_loop_start_sweeps_per_s": round(sweep_loop_rate, 2) if sweep_loop_rate else None,
                       "final_best_cost": float(np.min(res.costs))},

@@ -136,6 +136,9 @@ typedef struct {
   double pass_ms;        /* out (timing): summed durations of those passes */
   double env_ms;         /* out (timing): summed durations of those launches */
   double sweep_ms;       /* out (timing): device time of the sweep loop */
+  int32_t pass_tcols;    /* out: tile width (columns) of the fused pass, chosen
+                            on first use per (precision, n) by timing the
+                            candidates on the caller's builder */
 } qf_stats;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;

@@ -56,6 +56,7 @@ class QfStats(ctypes.Structure):
         ("pass_ms", ctypes.c_double),
         ("env_ms", ctypes.c_double),
         ("sweep_ms", ctypes.c_double),
+        ("pass_tcols", ctypes.c_int32),
     ]
 
 

@@ -124,13 +124,42 @@ __device__ __forceinline__ cd at_rk(const cd u[16], int r, int k) {
 // row's share of the pair's column norms and inner product and a two-step
 // butterfly completes the sums, so every lane holds bitwise-identical sums
 // and takes identical rotation decisions.
+// Lane exchange inside a quad with DPP quad_perm moves (plain VALU moves, no
+// trip through the LDS crossbar).  CTRL is the quad_perm selector
+// p0 | p1 << 2 | p2 << 4 | p3 << 6 (lane i of each quad reads lane p_i).
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+constexpr int kQuadXor1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // [1,0,3,2]
+constexpr int kQuadXor2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // [2,3,0,1]
+
+// Sum over the quad; every lane gets bitwise the same value (the two
+// addition orders it sees are commutations of the same pairs).
 __device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 4);
-  return v + __shfl_xor(v, 2, 4);
+  v += dpp_quad<kQuadXor1>(v);
+  return v + dpp_quad<kQuadXor2>(v);
 }
 __device__ __forceinline__ double quad_max(double v) {
-  v = fmax(v, __shfl_xor(v, 1, 4));
-  return fmax(v, __shfl_xor(v, 2, 4));
+  v = fmax(v, dpp_quad<kQuadXor1>(v));
+  return fmax(v, dpp_quad<kQuadXor2>(v));
+}
+// o[c] = this value as held by lane c of the quad.
+__device__ __forceinline__ void quad_gather(double v, double o[4]) {
+  o[0] = dpp_quad<0x00>(v);
+  o[1] = dpp_quad<0x55>(v);
+  o[2] = dpp_quad<0xAA>(v);
+  o[3] = dpp_quad<0xFF>(v);
+}
+__device__ __forceinline__ void quad_gather(cd v, cd o[4]) {
+  double re[4], im[4];
+  quad_gather(v.re, re);
+  quad_gather(v.im, im);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) o[c] = mk(re[c], im[c]);
 }
 
 // Jacobi rotation of columns (p, q) given the summed norms a, b and inner
@@ -267,15 +296,14 @@ __device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4],
     }
   }
   // u_new[r][c] = sum_j Y[r][j] conj(X[c][j]); rows of X from the quad
-  const int base = (int)(threadIdx.x & ~3u);
+  cd xall[4][4];  // xall[j][c] = X[c][j]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) quad_gather(x[j], xall[j]);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     cd acc = mk(0.0, 0.0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const cd xc = mk(__shfl(x[j].re, base + c), __shfl(x[j].im, base + c));
-      cmac(acc, y[j], conj(xc));
-    }
+    for (int j = 0; j < 4; ++j) cmac(acc, y[j], conj(xall[j][c]));
     unew_row[c] = acc;
   }
   return 0;
@@ -310,19 +338,17 @@ __device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[1
     return;
   }
   // u_new row r = sum_k u_old[r][k] w*[k][.]; rows of w* from the quad
-  const int base = (int)(threadIdx.x & ~3u);
   cd urow[4], v[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) urow[k] = at_rk(uold, r, k);
 #pragma unroll
   for (int c = 0; c < 4; ++c) v[c] = mk(0.0, 0.0);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int c = 0; c < 4; ++c) {
+    cd wall[4];  // wall[k] = w*[k][c]
+    quad_gather(w[c], wall);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const cd wk = mk(__shfl(w[c].re, base + k), __shfl(w[c].im, base + k));
-      cmac(v[c], urow[k], wk);
-    }
+    for (int k = 0; k < 4; ++k) cmac(v[c], urow[k], wall[k]);
   }
   // u_old w* carries u_old's own distance from unitarity; one Newton-Schulz
   // step u <- u (3I - u^dagger u) / 2 squares that distance, so the returned

@@ -107,13 +107,48 @@ PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols) {
 
 // ------------------------------------------------------------------ k_pass
 
-// One workgroup = one row quad x TCOLS columns (4*TCOLS elements), one
-// thread per 4x4 block.  The tile is loaded with 16-byte coalesced loads into
-// LDS, every thread transforms its block in registers and writes it back,
-// and the tile is stored with the same coalesced pattern.
+// One tile = one row quad x TCOLS columns (4*TCOLS elements), one thread per
+// 4x4 block.  A tile is loaded with 16-byte coalesced loads into LDS, every
+// thread transforms its block in registers and writes it back, and the tile
+// is stored with the same coalesced pattern.  The tile width TCOLS is a
+// tuning choice (smaller tiles shorten the end-of-grid drain, larger ones
+// cut per-workgroup overhead).
+struct TileBase {
+  uint32_t row, col;
+  size_t start_off;
+};
+
+__device__ __forceinline__ TileBase tile_base(const PassGeom& g, uint32_t tile) {
+  TileBase tb;
+  const uint32_t s = tile / g.tiles_per_start;
+  const uint32_t rem = tile - s * g.tiles_per_start;
+  const uint32_t rq = rem / g.col_tiles;
+  const uint32_t ct = rem - rq * g.col_tiles;
+  tb.row = insert00(rq, g.rlo, g.rhi);
+  uint32_t c = ct << g.tc;
+  if (g.nseg == 2)
+    c = insert0(c, g.seg_hi);
+  else if (g.nseg == 4)
+    c = insert00(c, g.seg_lo, g.seg_hi);
+  tb.col = c;
+  tb.start_off = (size_t)s * g.N * g.N;
+  return tb;
+}
+
+// Global element offset of element e (row-major 4 x TCOLS) of a tile.
+__device__ __forceinline__ size_t tile_elem(const PassGeom& g, const TileBase& tb, uint32_t e) {
+  const uint32_t i = e >> g.tcols_log;
+  const uint32_t tcol = e & ((1u << g.tcols_log) - 1u);
+  const uint32_t seg = tcol >> g.tc;
+  const uint32_t segoff =
+      (g.nseg == 4) ? local_off(seg, g.b0, g.b1) : ((g.nseg == 2) ? (seg << g.seg_hi) : 0u);
+  const size_t row = tb.row + local_off(i, g.b0, g.b1);
+  const size_t col = tb.col + segoff + (tcol & ((1u << g.tc) - 1u));
+  return tb.start_off + row * g.N + col;
+}
+
 template <typename R, bool HA, bool HB>
-__global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g, Operand A,
-                                              Operand B) {
+__global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g, Operand A, Operand B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<R>* tile = reinterpret_cast<cx<R>*>(smem_raw);
   using V = typename Vec16<R>::type;
@@ -122,42 +157,19 @@ __global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g,
   const uint32_t TCOLS = 1u << g.tcols_log;
   const uint32_t NT = TCOLS >> 2;
   const uint32_t t = threadIdx.x;
-  const uint32_t bid = blockIdx.x;
-  const uint32_t s = bid / g.tiles_per_start;
-  const uint32_t rem = bid - s * g.tiles_per_start;
-  const uint32_t rq = rem / g.col_tiles;
-  const uint32_t ct = rem - rq * g.col_tiles;
-  const uint32_t base_row = insert00(rq, g.rlo, g.rhi);
-  uint32_t base_col = ct << g.tc;
-  if (g.nseg == 2)
-    base_col = insert0(base_col, g.seg_hi);
-  else if (g.nseg == 4)
-    base_col = insert00(base_col, g.seg_lo, g.seg_hi);
-  cx<R>* Xs = X + (size_t)s * g.N * g.N;
-  const uint32_t tcmask = (1u << g.tc) - 1u;
+  const uint32_t cur = blockIdx.x;
+  const uint32_t s = cur / g.tiles_per_start;
+  const TileBase tb = tile_base(g, cur);
   const uint32_t nvec = (4u << g.tcols_log) / VE;
-
-  auto gaddr = [&](uint32_t e) -> cx<R>* {
-    const uint32_t i = e >> g.tcols_log;
-    const uint32_t tcol = e & (TCOLS - 1u);
-    const uint32_t seg = tcol >> g.tc;
-    const uint32_t segoff = (g.nseg == 4) ? local_off(seg, g.b0, g.b1)
-                                          : ((g.nseg == 2) ? (seg << g.seg_hi) : 0u);
-    const size_t row = base_row + local_off(i, g.b0, g.b1);
-    const size_t col = base_col + segoff + (tcol & tcmask);
-    return Xs + row * g.N + col;
-  };
 
   for (uint32_t v = t; v < nvec; v += NT) {
     const uint32_t e = v * VE;
-    *reinterpret_cast<V*>(tile + e) = *reinterpret_cast<const V*>(gaddr(e));
+    *reinterpret_cast<V*>(tile + e) = *reinterpret_cast<const V*>(X + tile_elem(g, tb, e));
   }
-
   cx<R> a[16], b[16];
   if (HA) load_operand<R>(a, A, s);
   if (HB) load_operand<R>(b, B, s);
   __syncthreads();
-
   {
     const uint32_t cb = insert00(t, g.tblo, g.tbhi);
     uint32_t col[4];
@@ -204,32 +216,33 @@ __global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g,
       for (uint32_t j = 0; j < 4; ++j) tile[i * TCOLS + col[j]] = x[4 * i + j];
   }
   __syncthreads();
-
   for (uint32_t v = t; v < nvec; v += NT) {
     const uint32_t e = v * VE;
-    *reinterpret_cast<V*>(gaddr(e)) = *reinterpret_cast<const V*>(tile + e);
+    *reinterpret_cast<V*>(X + tile_elem(g, tb, e)) = *reinterpret_cast<const V*>(tile + e);
   }
 }
 
+template <typename R, bool HA, bool HB>
+static hipError_t launch_pass_v(hipStream_t st, cx<R>* x, uint32_t total, const PassGeom& g, Operand A,
+                                Operand B) {
+  const uint32_t TCOLS = 1u << g.tcols_log;
+  const size_t lds = 4u * TCOLS * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_pass<R, HA, HB>), dim3(total), dim3(TCOLS >> 2), lds, st, x, g, A, B);
+  return hipGetLastError();
+}
+
+// Default tile width before (or without) tuning: 32 KiB of LDS per tile.
 int pass_max_tcols(int precision) { return precision == QF_C64 ? 1024 : 512; }
 
 template <typename R>
 static hipError_t launch_pass_t(hipStream_t st, void* X, int S, const PassGeom& g, Operand A,
                                 Operand B) {
-  const uint32_t TCOLS = 1u << g.tcols_log;
-  const dim3 block(TCOLS >> 2);
-  const dim3 grid((uint32_t)S * g.tiles_per_start);
-  const size_t lds = 4u * TCOLS * sizeof(cx<R>);
+  const uint32_t total = (uint32_t)S * g.tiles_per_start;
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
-  if (A.ptr && B.ptr)
-    hipLaunchKernelGGL((k_pass<R, true, true>), grid, block, lds, st, x, g, A, B);
-  else if (A.ptr)
-    hipLaunchKernelGGL((k_pass<R, true, false>), grid, block, lds, st, x, g, A, B);
-  else if (B.ptr)
-    hipLaunchKernelGGL((k_pass<R, false, true>), grid, block, lds, st, x, g, A, B);
-  else
-    return hipSuccess;
-  return hipGetLastError();
+  if (A.ptr && B.ptr) return launch_pass_v<R, true, true>(st, x, total, g, A, B);
+  if (A.ptr) return launch_pass_v<R, true, false>(st, x, total, g, A, B);
+  if (B.ptr) return launch_pass_v<R, false, true>(st, x, total, g, A, B);
+  return hipSuccess;
 }
 
 hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
