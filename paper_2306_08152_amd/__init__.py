@@ -14,7 +14,8 @@ from ._native import (  # noqa: F401
 from .hipbuild import build as build_library, lib_path  # noqa: F401
 
 _API = ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "cost", "instantiate",
-        "default_options", "workspace_size", "Result")
+        "default_options", "workspace_size", "Result", "instantiate_batch", "pack_batch",
+        "batch_workspace_size", "BatchResult")
 
 
 def __getattr__(name):

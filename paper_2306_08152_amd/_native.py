@@ -16,7 +16,7 @@ QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC = 0, 1, 2, 3
 EXPORTED = [
     "qf_create", "qf_destroy", "qf_set_stream", "qf_strerror", "qf_last_error", "qf_options_default",
     "qf_workspace_size", "qf_build", "qf_apply_gate", "qf_environment", "qf_optimize_gate",
-    "qf_update_gate", "qf_cost", "qf_instantiate",
+    "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
 ]
 
 
@@ -83,6 +83,11 @@ _SIGS = {
     "qf_instantiate": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int,
                                       ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _VP, _VP,
                                       _DP, ctypes.POINTER(QfStats)]),
+    "qf_batch_workspace_size": (ctypes.c_size_t, [ctypes.c_int, _I32P, _I32P, ctypes.c_int,
+                                                  ctypes.POINTER(QfOptions)]),
+    "qf_instantiate_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32P, _I32P, _I32P, _VP, _VP, ctypes.c_int,
+                                            ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _VP,
+                                            _DP, _I32P, _I32P, _I32P, ctypes.POINTER(QfStats)]),
 }
 
 _lib = None

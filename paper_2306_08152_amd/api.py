@@ -215,3 +215,88 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
         else dict(pass_tcols=st.pass_tcols)
     return Result(out, out_all, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.n_resets,
                   st.n_rechecks, st.mode_used, st.elapsed_ms, h, tm)
+
+
+@dataclass
+class BatchResult:
+    gates: torch.Tensor          # flat: per block, n_starts x p_b x 4 x 4 (every start's final gates)
+    gate_offsets: np.ndarray     # (n_blocks + 1,)
+    n_starts: int
+    costs: np.ndarray            # (n_blocks, S) FP64 costs of the returned gates
+    best: np.ndarray             # (n_blocks,)
+    status: np.ndarray           # (n_blocks,)
+    sweeps: np.ndarray           # (n_blocks,)
+    elapsed_ms: float
+    kernel_ms: float
+
+    def block_gates(self, b: int) -> torch.Tensor:
+        """(S, p_b, 4, 4) view of block b's gates."""
+        g0, g1 = int(self.gate_offsets[b]), int(self.gate_offsets[b + 1])
+        S = self.n_starts
+        return self.gates[S * g0:S * g1].view(S, g1 - g0, 4, 4)
+
+
+def pack_batch(targets, locs, init_gates):
+    """Concatenate per-block targets (N_b x N_b), locations (p_b x 2) and
+    initial gates (S x p_b x 4 x 4) into the flat layout of
+    qf_instantiate_batch."""
+    block_n = np.array([_n_of(t.shape[0]) for t in targets], np.int32)
+    counts = [int(np.asarray(l).reshape(-1, 2).shape[0]) for l in locs]
+    gate_offsets = np.zeros(len(counts) + 1, np.int32)
+    gate_offsets[1:] = np.cumsum(counts)
+    loc_flat = np.concatenate([np.asarray(l, np.int32).reshape(-1, 2) for l in locs])
+    tflat = torch.cat([t.reshape(-1) for t in targets])
+    gflat = torch.cat([g.reshape(-1, 4, 4) for g in init_gates])
+    return block_n, gate_offsets, loc_flat, tflat, gflat
+
+
+def batch_workspace_size(block_n, gate_offsets, S: int, opt: nat.QfOptions) -> int:
+    bn = np.ascontiguousarray(block_n, np.int32)
+    go = np.ascontiguousarray(gate_offsets, np.int32)
+    return int(nat.load().qf_batch_workspace_size(len(bn), bn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                  go.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), S,
+                                                  ctypes.byref(opt)))
+
+
+def instantiate_batch(block_n, gate_offsets, locations, targets: torch.Tensor, init_gates: torch.Tensor,
+                      n_starts: int, tol: float = 1e-10, options: nat.QfOptions | None = None,
+                      workspace: torch.Tensor | None = None, out_gates: torch.Tensor | None = None,
+                      timing: bool = False, **kw) -> BatchResult:
+    """Batched QFactor over many small blocks (qf_instantiate_batch); the
+    arguments are in the flat layout that pack_batch produces."""
+    opt = options if options is not None else default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    bn = np.ascontiguousarray(block_n, np.int32)
+    go = np.ascontiguousarray(gate_offsets, np.int32)
+    lf = np.ascontiguousarray(locations, np.int32).reshape(-1)
+    nb = len(bn)
+    if targets.dtype != torch.complex128 or init_gates.dtype != torch.complex128:
+        raise TypeError("targets and init_gates must be complex128")
+    if not (targets.is_contiguous() and init_gates.is_contiguous()):
+        raise ValueError("targets and init_gates must be contiguous")
+    lib = nat.load()
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    need = int(lib.qf_batch_workspace_size(nb, bn.ctypes.data_as(i32p), go.ctypes.data_as(i32p), n_starts,
+                                           ctypes.byref(opt))) if nb > 0 else 0
+    if need == 0:
+        need = 1  # invalid sizes or options: the library rejects them with its message
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=targets.device)
+    if out_gates is None:
+        out_gates = torch.empty_like(init_gates)
+    costs = np.zeros((max(nb, 1), n_starts), np.float64)
+    best = np.zeros(max(nb, 1), np.int32)
+    status = np.zeros(max(nb, 1), np.int32)
+    sweeps = np.zeros(max(nb, 1), np.int32)
+    st = nat.QfStats()
+    st.timing = 1 if timing else 0
+    ctx = _ctx(targets.device)
+    rc = lib.qf_instantiate_batch(ctx, nb, bn.ctypes.data_as(i32p), go.ctypes.data_as(i32p), lf.ctypes.data_as(i32p),
+                                  _ptr(targets), _ptr(init_gates), n_starts, float(tol), ctypes.byref(opt),
+                                  _ptr(workspace), need, _ptr(out_gates),
+                                  costs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), best.ctypes.data_as(i32p),
+                                  status.ctypes.data_as(i32p), sweeps.ctypes.data_as(i32p), ctypes.byref(st))
+    nat.check(rc, ctx)
+    return BatchResult(out_gates, go, n_starts, costs[:nb], best[:nb], status[:nb], sweeps[:nb], st.elapsed_ms,
+                       st.sweep_ms)

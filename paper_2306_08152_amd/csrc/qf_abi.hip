@@ -657,6 +657,62 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
   return QF_OK;
 }
 
+// Workspace layout of qf_instantiate_batch.
+struct BatchLayout {
+  size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, hist = 0, scratch = 0, cost = 0,
+         best = 0, status = 0, sweeps = 0, queue = 0;
+  size_t total = 0;
+  int ring = 2, groups = 0;
+};
+
+BatchLayout make_batch_layout(int n_blocks, int total_gates, int S, const qf_options& o) {
+  BatchLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t nb = (size_t)n_blocks;
+  L.order = take(nb * 4);
+  L.blk_n = take(nb * 4);
+  L.gate_off = take((nb + 1) * 4);
+  L.tgt_off = take(nb * 8);
+  L.locs = take((size_t)total_gates * 8);
+  L.ring = std::max(2, o.long_diff_count + 1);
+  L.hist = take(nb * S * L.ring * 8);
+  L.groups = batch_groups(n_blocks, S);
+  L.scratch = take(batch_scratch_entries(std::min(L.groups, kBatchMaxGrid)) * 16);
+  L.cost = take(nb * S * 8);
+  L.best = take(nb * 4);
+  L.status = take(nb * 4);
+  L.sweeps = take(nb * 4);
+  L.queue = take(4);
+  L.total = off;
+  return L;
+}
+
+int validate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, const int32_t* gate_offsets,
+                   const int32_t* locs, int S) {
+  if (n_blocks < 1) return fail(ctx, QF_EINVAL, "n_blocks must be >= 1");
+  if (!block_n || !gate_offsets) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (S < 1 || S > 16) return fail(ctx, QF_EINVAL, "n_starts=%d outside [1, 16]", S);
+  if (gate_offsets[0] != 0) return fail(ctx, QF_EINVAL, "gate_offsets[0] must be 0");
+  for (int b = 0; b < n_blocks; ++b) {
+    if (block_n[b] < 2 || block_n[b] > 4) return fail(ctx, QF_EINVAL, "block %d: n=%d outside [2, 4]", b, block_n[b]);
+    if (gate_offsets[b + 1] <= gate_offsets[b]) return fail(ctx, QF_EINVAL, "block %d has no gates", b);
+    if ((int64_t)gate_offsets[b + 1] * S * 16 > ((int64_t)1 << 31))
+      return fail(ctx, QF_EINVAL, "too many gates in the batch");
+  }
+  if (!locs) return fail(ctx, QF_EINVAL, "locations is NULL");
+  for (int b = 0; b < n_blocks; ++b)
+    for (int g = gate_offsets[b]; g < gate_offsets[b + 1]; ++g)
+      if (!valid_loc(block_n[b], locs + 2 * g))
+        return fail(ctx, QF_EINVAL, "block %d gate %d: location (%d, %d) invalid for n=%d", b, g - gate_offsets[b],
+                    locs[2 * g], locs[2 * g + 1], block_n[b]);
+  return QF_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -691,7 +747,7 @@ void qf_options_default(qf_options* o) {
   o->beta = 0.0;
   o->precision = QF_C128;
   o->mode = QF_MODE_AUTO;
-  o->recheck_below = 1e-6;
+  o->recheck_below = 1e-3;
   o->stream_groups = 0;
 }
 
@@ -956,6 +1012,144 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (all_numeric) return fail(ctx, QF_ENUMERIC, "every start produced non-finite values");
+  return QF_OK;
+}
+
+size_t qf_batch_workspace_size(int n_blocks, const int32_t* block_n, const int32_t* gate_offsets, int n_starts,
+                               const qf_options* opt) {
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (validate_options(nullptr, o) != QF_OK) return 0;
+  if (n_blocks < 1 || !block_n || !gate_offsets || n_starts < 1 || n_starts > 16) return 0;
+  for (int b = 0; b < n_blocks; ++b)
+    if (block_n[b] < 2 || block_n[b] > 4 || gate_offsets[b + 1] <= gate_offsets[b]) return 0;
+  return make_batch_layout(n_blocks, gate_offsets[n_blocks], n_starts, o).total;
+}
+
+int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, const int32_t* gate_offsets,
+                         const int32_t* locations, const void* targets, const void* init_gates, int n_starts,
+                         double tol, const qf_options* opt, void* workspace, size_t ws_bytes, void* out_gates,
+                         double* out_costs, int32_t* out_best, int32_t* out_status, int32_t* out_sweeps,
+                         qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, QF_EINVAL, "tol must be finite and > 0");
+  o.dist_tol = tol;
+  int rc = validate_options(ctx, o);
+  if (rc) return rc;
+  rc = validate_batch(ctx, n_blocks, block_n, gate_offsets, locations, n_starts);
+  if (rc) return rc;
+  if (!targets || !init_gates || !out_gates || !out_costs) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  const int total_gates = gate_offsets[n_blocks];
+  const BatchLayout L = make_batch_layout(n_blocks, total_gates, n_starts, o);
+  if (!workspace || ws_bytes < L.total)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = ctx->stream;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+
+  // Block descriptors.  Blocks run largest-first (work N^2 * p) so that the
+  // queue ends on short problems, and neighbours in a workgroup are alike.
+  std::vector<int32_t> order(n_blocks);
+  std::vector<int64_t> tgt_off(n_blocks);
+  int64_t acc = 0;
+  for (int b = 0; b < n_blocks; ++b) {
+    order[b] = b;
+    tgt_off[b] = acc;
+    acc += (int64_t)1 << (2 * block_n[b]);
+  }
+  auto work = [&](int b) { return ((int64_t)1 << (2 * block_n[b])) * (gate_offsets[b + 1] - gate_offsets[b]); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.order, order.data(), (size_t)n_blocks * 4, hipMemcpyHostToDevice, st));
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.blk_n, block_n, (size_t)n_blocks * 4, hipMemcpyHostToDevice, st));
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.gate_off, gate_offsets, (size_t)(n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.tgt_off, tgt_off.data(), (size_t)n_blocks * 8, hipMemcpyHostToDevice, st));
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.locs, locations, (size_t)total_gates * 8, hipMemcpyHostToDevice, st));
+  const size_t gate_bytes = (size_t)total_gates * n_starts * 256;
+  if (out_gates != init_gates)
+    QF_HIP(ctx, hipMemcpyAsync(out_gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  int32_t* queue = reinterpret_cast<int32_t*>(ws + L.queue);
+  QF_HIP(ctx, launch_fill_i32(st, queue, 0, 1));
+
+  BatchArgs a{};
+  a.n_blocks = n_blocks;
+  a.S = n_starts;
+  a.order = reinterpret_cast<const int32_t*>(ws + L.order);
+  a.blk_n = reinterpret_cast<const int32_t*>(ws + L.blk_n);
+  a.gate_off = reinterpret_cast<const int32_t*>(ws + L.gate_off);
+  a.tgt_off = reinterpret_cast<const int64_t*>(ws + L.tgt_off);
+  a.locs = reinterpret_cast<const int32_t*>(ws + L.locs);
+  a.V = reinterpret_cast<const double*>(targets);
+  a.gates = reinterpret_cast<double*>(out_gates);
+  a.tol = tol;
+  a.opt = o;
+  a.hist = reinterpret_cast<double*>(ws + L.hist);
+  a.ring = L.ring;
+  a.scratch = reinterpret_cast<double*>(ws + L.scratch);
+  a.out_cost = reinterpret_cast<double*>(ws + L.cost);
+  a.out_best = reinterpret_cast<int32_t*>(ws + L.best);
+  a.out_status = reinterpret_cast<int32_t*>(ws + L.status);
+  a.out_sweeps = reinterpret_cast<int32_t*>(ws + L.sweeps);
+  a.queue = queue;
+  // grid <= min(groups, kBatchMaxGrid), the count the scratch was sized for
+  const int grid = batch_grid(o.precision, L.groups);
+  const bool timed = stats && stats->timing;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
+    }
+  } ev_free{ev};
+  if (timed) {
+    QF_HIP(ctx, hipEventCreate(&ev[0]));
+    QF_HIP(ctx, hipEventCreate(&ev[1]));
+    QF_HIP(ctx, hipEventRecord(ev[0], st));
+  }
+  QF_HIP(ctx, launch_batch(st, o.precision, grid, a));
+  if (timed) QF_HIP(ctx, hipEventRecord(ev[1], st));
+
+  std::vector<int32_t> best(n_blocks), status(n_blocks), sweeps(n_blocks);
+  QF_HIP(ctx, hipMemcpyAsync(out_costs, ws + L.cost, (size_t)n_blocks * n_starts * 8, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipMemcpyAsync(best.data(), ws + L.best, (size_t)n_blocks * 4, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipMemcpyAsync(status.data(), ws + L.status, (size_t)n_blocks * 4, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipMemcpyAsync(sweeps.data(), ws + L.sweeps, (size_t)n_blocks * 4, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  if (out_best) std::memcpy(out_best, best.data(), (size_t)n_blocks * 4);
+  if (out_status) std::memcpy(out_status, status.data(), (size_t)n_blocks * 4);
+  if (out_sweeps) std::memcpy(out_sweeps, sweeps.data(), (size_t)n_blocks * 4);
+  if (stats) {
+    int max_sweeps = 0, worst = QF_CONVERGED;
+    double worst_cost = 0.0;
+    for (int b = 0; b < n_blocks; ++b) {
+      max_sweeps = std::max(max_sweeps, sweeps[b]);
+      worst = std::max(worst, status[b]);
+      worst_cost = std::max(worst_cost, out_costs[(size_t)b * n_starts + best[b]]);
+    }
+    stats->sweeps = max_sweeps;
+    stats->best_start = 0;
+    stats->status = worst;
+    stats->n_resets = o.reset_iter > 0 ? max_sweeps / o.reset_iter : 0;
+    stats->n_rechecks = 0;
+    stats->mode_used = QF_MODE_RESIDENT;
+    stats->best_cost = worst_cost;
+    stats->pass_launches = stats->env_launches = 0;
+    stats->pass_ms = stats->env_ms = 0.0;
+    float kms = 0.0f;
+    if (timed) QF_HIP(ctx, hipEventElapsedTime(&kms, ev[0], ev[1]));
+    stats->sweep_ms = kms;
+    stats->pass_tcols = 0;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
   return QF_OK;
 }
 

@@ -96,6 +96,35 @@ struct ResidentArgs {
   int32_t history_rows;
 };
 hipError_t launch_resident(hipStream_t st, const ResidentArgs& a, int* ok_coresident);
+
+// Batched small problems (n <= 4), one persistent launch.
+struct BatchArgs {
+  int n_blocks, S;
+  const int32_t* order;     // device, n_blocks
+  const int32_t* blk_n;     // device, n_blocks
+  const int32_t* gate_off;  // device, n_blocks + 1
+  const int64_t* tgt_off;   // device, n_blocks
+  const int32_t* locs;      // device, total_gates x 2
+  const double* V;          // device targets (c128)
+  double* gates;            // device (c128), in/out
+  double tol;
+  qf_options opt;
+  double* hist;             // device, n_blocks x S x ring
+  int ring;
+  double* scratch;          // device, batch_scratch_entries(grid) c128 entries
+  double* out_cost;         // device, n_blocks x S
+  int32_t* out_best;        // device, n_blocks
+  int32_t* out_status;      // device, n_blocks
+  int32_t* out_sweeps;      // device, n_blocks
+  int32_t* queue;           // device, 1 (zero before launch)
+};
+// Quads of one wavefront hold (block, start) pairs: 16 / S blocks per group
+// of work; at most kBatchMaxGrid workgroups, each with its own FP64 scratch.
+constexpr int kBatchMaxGrid = 2048;
+int batch_groups(int n_blocks, int S);
+int batch_grid(int precision, int n_groups);  // workgroups to launch (device occupancy)
+size_t batch_scratch_entries(int grid);       // c128 scratch entries for `grid` workgroups
+hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs& a);
 size_t resident_lds_bytes(int n, int precision);
 
 }  // namespace qf

@@ -84,10 +84,41 @@ def test_workspace_size_layout(lib):
     assert lib.qf_workspace_size(4, 3, 1, ctypes.byref(_opts(lib, beta=1.5))) == 0
 
 
+def test_batch_workspace_size(lib):
+    """Batched layout: descriptors, history ring per (block, start), and an
+    FP64 scratch builder (16 x 16) per quad of each launched workgroup."""
+    I32 = ctypes.c_int32
+    bn = (I32 * 3)(3, 4, 2)
+    go = (I32 * 4)(0, 5, 17, 18)
+    o = _opts(lib)
+    ws = lib.qf_batch_workspace_size(3, bn, go, 8, ctypes.byref(o))
+    ring = o.long_diff_count + 1
+    groups = 2  # two blocks of 8 starts per wavefront of 16 quads
+    assert ws >= 3 * 8 * ring * 8 + groups * 16 * 256 * 16
+    assert ws <= 3 * 8 * ring * 8 + groups * 16 * 256 * 16 + 8192
+    # more blocks than the workgroup cap: scratch stops growing
+    big = 1 << 16
+    bnb = (I32 * big)(*([3] * big))
+    gob = (I32 * (big + 1))(*range(big + 1))
+    wsb = lib.qf_batch_workspace_size(big, bnb, gob, 1, ctypes.byref(o))
+    assert wsb < big * ring * 8 + 2048 * 16 * 256 * 16 + (4 << 20)
+    # invalid -> 0
+    assert lib.qf_batch_workspace_size(3, bn, go, 17, ctypes.byref(o)) == 0
+    assert lib.qf_batch_workspace_size(3, bn, go, 0, ctypes.byref(o)) == 0
+    assert lib.qf_batch_workspace_size(0, bn, go, 8, ctypes.byref(o)) == 0
+    bad = (I32 * 3)(3, 5, 2)
+    assert lib.qf_batch_workspace_size(3, bad, go, 8, ctypes.byref(o)) == 0
+    empty = (I32 * 4)(0, 5, 5, 6)
+    assert lib.qf_batch_workspace_size(3, bn, empty, 8, ctypes.byref(o)) == 0
+
+
 def test_null_context_is_rejected_before_device_work(lib):
     locs = (ctypes.c_int32 * 2)(0, 1)
     assert lib.qf_instantiate(None, 2, None, 1, locs, None, 1, 1e-8, None, None, 0, None, None, None,
                               None) == nat.QF_EINVAL
+    I32 = ctypes.c_int32
+    assert lib.qf_instantiate_batch(None, 1, (I32 * 1)(2), (I32 * 2)(0, 1), locs, None, None, 1, 1e-8, None, None,
+                                    0, None, None, None, None, None, None) == nat.QF_EINVAL
     assert lib.qf_apply_gate(None, 2, 1, None, 0, locs, None, 0, 0) == nat.QF_EINVAL
     assert lib.qf_environment(None, 2, 1, None, 0, locs, None) == nat.QF_EINVAL
     assert lib.qf_destroy(None) == nat.QF_EINVAL
