@@ -11,10 +11,12 @@ read-back and the final FP64 re-evaluation included), inputs resident in HBM.
 
 Extra workloads are reported in the same line: the complex128 form of the same
 problem, n = 12 (44 gates, one start, 4096 x 4096 builder) in both precisions,
-and full n = 6 / n = 3 instantiations (converged instantiations per second).
+full n = 6 / n = 3 instantiations (converged instantiations per second), and
+the batched workload of 4096 independent 3- and 4-qubit blocks x 8 starts in
+one persistent launch (converged blocks per second).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
-                       [--probe copy]
+                       [--probe copy|batch]
 """
 from __future__ import annotations
 
@@ -61,8 +63,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy"], default=None,
-                    help="run only a plain device copy of known size (traffic-counter calibration)")
+    ap.add_argument("--probe", choices=["copy", "batch"], default=None,
+                    help="copy: only a plain device copy of known size (traffic-counter calibration); "
+                         "batch: only the 4096-block batched workload")
     return ap.parse_args()
 
 
@@ -124,6 +127,34 @@ def copy_probe(torch):
                       "GBps_read_plus_write": 2 * n * 10 / dt / 1e9}), flush=True)
 
 
+def batch_workload(qf, torch) -> dict:
+    """4096 independent 3- and 4-qubit blocks x 8 starts, each in one
+    persistent launch per precision; converged blocks per second over the
+    whole qf_instantiate_batch call."""
+    import qfinputs as I
+    probs = I.config4_blocks()
+    bn, go, lf, tf, gf = qf.pack_batch([torch.from_numpy(p.target).to("cuda") for p in probs],
+                                       [p.locs for p in probs],
+                                       [torch.from_numpy(p.init_gates).to("cuda") for p in probs])
+    out = {}
+    for prec, tag in ((1, "c64"), (0, "c128")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb = qf.instantiate_batch(bn, go, lf, tf, gf, I.C4["starts"], tol=I.C4["tol"], precision=prec,
+                                  timing=True)
+        torch.cuda.synchronize()
+        db = time.perf_counter() - t0
+        conv = int(np.sum(rb.status == 0))
+        out[f"batch4096_s8_{tag}_converged_blocks_per_s"] = round(conv / db, 1)
+        out[f"batch4096_s8_{tag}_start_sweeps_per_s"] = round(float(np.sum(rb.sweeps)) * I.C4["starts"] / db, 1)
+        out[f"batch4096_s8_{tag}_launch_ms"] = round(rb.kernel_ms, 2)
+        out[f"batch4096_s8_{tag}_converged"] = conv
+        out[f"batch4096_s8_{tag}_sweeps_median_p99_max"] = [float(np.median(rb.sweeps)),
+                                                            float(np.percentile(rb.sweeps, 99)),
+                                                            int(rb.sweeps.max())]
+    return out
+
+
 def cpu_baseline(n_sweeps=3):
     """The FP64 oracle (builder mode) on the host: 3 sweeps of one start of the
     n = 10 headline problem."""
@@ -161,6 +192,9 @@ def main():
     torch.cuda.set_device(0)
     if args.probe == "copy":
         copy_probe(torch)
+        return
+    if args.probe == "batch":
+        print(json.dumps(batch_workload(qf, torch)), flush=True)
         return
 
     K, W = max(1, args.steps), max(0, args.warmup)
@@ -257,6 +291,7 @@ def main():
         d3 = time.perf_counter() - t0
         extra["n3_p4_c128_sweeps_per_s"] = round(r3.sweeps / d3, 1)
         extra["n3_p4_c128_status"] = int(r3.status)
+        extra.update(batch_workload(qf, torch))
         out["extra"] = extra
 
     if not args.no_cpu:

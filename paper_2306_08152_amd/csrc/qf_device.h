@@ -192,7 +192,12 @@ __device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, do
   const cd yp = y[p], yq = ph * y[q];
   y[p] = scale(yp, c) - scale(yq, s);
   y[q] = scale(yp, s) + scale(yq, c);
-  return 1.0;
+  // 1 = a large rotation; 0 = a small one: cosine of the pair and tan of the
+  // angle both below 1e-8.  A later rotation (p, r) moves the cosine of an
+  // orthogonalised pair (p, q) by at most about max(tan, cosine of (p, r))
+  // times the cosine of (r, q), so a sweep of small rotations leaves every
+  // cosine below ~4e-16, the round-off threshold above: no confirming sweep.
+  return (g2 > 1e-16 * (a * b) || fabs(t) > 1e-8) ? 1.0 : 0.0;
 }
 
 template <int P0, int Q0, int P1, int Q1>
@@ -244,7 +249,7 @@ __device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4],
   cd y[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) y[j] = mk(j == r ? 1.0 : 0.0, 0.0);
-  // Cyclic sweeps until a sweep finds no pair above round-off.
+  // Cyclic sweeps until a sweep makes no large rotation.
   for (int sweep = 0; sweep < 30; ++sweep) {
     double rel = quad_round<0, 1, 2, 3>(mrow, y);
     rel = fmax(rel, quad_round<0, 2, 1, 3>(mrow, y));
