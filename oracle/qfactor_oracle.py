@@ -52,7 +52,11 @@ the exact derivative of the trace (brute force), unitarity, local optimality
 against random unitaries (von Neumann trace inequality), per-update
 monotonicity, the Frobenius identity of Eq. cost, closed-form single-gate and
 product-target cases, dense Kronecker embeddings, and builder mode against
-definition mode.
+definition mode; for the gradient: brute-force central differences, torch's
+own autograd on an independent dense construction, the flat gate-phase
+direction, the vanishing Riemannian gradient at the global minimum, the
+closed form exp(i t P) = cos t I + i sin t P of the parameterised gates, and
+finite differences of the parameter chain rule.
 """
 from __future__ import annotations
 
@@ -66,6 +70,7 @@ __all__ = [
     "optimize_gate", "sweep_definition", "BuilderOracle", "instantiate",
     "STATUS_CONVERGED", "STATUS_PLATEAU", "STATUS_MAX_ITER", "STATUS_NUMERIC",
     "nuclear_norm", "frobenius_distance_sq", "optimize_gate_batched", "builder_rows",
+    "cost_gradient", "PAULI2", "su4_hermitian", "su4_gate", "su4_theta_gradient", "param_cost_gradient",
 ]
 
 STATUS_CONVERGED = 0
@@ -507,3 +512,80 @@ def nuclear_norm(E: np.ndarray) -> float:
 
 def frobenius_distance_sq(V: np.ndarray, C: np.ndarray) -> float:
     return float(np.sum(np.abs(C - V) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Gradient of the cost (Sec. II: the cost Delta, and the gradient-based
+# optimisers of "Numerical Optimization in Instantiation"; Q6 environment).
+# ---------------------------------------------------------------------------
+
+def cost_gradient(V: np.ndarray, gates, locs, n: int) -> tuple[float, np.ndarray]:
+    """Delta and, for every gate matrix u_g, the real gradient packed as a
+    complex matrix: G_g[i, j] = dDelta/dRe u_g[i, j] + 1j dDelta/dIm u_g[i, j].
+
+    With T = Tr(V^dagger C) = Tr(E_g u_g) (Q6), dT/du_g[i, j] = E_g[j, i], so
+    d|T| along a change du is Re(conj(T) Tr(E_g du)) / |T|, which gives
+    G_g = -(T / |T|) conj(E_g)^T / N.  At T = 0 the modulus is not
+    differentiable; the zero matrix is returned there."""
+    gates = np.asarray(gates, np.complex128)
+    N = 1 << n
+    T = overlap(V, circuit_unitary(gates, locs, n))
+    G = np.zeros_like(gates)
+    if abs(T) > 0.0:
+        ph = T / abs(T)
+        for g in range(len(gates)):
+            E = environment(V, gates, locs, n, g)
+            G[g] = -(ph / N) * E.conj().T
+    return 1.0 - abs(T) / N, G
+
+
+# Parameterised two-qubit gates for the gradient-based baseline: a gate is
+# exp(i H(theta)) with H = sum_k theta_k P_k over the 15 non-identity
+# two-qubit Pauli products P_k = sigma_a (x) sigma_b, (a, b) != (0, 0), in
+# the order a = 0..3 major, b = 0..3 minor.  H is Hermitian and traceless, so
+# the gate is in SU(4); the cost does not see a gate's global phase, so 15
+# real parameters reach every U(4) gate up to that phase.
+
+_SIGMA = [np.eye(2, dtype=np.complex128),
+          np.array([[0, 1], [1, 0]], np.complex128),
+          np.array([[0, -1j], [1j, 0]], np.complex128),
+          np.array([[1, 0], [0, -1]], np.complex128)]
+PAULI2 = np.stack([np.kron(_SIGMA[a], _SIGMA[b]) for a in range(4) for b in range(4) if (a, b) != (0, 0)])
+
+
+def su4_hermitian(theta: np.ndarray) -> np.ndarray:
+    """H(theta) = sum_k theta_k P_k for theta of shape (..., 15)."""
+    return np.tensordot(np.asarray(theta, np.float64), PAULI2, axes=([-1], [0]))
+
+
+def su4_gate(theta: np.ndarray) -> np.ndarray:
+    """exp(i H(theta)) for theta of shape (..., 15) (matrix exponential)."""
+    from scipy.linalg import expm
+    th = np.asarray(theta, np.float64)
+    flat = th.reshape(-1, 15)
+    out = np.stack([expm(1j * su4_hermitian(t)) for t in flat])
+    return out.reshape(th.shape[:-1] + (4, 4))
+
+
+def su4_theta_gradient(theta: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Chain rule from a gate-matrix gradient G (packed as in cost_gradient)
+    to the 15 parameters: dDelta/dtheta_k = Re Tr(G^dagger dU/dtheta_k), with
+    dU/dtheta_k the Frechet derivative of the exponential at iH in the
+    direction iP_k."""
+    from scipy.linalg import expm_frechet
+    th = np.asarray(theta, np.float64).reshape(-1, 15)
+    Gf = np.asarray(G, np.complex128).reshape(-1, 4, 4)
+    out = np.zeros_like(th)
+    for i in range(th.shape[0]):
+        A = 1j * su4_hermitian(th[i])
+        for k in range(15):
+            dU = expm_frechet(A, 1j * PAULI2[k], compute_expm=False)
+            out[i, k] = float(np.real(np.vdot(Gf[i], dU)))
+    return out.reshape(np.shape(theta))
+
+
+def param_cost_gradient(V: np.ndarray, theta: np.ndarray, locs, n: int) -> tuple[float, np.ndarray]:
+    """Delta and dDelta/dtheta for gates exp(i H(theta_g)), theta (p, 15)."""
+    gates = su4_gate(theta)
+    c, G = cost_gradient(V, gates, locs, n)
+    return c, su4_theta_gradient(theta, G)

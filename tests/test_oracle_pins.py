@@ -432,3 +432,134 @@ def test_update_scale_invariance():
         np.testing.assert_allclose(O.optimize_gate(c * E, u0), ref, atol=1e-13)
         np.testing.assert_allclose(O.optimize_gate_batched((c * E)[None], u0[None])[0], ref, atol=1e-13)
     np.testing.assert_array_equal(O.optimize_gate(1e-305 * E, u0), u0)
+
+
+# ---------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("n,p", [(2, 1), (2, 3), (3, 4)])
+def test_cost_gradient_is_brute_force_derivative(n, p):
+    """Central differences of the cost (dense circuit product) over the real
+    and imaginary part of every gate entry."""
+    rng = np.random.default_rng(900 + 10 * n + p)
+    locs = rand_locs(n, p, rng)
+    V = haar(1 << n, rng)
+    g = rand_gates(p, rng)
+    c, G = O.cost_gradient(V, g, locs, n)
+    assert abs(c - O.cost(V, g, locs, n)) < 1e-14
+    h = 1e-6
+    for k in range(p):
+        for i in range(4):
+            for j in range(4):
+                for unit in (1.0, 1j):
+                    gp, gm = g.copy(), g.copy()
+                    gp[k, i, j] += h * unit
+                    gm[k, i, j] -= h * unit
+                    fd = (O.cost(V, gp, locs, n) - O.cost(V, gm, locs, n)) / (2 * h)
+                    an = G[k, i, j].real if unit == 1.0 else G[k, i, j].imag
+                    assert abs(fd - an) < 1e-8, (k, i, j, unit)
+
+
+def test_cost_gradient_matches_torch_autograd_convention():
+    """The packed gradient equals what torch's autograd accumulates for complex
+    leaves (x-derivative + 1j y-derivative) on an independent dense torch
+    construction of the cost (Kronecker products, n = 3)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(910)
+    locs = [(0, 1), (1, 2), (0, 1)]
+    V = haar(8, rng)
+    g = rand_gates(3, rng)
+    us = [torch.tensor(g[k], dtype=torch.complex128, requires_grad=True) for k in range(3)]
+    I2 = torch.eye(2, dtype=torch.complex128)
+    C = torch.eye(8, dtype=torch.complex128)
+    for u, loc in zip(us, locs):
+        M = torch.kron(u, I2) if loc == (0, 1) else torch.kron(I2, u)
+        C = M @ C
+    L = 1.0 - torch.abs(torch.trace(torch.tensor(V).conj().T @ C)) / 8
+    L.backward()
+    c, G = O.cost_gradient(V, g, locs, 3)
+    assert abs(float(L.detach()) - c) < 1e-14
+    for k in range(3):
+        assert np.abs(us[k].grad.numpy() - G[k]).max() < 1e-13
+
+
+def test_gradient_flat_along_gate_phase():
+    """A global phase on one gate leaves |Tr| unchanged: Re Tr(G^dagger i u) = 0."""
+    rng = np.random.default_rng(920)
+    n, p = 3, 5
+    locs = rand_locs(n, p, rng)
+    V = haar(8, rng)
+    g = rand_gates(p, rng)
+    _, G = O.cost_gradient(V, g, locs, n)
+    for k in range(p):
+        assert abs(np.real(np.vdot(G[k], 1j * g[k]))) < 1e-14
+
+
+def test_riemannian_gradient_vanishes_at_solution():
+    """At the global minimum (target = own circuit) every tangent direction
+    u (iK), K Hermitian, has zero derivative; away from it some does not."""
+    rng = np.random.default_rng(930)
+    n, p = 3, 4
+    locs = rand_locs(n, p, rng)
+    g = rand_gates(p, rng)
+    V = O.circuit_unitary(g, locs, n)
+    basis = [np.eye(4, dtype=np.complex128)] + list(O.PAULI2)
+    c, G = O.cost_gradient(V, g, locs, n)
+    assert c < 1e-14
+    assert max(abs(np.real(np.vdot(G[k], g[k] @ (1j * K)))) for k in range(p) for K in basis) < 1e-14
+    g2 = rand_gates(p, rng)
+    _, G2 = O.cost_gradient(V, g2, locs, n)
+    assert max(abs(np.real(np.vdot(G2[k], g2[k] @ (1j * K)))) for k in range(p) for K in basis) > 1e-3
+
+
+def test_su4_closed_forms():
+    """exp(i t P) = cos t I + i sin t P for a Pauli product P (P^2 = I);
+    theta = 0 gives I; every gate is unitary with determinant 1."""
+    rng = np.random.default_rng(940)
+    for k in range(15):
+        t = float(rng.uniform(-3, 3))
+        th = np.zeros(15)
+        th[k] = t
+        U = O.su4_gate(th)
+        assert np.abs(U - (np.cos(t) * np.eye(4) + 1j * np.sin(t) * O.PAULI2[k])).max() < 1e-14
+    assert np.abs(O.su4_gate(np.zeros(15)) - np.eye(4)).max() == 0
+    th = rng.normal(size=(6, 15))
+    U = O.su4_gate(th)
+    for u in U:
+        assert np.abs(u.conj().T @ u - np.eye(4)).max() < 1e-13
+        assert abs(np.linalg.det(u) - 1) < 1e-13
+    # the 15 Pauli products are orthogonal, Hermitian and traceless
+    P = O.PAULI2
+    assert np.abs(np.einsum("aij,bji->ab", P, P) - 4 * np.eye(15)).max() == 0
+    assert np.abs(P - np.conj(np.swapaxes(P, -1, -2))).max() == 0
+
+
+def test_su4_theta_gradient_finite_differences():
+    rng = np.random.default_rng(950)
+    th = rng.normal(size=(3, 15))
+    G = rng.normal(size=(3, 4, 4)) + 1j * rng.normal(size=(3, 4, 4))
+    d = O.su4_theta_gradient(th, G)
+    h = 1e-6
+    for i in range(3):
+        for k in range(15):
+            tp, tm = th[i].copy(), th[i].copy()
+            tp[k] += h
+            tm[k] -= h
+            fd = (np.real(np.vdot(G[i], O.su4_gate(tp))) - np.real(np.vdot(G[i], O.su4_gate(tm)))) / (2 * h)
+            assert abs(fd - d[i, k]) < 1e-8, (i, k)
+
+
+def test_param_cost_gradient_finite_differences():
+    rng = np.random.default_rng(960)
+    n, p = 3, 3
+    locs = rand_locs(n, p, rng)
+    V = haar(8, rng)
+    th = rng.normal(size=(p, 15))
+    c, d = O.param_cost_gradient(V, th, locs, n)
+    h = 1e-6
+    for g in range(p):
+        for k in range(15):
+            tp, tm = th.copy(), th.copy()
+            tp[g, k] += h
+            tm[g, k] -= h
+            fd = (O.cost(V, O.su4_gate(tp), locs, n) - O.cost(V, O.su4_gate(tm), locs, n)) / (2 * h)
+            assert abs(fd - d[g, k]) < 1e-8, (g, k)
