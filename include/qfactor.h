@@ -264,6 +264,65 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
                          double* out_costs, int32_t* out_best, int32_t* out_status, int32_t* out_sweeps,
                          qf_stats* stats);
 
+/* Cost and gradient of the cost with respect to every gate matrix (the
+ * derivative the gradient-based instantiation optimisers of Sec. II,
+ * "Numerical Optimization in Instantiation", need; cost as in Sec. II).
+ * With T = Tr(V^dagger C) = Tr(E_g u_g) (Sec. III), the real gradient packed
+ * as a complex matrix is
+ *     grad_g = dDelta/dRe u_g + i dDelta/dIm u_g = -(T/|T|) E_g^dagger / N
+ * (zero where T = 0).  All p environments come from one half-sweep of the
+ * builder with the gates held fixed, so memory is one builder per start.
+ *   target:   device, N x N c128;  locations: host, n_gates x 2
+ *   gates:    device, n_starts x n_gates x 4 x 4 c128 (not modified)
+ *   precision QF_C128 or QF_C64 (builder precision; sums and outputs FP64)
+ *   workspace: device, >= qf_gradient_workspace_size(...)
+ *   cost_out: device, n_starts doubles;  grad_out: device, same layout as gates
+ * Work is enqueued on the context's stream; the call does not synchronise. */
+size_t qf_gradient_workspace_size(int n, int n_gates, int n_starts, int precision);
+int qf_gradient(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const void* gates,
+                int n_starts, int precision, void* workspace, size_t ws_bytes, double* cost_out, void* grad_out);
+
+/* Parameterised two-qubit gates of the gradient-based baseline: a gate is
+ * exp(i H(theta)), H = sum_k theta_k P_k over the 15 non-identity Pauli
+ * products P_k = sigma_a (x) sigma_b, k = 4a + b - 1 (sigma_0..3 = I, X, Y,
+ * Z); H is traceless Hermitian so the gate is in SU(4), and a gate's global
+ * phase does not change the cost.  (Sec. VI discusses the parameter counts of
+ * such encodings.)
+ *   qf_su4_gates: theta (device, count x 15 FP64) -> gates (device, count x
+ *                 4 x 4 c128)
+ *   qf_su4_vjp:   grad_gates (device, count x 4 x 4 c128, packed as in
+ *                 qf_gradient) -> dtheta (device, count x 15):
+ *                 dtheta_k = Re Tr(grad^dagger dU/dtheta_k)
+ * Asynchronous on the context's stream. */
+int qf_su4_gates(qf_ctx* ctx, int count, const double* theta, void* gates);
+int qf_su4_vjp(qf_ctx* ctx, int count, const double* theta, const void* grad_gates, double* dtheta);
+
+/* L-BFGS baseline (the gradient-descent comparison optimiser of Sec. II and
+ * Sec. V) over parameterised SU(4) gates, driven by qf_gradient: every
+ * evaluation maps theta to gates, builds the builders, and takes the cost and
+ * the gradient; the two-loop recursion and the backtracking (Armijo) line
+ * search run on the host, all starts in lockstep. */
+typedef struct {
+  int32_t history;   /* correction pairs kept (default 10) */
+  int32_t max_iter;  /* iterations (default 1000) */
+  int32_t max_ls;    /* trial steps per line search (default 30) */
+  double c1;         /* sufficient-decrease constant (default 1e-4) */
+  double grad_tol;   /* a start stops when max |dDelta/dtheta| < grad_tol (default 1e-12) */
+  double ftol_r;     /* ... or when f_{k-1} - f_k <= ftol_r * f_k (default 1e-12) */
+  int32_t precision; /* builder precision, QF_C128 (default) or QF_C64 */
+} qf_lbfgs_options;
+void qf_lbfgs_options_default(qf_lbfgs_options* o);
+size_t qf_lbfgs_workspace_size(int n, int n_gates, int n_starts, const qf_lbfgs_options* opt);
+/* theta0, theta_out: device, n_starts x n_gates x 15 FP64;  out_costs: host,
+ * n_starts final costs.  The job stops when a start's cost falls below tol,
+ * when every start has stopped, or after max_iter iterations.  stats (optional):
+ * sweeps = iterations, best_start, status (QF_CONVERGED / QF_PLATEAU = every
+ * start stopped / QF_MAX_ITER), best_cost, elapsed_ms, cost_history as in
+ * qf_instantiate (rows = iterations + 1), pass_launches = evaluations. */
+int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const double* theta0,
+             int n_starts, double tol, const qf_lbfgs_options* opt, void* workspace, size_t ws_bytes,
+             double* theta_out, double* out_costs, qf_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,13 +9,14 @@ import importlib
 
 from ._native import (  # noqa: F401
     QF_C128, QF_C64, QF_MODE_AUTO, QF_MODE_RESIDENT, QF_MODE_STREAMING, QF_LEFT, QF_RIGHT,
-    QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC, QfError, QfOptions, QfStats, load,
+    QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC, QfError, QfOptions, QfStats, QfLbfgsOptions, load,
 )
 from .hipbuild import build as build_library, lib_path  # noqa: F401
 
 _API = ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "cost", "instantiate",
         "default_options", "workspace_size", "Result", "instantiate_batch", "pack_batch",
-        "batch_workspace_size", "BatchResult")
+        "batch_workspace_size", "BatchResult", "gradient", "cost_fn", "su4_gates", "su4_vjp", "su4",
+        "lbfgs", "lbfgs_options", "LbfgsResult")
 
 
 def __getattr__(name):

@@ -17,6 +17,8 @@ EXPORTED = [
     "qf_create", "qf_destroy", "qf_set_stream", "qf_strerror", "qf_last_error", "qf_options_default",
     "qf_workspace_size", "qf_build", "qf_apply_gate", "qf_environment", "qf_optimize_gate",
     "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
+    "qf_gradient_workspace_size", "qf_gradient", "qf_su4_gates", "qf_su4_vjp", "qf_lbfgs_options_default",
+    "qf_lbfgs_workspace_size", "qf_lbfgs",
 ]
 
 
@@ -60,6 +62,18 @@ class QfStats(ctypes.Structure):
     ]
 
 
+class QfLbfgsOptions(ctypes.Structure):
+    _fields_ = [
+        ("history", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("max_ls", ctypes.c_int32),
+        ("c1", ctypes.c_double),
+        ("grad_tol", ctypes.c_double),
+        ("ftol_r", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+    ]
+
+
 _VP = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -88,6 +102,17 @@ _SIGS = {
     "qf_instantiate_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32P, _I32P, _I32P, _VP, _VP, ctypes.c_int,
                                             ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _VP,
                                             _DP, _I32P, _I32P, _I32P, ctypes.POINTER(QfStats)]),
+    "qf_gradient_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "qf_gradient": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int, ctypes.c_int,
+                                   _VP, ctypes.c_size_t, _VP, _VP]),
+    "qf_su4_gates": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
+    "qf_su4_vjp": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "qf_lbfgs_options_default": (None, [ctypes.POINTER(QfLbfgsOptions)]),
+    "qf_lbfgs_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.POINTER(QfLbfgsOptions)]),
+    "qf_lbfgs": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(QfLbfgsOptions), _VP, ctypes.c_size_t, _VP, _DP,
+                                ctypes.POINTER(QfStats)]),
 }
 
 _lib = None

@@ -300,3 +300,156 @@ def instantiate_batch(block_n, gate_offsets, locations, targets: torch.Tensor, i
     nat.check(rc, ctx)
     return BatchResult(out_gates, go, n_starts, costs[:nb], best[:nb], status[:nb], sweeps[:nb], st.elapsed_ms,
                        st.sweep_ms)
+
+
+# ------------------------------------------------------------------ gradient
+
+def _gates4(gates: torch.Tensor) -> tuple[torch.Tensor, bool]:
+    if gates.dim() == 3:
+        return gates.unsqueeze(0), True
+    return gates, False
+
+
+def gradient(target: torch.Tensor, locs, gates: torch.Tensor, precision: int = nat.QF_C128,
+             workspace: torch.Tensor | None = None):
+    """Cost and gate gradient (qf_gradient): gates (S, p, 4, 4) or (p, 4, 4)
+    complex128; returns cost (S,) float64 and grad (same shape as gates),
+    grad = dDelta/dRe u + i dDelta/dIm u."""
+    g4, squeeze = _gates4(gates)
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 2)
+    S, p = g4.shape[0], g4.shape[1]
+    _c128(target, (N, N))
+    _c128(g4, (S, p, 4, 4))
+    lib = nat.load()
+    need = int(lib.qf_gradient_workspace_size(n, p, S, precision)) or 1
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
+    cost_t = torch.empty((S,), dtype=torch.float64, device=target.device)
+    grad = torch.empty_like(g4)
+    ctx = _ctx(target.device)
+    nat.check(lib.qf_gradient(ctx, n, _ptr(target), p, _loc(locs), _ptr(g4), S, precision, _ptr(workspace), need,
+                              _ptr(cost_t), _ptr(grad)), ctx)
+    if squeeze:
+        return cost_t[0], grad[0]
+    return cost_t, grad
+
+
+class _CostFn(torch.autograd.Function):
+    """Delta(gates) with the backward from qf_gradient (forward and gradient
+    are taken together; the gradient is kept for the backward)."""
+
+    @staticmethod
+    def forward(ctx, gates, target, locs, precision):
+        c, G = gradient(target, locs, gates.detach(), precision)
+        ctx.save_for_backward(G)
+        return c
+
+    @staticmethod
+    def backward(ctx, gout):
+        (G,) = ctx.saved_tensors
+        shape = (-1,) + (1,) * (G.dim() - 1) if G.dim() == 4 else ()
+        return gout.reshape(shape).to(G.dtype) * G, None, None, None
+
+
+def cost_fn(gates: torch.Tensor, target: torch.Tensor, locs, precision: int = nat.QF_C128) -> torch.Tensor:
+    """Differentiable cost: gates (S, p, 4, 4) -> (S,) (or (p, 4, 4) -> scalar)."""
+    return _CostFn.apply(gates, target, np.asarray(locs, np.int32).reshape(-1, 2), precision)
+
+
+def su4_gates(theta: torch.Tensor) -> torch.Tensor:
+    """exp(i H(theta)) for theta (..., 15) float64 on the GPU (qf_su4_gates)."""
+    th = theta.contiguous()
+    if th.dtype != torch.float64:
+        raise TypeError("theta must be float64")
+    count = th.numel() // 15
+    out = torch.empty(th.shape[:-1] + (4, 4), dtype=torch.complex128, device=th.device)
+    ctx = _ctx(th.device)
+    nat.check(nat.load().qf_su4_gates(ctx, count, _ptr(th), _ptr(out)), ctx)
+    return out
+
+
+def su4_vjp(theta: torch.Tensor, grad_gates: torch.Tensor) -> torch.Tensor:
+    """dtheta_k = Re Tr(grad^dagger dU/dtheta_k) (qf_su4_vjp)."""
+    th = theta.contiguous()
+    gg = grad_gates.contiguous().to(torch.complex128)
+    count = th.numel() // 15
+    out = torch.empty_like(th)
+    ctx = _ctx(th.device)
+    nat.check(nat.load().qf_su4_vjp(ctx, count, _ptr(th), _ptr(gg), _ptr(out)), ctx)
+    return out
+
+
+class _SU4Fn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta):
+        ctx.save_for_backward(theta)
+        return su4_gates(theta.detach())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (theta,) = ctx.saved_tensors
+        return su4_vjp(theta.detach(), gout)
+
+
+def su4(theta: torch.Tensor) -> torch.Tensor:
+    """Differentiable theta -> exp(i H(theta))."""
+    return _SU4Fn.apply(theta)
+
+
+def lbfgs_options(**kw) -> nat.QfLbfgsOptions:
+    o = nat.QfLbfgsOptions()
+    nat.load().qf_lbfgs_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class LbfgsResult:
+    theta: torch.Tensor      # (S, p, 15)
+    costs: np.ndarray        # (S,)
+    best_start: int
+    iterations: int
+    status: int
+    evaluations: int
+    elapsed_ms: float
+    history: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+
+
+def lbfgs(target: torch.Tensor, locs, theta0: torch.Tensor, tol: float = 1e-10, history_rows: int = 0,
+          options: nat.QfLbfgsOptions | None = None, **kw) -> LbfgsResult:
+    """L-BFGS over parameterised SU(4) gates (qf_lbfgs); theta0 (S, p, 15)."""
+    opt = options if options is not None else lbfgs_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    th = theta0.contiguous()
+    if th.dim() == 2:
+        th = th.unsqueeze(0)
+    if th.dtype != torch.float64:
+        raise TypeError("theta0 must be float64")
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 2)
+    S, p = th.shape[0], th.shape[1]
+    _c128(target, (N, N))
+    lib = nat.load()
+    need = int(lib.qf_lbfgs_workspace_size(n, p, S, ctypes.byref(opt))) or 1
+    workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
+    out = torch.empty_like(th)
+    costs = (ctypes.c_double * S)()
+    st = nat.QfStats()
+    hist = None
+    if history_rows > 0:
+        hist = np.full((history_rows, S), np.nan, dtype=np.float64)
+        st.cost_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st.cost_history_rows = history_rows
+    ctx = _ctx(target.device)
+    nat.check(lib.qf_lbfgs(ctx, n, _ptr(target), p, _loc(locs), _ptr(th), S, float(tol), ctypes.byref(opt),
+                           _ptr(workspace), need, _ptr(out), costs, ctypes.byref(st)), ctx)
+    h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
+    return LbfgsResult(out, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.pass_launches,
+                       st.elapsed_ms, h)

@@ -713,6 +713,89 @@ int validate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, const int3
   return QF_OK;
 }
 
+// Workspace layout of qf_gradient.
+struct GradLayout {
+  size_t X = 0, partials = 0, counters = 0, envP = 0, trace = 0, total = 0;
+};
+
+GradLayout make_grad_layout(int n, int p, int S, int precision) {
+  GradLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t N = (size_t)1 << n;
+  L.X = take((size_t)S * N * N * elem_bytes(precision));
+  L.partials = take((size_t)S * env_workgroups(n) * 16 * 16);
+  L.counters = take((size_t)S * 4);
+  L.envP = take((size_t)p * S * 16 * 16);
+  L.trace = take((size_t)S * 16);
+  L.total = off;
+  return L;
+}
+
+// Cost and gate gradient of S starts (gates: device S x p x 16 c128).
+int run_gradient(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, const double* gates, int S,
+                 int prec, unsigned char* ws, const GradLayout& L, double* cost_out, double* grad_out) {
+  hipStream_t st = ctx->stream;
+  void* X = ws + L.X;
+  const int64_t gstride = (int64_t)p * 16;
+  double* envP = reinterpret_cast<double*>(ws + L.envP);
+  double* trace = reinterpret_cast<double*>(ws + L.trace);
+  int32_t* counters = reinterpret_cast<int32_t*>(ws + L.counters);
+  QF_HIP(ctx, launch_fill_i32(st, counters, 0, (uint32_t)S));
+  int rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, prec, X);
+  if (rc) return rc;
+  QF_HIP(ctx, launch_cost(st, prec, X, n, S, cost_out, trace));
+  EnvArgs ea{};
+  ea.n = n;
+  ea.S = S;
+  ea.do_update = 0;
+  ea.partials = reinterpret_cast<double*>(ws + L.partials);
+  ea.counters = counters;
+  for (int g = p - 1; g >= 0; --g) {
+    ea.q0 = locs[2 * g];
+    ea.q1 = locs[2 * g + 1];
+    ea.env_out = envP + (size_t)g * S * 32;
+    QF_HIP(ctx, launch_env(st, prec, X, ea));
+    if (g > 0) {  // move u_g to the input legs; the last move is not needed
+      const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n));
+      Operand ud{gates + 2 * 16 * (int64_t)g, gstride, 1};
+      Operand u{gates + 2 * 16 * (int64_t)g, gstride, 0};
+      QF_HIP(ctx, launch_pass(st, prec, X, S, geo, ud, u));
+    }
+  }
+  QF_HIP(ctx, launch_grad_finish(st, envP, gates, trace, n, S, p, grad_out));
+  return QF_OK;
+}
+
+// Workspace layout of qf_lbfgs: the gradient's, plus gates, gate gradients,
+// trial parameters, parameter gradients and costs of every start.
+struct LbfgsLayout {
+  GradLayout G;
+  size_t gates = 0, ggrad = 0, theta = 0, dtheta = 0, costs = 0, total = 0;
+};
+
+LbfgsLayout make_lbfgs_layout(int n, int p, int S, int precision) {
+  LbfgsLayout L;
+  L.G = make_grad_layout(n, p, S, precision);
+  size_t off = L.G.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.gates = take((size_t)S * p * 256);
+  L.ggrad = take((size_t)S * p * 256);
+  L.theta = take((size_t)S * p * 15 * 8);
+  L.dtheta = take((size_t)S * p * 15 * 8);
+  L.costs = take((size_t)S * 8);
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1148,6 +1231,286 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
     if (timed) QF_HIP(ctx, hipEventElapsedTime(&kms, ev[0], ev[1]));
     stats->sweep_ms = kms;
     stats->pass_tcols = 0;
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return QF_OK;
+}
+
+size_t qf_gradient_workspace_size(int n, int n_gates, int n_starts, int precision) {
+  if (n < 2 || n > 16 || n_gates < 1 || n_starts < 1) return 0;
+  if (precision != QF_C128 && precision != QF_C64) return 0;
+  return make_grad_layout(n, n_gates, n_starts, precision).total;
+}
+
+int qf_gradient(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const void* gates,
+                int n_starts, int precision, void* workspace, size_t ws_bytes, double* cost_out, void* grad_out) {
+  if (!ctx) return QF_EINVAL;
+  int rc = validate_problem(ctx, n, n_gates, locations, n_starts);
+  if (rc) return rc;
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (!target || !gates || !cost_out || !grad_out) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  const GradLayout L = make_grad_layout(n, n_gates, n_starts, precision);
+  if (!workspace || ws_bytes < L.total)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  return run_gradient(ctx, n, target, n_gates, locations, reinterpret_cast<const double*>(gates), n_starts,
+                      precision, reinterpret_cast<unsigned char*>(workspace), L, cost_out,
+                      reinterpret_cast<double*>(grad_out));
+}
+
+int qf_su4_gates(qf_ctx* ctx, int count, const double* theta, void* gates) {
+  if (!ctx) return QF_EINVAL;
+  if (count < 1) return fail(ctx, QF_EINVAL, "count must be >= 1");
+  if (!theta || !gates) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  DeviceGuard dg(ctx->device);
+  QF_HIP(ctx, launch_su4_expm(ctx->stream, theta, count, reinterpret_cast<double*>(gates)));
+  return QF_OK;
+}
+
+int qf_su4_vjp(qf_ctx* ctx, int count, const double* theta, const void* grad_gates, double* dtheta) {
+  if (!ctx) return QF_EINVAL;
+  if (count < 1) return fail(ctx, QF_EINVAL, "count must be >= 1");
+  if (!theta || !grad_gates || !dtheta) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  DeviceGuard dg(ctx->device);
+  QF_HIP(ctx, launch_su4_vjp(ctx->stream, theta, reinterpret_cast<const double*>(grad_gates), count, dtheta));
+  return QF_OK;
+}
+
+void qf_lbfgs_options_default(qf_lbfgs_options* o) {
+  if (!o) return;
+  o->history = 10;
+  o->max_iter = 1000;
+  o->max_ls = 30;
+  o->c1 = 1e-4;
+  o->grad_tol = 1e-12;
+  o->ftol_r = 1e-12;
+  o->precision = QF_C128;
+}
+
+size_t qf_lbfgs_workspace_size(int n, int n_gates, int n_starts, const qf_lbfgs_options* opt) {
+  qf_lbfgs_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_lbfgs_options_default(&o);
+  if (n < 2 || n > 16 || n_gates < 1 || n_starts < 1) return 0;
+  if (o.precision != QF_C128 && o.precision != QF_C64) return 0;
+  return make_lbfgs_layout(n, n_gates, n_starts, o.precision).total;
+}
+
+int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const double* theta0,
+             int n_starts, double tol, const qf_lbfgs_options* opt, void* workspace, size_t ws_bytes,
+             double* theta_out, double* out_costs, qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  qf_lbfgs_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_lbfgs_options_default(&o);
+  const int p = n_gates, S = n_starts;
+  int rc = validate_problem(ctx, n, p, locations, S);
+  if (rc) return rc;
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, QF_EINVAL, "tol must be finite and > 0");
+  if (o.history < 1 || o.history > 1000) return fail(ctx, QF_EINVAL, "history must be in [1, 1000]");
+  if (o.max_iter < 0 || o.max_ls < 1) return fail(ctx, QF_EINVAL, "max_iter must be >= 0 and max_ls >= 1");
+  if (!(o.c1 > 0 && o.c1 < 1)) return fail(ctx, QF_EINVAL, "c1 must be in (0, 1)");
+  if (!(o.grad_tol >= 0) || !(o.ftol_r >= 0)) return fail(ctx, QF_EINVAL, "grad_tol and ftol_r must be >= 0");
+  if (o.precision != QF_C128 && o.precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (!target || !theta0 || !theta_out || !out_costs) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (stats && stats->cost_history && stats->cost_history_rows < 0)
+    return fail(ctx, QF_EINVAL, "cost_history_rows must be >= 0");
+  const LbfgsLayout L = make_lbfgs_layout(n, p, S, o.precision);
+  if (!workspace || ws_bytes < L.total)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = ctx->stream;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  double* d_gates = reinterpret_cast<double*>(ws + L.gates);
+  double* d_ggrad = reinterpret_cast<double*>(ws + L.ggrad);
+  double* d_theta = reinterpret_cast<double*>(ws + L.theta);
+  double* d_dtheta = reinterpret_cast<double*>(ws + L.dtheta);
+  double* d_costs = reinterpret_cast<double*>(ws + L.costs);
+  const size_t D = (size_t)p * 15;  // parameters per start
+  const size_t nd = D * S;
+  int evals = 0;
+
+  // f and grad of every start at the parameters in d_theta (host copies out)
+  std::vector<double> hf(S), hg(nd);
+  auto evaluate = [&](const std::vector<double>& x) -> int {
+    QF_HIP(ctx, hipMemcpyAsync(d_theta, x.data(), nd * 8, hipMemcpyHostToDevice, st));
+    QF_HIP(ctx, launch_su4_expm(st, d_theta, S * p, d_gates));
+    int r2 = run_gradient(ctx, n, target, p, locations, d_gates, S, o.precision, ws, L.G, d_costs, d_ggrad);
+    if (r2) return r2;
+    QF_HIP(ctx, launch_su4_vjp(st, d_theta, d_ggrad, S * p, d_dtheta));
+    QF_HIP(ctx, hipMemcpyAsync(hf.data(), d_costs, (size_t)S * 8, hipMemcpyDeviceToHost, st));
+    QF_HIP(ctx, hipMemcpyAsync(hg.data(), d_dtheta, nd * 8, hipMemcpyDeviceToHost, st));
+    QF_HIP(ctx, hipStreamSynchronize(st));
+    ++evals;
+    return QF_OK;
+  };
+  auto dot = [&](const double* a, const double* b) {
+    double acc = 0.0;
+    for (size_t k = 0; k < D; ++k) acc += a[k] * b[k];
+    return acc;
+  };
+
+  std::vector<double> x(nd), g(nd), xt(nd), d(nd);
+  QF_HIP(ctx, hipMemcpyAsync(x.data(), theta0, nd * 8, hipMemcpyDeviceToHost, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  if ((rc = evaluate(x))) return rc;
+  std::vector<double> f = hf;
+  g = hg;
+  for (int s = 0; s < S; ++s)
+    if (!std::isfinite(f[s])) f[s] = INFINITY;
+  // Per-start history (ring of s = x_{k+1} - x_k, y = g_{k+1} - g_k, rho).
+  const int m = o.history;
+  std::vector<std::vector<double>> sh(S, std::vector<double>((size_t)m * D)), yh(S, std::vector<double>((size_t)m * D));
+  std::vector<std::vector<double>> rho(S, std::vector<double>(m, 0.0));
+  std::vector<int> cnt(S, 0), head(S, 0);
+  std::vector<char> active(S, 1);
+  auto record = [&](int row) {
+    if (stats && stats->cost_history && row < stats->cost_history_rows)
+      for (int s = 0; s < S; ++s) stats->cost_history[(size_t)row * S + s] = f[s];
+  };
+  record(0);
+  for (int s = 0; s < S; ++s) active[s] = std::isfinite(f[s]) ? 1 : 0;
+  int it = 0, status = QF_MAX_ITER;
+  std::vector<double> alpha(S), gd(S), fnew(S);
+  std::vector<char> done_ls(S);
+  auto any_converged = [&]() {
+    for (int s = 0; s < S; ++s)
+      if (f[s] < tol) return true;
+    return false;
+  };
+  if (any_converged()) status = QF_CONVERGED;
+  while (status == QF_MAX_ITER && it < o.max_iter) {
+    bool any_active = false;
+    for (int s = 0; s < S; ++s) any_active = any_active || active[s];
+    if (!any_active) {
+      status = QF_PLATEAU;
+      break;
+    }
+    ++it;
+    // two-loop recursion: d = -H g
+    for (int s = 0; s < S; ++s) {
+      double* ds = d.data() + s * D;
+      const double* gs = g.data() + s * D;
+      if (!active[s]) {
+        std::fill(ds, ds + D, 0.0);
+        continue;
+      }
+      for (size_t k = 0; k < D; ++k) ds[k] = -gs[k];
+      std::vector<double> a(cnt[s]);
+      for (int j = 0; j < cnt[s]; ++j) {
+        const int slot = (head[s] - 1 - j + m) % m;
+        a[j] = rho[s][slot] * dot(&sh[s][(size_t)slot * D], ds);
+        const double* yv = &yh[s][(size_t)slot * D];
+        for (size_t k = 0; k < D; ++k) ds[k] -= a[j] * yv[k];
+      }
+      if (cnt[s] > 0) {
+        const int last = (head[s] - 1 + m) % m;
+        const double* yv = &yh[s][(size_t)last * D];
+        const double gamma = 1.0 / (rho[s][last] * dot(yv, yv));
+        for (size_t k = 0; k < D; ++k) ds[k] *= gamma;
+      }
+      for (int j = cnt[s] - 1; j >= 0; --j) {
+        const int slot = (head[s] - 1 - j + m) % m;
+        const double b = rho[s][slot] * dot(&yh[s][(size_t)slot * D], ds);
+        const double* sv = &sh[s][(size_t)slot * D];
+        for (size_t k = 0; k < D; ++k) ds[k] += (a[j] - b) * sv[k];
+      }
+      gd[s] = dot(gs, ds);
+      if (!(gd[s] < 0.0)) {  // not a descent direction: restart from steepest descent
+        cnt[s] = head[s] = 0;
+        for (size_t k = 0; k < D; ++k) ds[k] = -gs[k];
+        gd[s] = dot(gs, ds);
+      }
+      double gn = 0.0;
+      for (size_t k = 0; k < D; ++k) gn = std::max(gn, std::fabs(gs[k]));
+      alpha[s] = (cnt[s] == 0) ? std::min(1.0, 1.0 / std::max(gn, 1e-300)) : 1.0;
+      done_ls[s] = 0;
+    }
+    // backtracking line search, all starts in lockstep
+    std::vector<double> gnew(nd);
+    std::vector<double> xnew = x;
+    for (int s = 0; s < S; ++s) done_ls[s] = active[s] ? 0 : 1;
+    for (int ls = 0; ls < o.max_ls; ++ls) {
+      bool pending = false;
+      for (int s = 0; s < S; ++s) {
+        if (done_ls[s]) continue;
+        pending = true;
+        for (size_t k = 0; k < D; ++k) xt[s * D + k] = x[s * D + k] + alpha[s] * d[s * D + k];
+      }
+      if (!pending) break;
+      for (int s = 0; s < S; ++s)
+        if (done_ls[s])
+          for (size_t k = 0; k < D; ++k) xt[s * D + k] = xnew[s * D + k];
+      if ((rc = evaluate(xt))) return rc;
+      for (int s = 0; s < S; ++s) {
+        if (done_ls[s]) continue;
+        const double ft = std::isfinite(hf[s]) ? hf[s] : INFINITY;
+        if (ft <= f[s] + o.c1 * alpha[s] * gd[s]) {
+          done_ls[s] = 2;  // accepted
+          fnew[s] = ft;
+          std::copy(xt.begin() + s * D, xt.begin() + (s + 1) * D, xnew.begin() + s * D);
+          std::copy(hg.begin() + s * D, hg.begin() + (s + 1) * D, gnew.begin() + s * D);
+        } else {
+          alpha[s] *= 0.5;
+        }
+      }
+    }
+    for (int s = 0; s < S; ++s) {
+      if (!active[s]) continue;
+      if (done_ls[s] != 2) {  // no sufficient decrease: this start stops
+        active[s] = 0;
+        continue;
+      }
+      double sy = 0.0, yy = 0.0, gmax = 0.0;
+      const int slot = head[s];
+      double* sv = &sh[s][(size_t)slot * D];
+      double* yv = &yh[s][(size_t)slot * D];
+      for (size_t k = 0; k < D; ++k) {
+        sv[k] = xnew[s * D + k] - x[s * D + k];
+        yv[k] = gnew[s * D + k] - g[s * D + k];
+        sy += sv[k] * yv[k];
+        yy += yv[k] * yv[k];
+        gmax = std::max(gmax, std::fabs(gnew[s * D + k]));
+      }
+      if (sy > 1e-300 && yy > 0.0) {  // keep the pair only with positive curvature
+        rho[s][slot] = 1.0 / sy;
+        head[s] = (head[s] + 1) % m;
+        cnt[s] = std::min(cnt[s] + 1, m);
+      }
+      const double fprev = f[s];
+      f[s] = fnew[s];
+      std::copy(xnew.begin() + s * D, xnew.begin() + (s + 1) * D, x.begin() + s * D);
+      std::copy(gnew.begin() + s * D, gnew.begin() + (s + 1) * D, g.begin() + s * D);
+      if (gmax < o.grad_tol || fprev - f[s] <= o.ftol_r * f[s]) active[s] = 0;
+    }
+    record(it);
+    if (any_converged()) status = QF_CONVERGED;
+  }
+  int best = 0;
+  for (int s = 0; s < S; ++s) {
+    out_costs[s] = f[s];
+    if (f[s] < f[best]) best = s;
+  }
+  QF_HIP(ctx, hipMemcpyAsync(theta_out, x.data(), nd * 8, hipMemcpyHostToDevice, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  if (status != QF_CONVERGED && f[best] < tol) status = QF_CONVERGED;
+  if (stats) {
+    stats->sweeps = it;
+    stats->best_start = best;
+    stats->status = status;
+    stats->n_resets = 0;
+    stats->n_rechecks = 0;
+    stats->mode_used = QF_MODE_STREAMING;
+    stats->best_cost = f[best];
+    stats->pass_launches = evals;
+    stats->env_launches = 0;
+    stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
+    stats->pass_tcols = pass_tcols(ctx, o.precision, n);
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;

@@ -124,6 +124,13 @@ constexpr int kBatchMaxGrid = 2048;
 int batch_groups(int n_blocks, int S);
 int batch_grid(int precision, int n_groups);  // workgroups to launch (device occupancy)
 size_t batch_scratch_entries(int grid);       // c128 scratch entries for `grid` workgroups
+
+// Gradient (qf_grad.hip).
+hipError_t launch_grad_finish(hipStream_t st, const double* envP, const double* gates, const double* trace, int n,
+                              int S, int p, double* grad);
+hipError_t launch_su4_expm(hipStream_t st, const double* theta, int count, double* gates);
+hipError_t launch_su4_vjp(hipStream_t st, const double* theta, const double* grad_gates, int count,
+                          double* dtheta);
 hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs& a);
 size_t resident_lds_bytes(int n, int precision);
 
