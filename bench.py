@@ -13,10 +13,12 @@ Extra workloads are reported in the same line: the complex128 form of the same
 problem, n = 12 (44 gates, one start, 4096 x 4096 builder) in both precisions,
 full n = 6 / n = 3 instantiations (converged instantiations per second), and
 the batched workload of 4096 independent 3- and 4-qubit blocks x 8 starts in
-one persistent launch (converged blocks per second).
+one persistent launch (converged blocks per second), and at n = 12 the
+gradient (evaluations per second) and the L-BFGS baseline against QFactor
+sweeps from the same initial circuit.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
-                       [--probe copy|batch]
+                       [--probe copy|batch|gradient]
 """
 from __future__ import annotations
 
@@ -63,9 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy", "batch"], default=None,
+    ap.add_argument("--probe", choices=["copy", "batch", "gradient"], default=None,
                     help="copy: only a plain device copy of known size (traffic-counter calibration); "
-                         "batch: only the 4096-block batched workload")
+                         "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
+                         "and L-BFGS workload")
     return ap.parse_args()
 
 
@@ -155,6 +158,45 @@ def batch_workload(qf, torch) -> dict:
     return out
 
 
+def gradient_workload(qf, torch) -> dict:
+    """n = 12 brick-wall of depth 8 (44 gates), one start: gradient
+    evaluations per second (one half-sweep each) in both precisions, and the
+    L-BFGS baseline over SU(4)-parameterised gates against QFactor sweeps from
+    the same initial circuit and target, 30 iterations / sweeps each."""
+    import qfinputs as I
+    pr = I.config5(n_starts=1, build_target=False)
+    V = torch.from_numpy(I.circuit_unitary(pr.target_gates, pr.locs, 12)).to("cuda")
+    th0 = torch.from_numpy(I.su4_params(5, 1, pr.n_gates)).to("cuda")
+    g0 = qf.su4_gates(th0)
+    out = {}
+    for prec, tag in ((1, "c64"), (0, "c128")):
+        qf.gradient(V, pr.locs, g0, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            qf.gradient(V, pr.locs, g0, precision=prec)
+        torch.cuda.synchronize()
+        out[f"n12_{tag}_gradient_evals_per_s"] = round(reps / (time.perf_counter() - t0), 2)
+    iters = 30
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rl = qf.lbfgs(V, pr.locs, th0, tol=1e-8, precision=1, max_iter=iters)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rq = qf.instantiate(V, pr.locs, g0, tol=1e-8, precision=1, max_iter=iters, diff_tol_r=0.0, long_diff_count=0)
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - t0
+    c0, _ = qf.gradient(V, pr.locs, g0)
+    out["n12_lbfgs_vs_qfactor_c64"] = {
+        "initial_cost": float(c0.item()),
+        "lbfgs": {"iterations": rl.iterations, "evaluations": rl.evaluations, "seconds": round(tl, 3),
+                  "cost": float(rl.costs[0])},
+        "qfactor": {"sweeps": rq.sweeps, "seconds": round(tq, 3), "cost": float(rq.costs[0])}}
+    return out
+
+
 def cpu_baseline(n_sweeps=3):
     """The FP64 oracle (builder mode) on the host: 3 sweeps of one start of the
     n = 10 headline problem."""
@@ -195,6 +237,9 @@ def main():
         return
     if args.probe == "batch":
         print(json.dumps(batch_workload(qf, torch)), flush=True)
+        return
+    if args.probe == "gradient":
+        print(json.dumps(gradient_workload(qf, torch)), flush=True)
         return
 
     K, W = max(1, args.steps), max(0, args.warmup)
@@ -292,6 +337,7 @@ def main():
         extra["n3_p4_c128_sweeps_per_s"] = round(r3.sweeps / d3, 1)
         extra["n3_p4_c128_status"] = int(r3.status)
         extra.update(batch_workload(qf, torch))
+        extra.update(gradient_workload(qf, torch))
         out["extra"] = extra
 
     if not args.no_cpu:

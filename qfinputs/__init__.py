@@ -31,6 +31,7 @@ import numpy as np
 ROLE_TARGET = 0
 ROLE_INIT = 1
 ROLE_STRUCTURE = 2
+ROLE_PARAMS = 3
 
 
 def rng_for(config_id: int, role: int, index: int) -> np.random.Generator:
@@ -165,6 +166,14 @@ def config4_blocks(n_blocks: int = C4["blocks"], n_starts: int = C4["starts"], b
         probs.append(make_problem(C4["config_id"], f"block{b}", n, locs, n_starts,
                                   build_target=build_target, block=b))
     return probs
+
+
+def su4_params(config_id: int, n_starts: int, count: int, scale: float = 1.0) -> np.ndarray:
+    """(n_starts, count, 15) Gaussian parameters (standard deviation `scale`)
+    for gates exp(i sum_k theta_k P_k); start s draws from stream
+    (role 3, index s)."""
+    return np.stack([scale * rng_for(config_id, ROLE_PARAMS, s).standard_normal((count, 15))
+                     for s in range(n_starts)])
 
 
 def random_builder(rng: np.random.Generator, n_starts: int, n: int) -> np.ndarray:
