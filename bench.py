@@ -276,10 +276,11 @@ def main():
                    "starts": S, "builder": "1024x1024 complex64 per start", "parallelism": "multistarts"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_pass<float,true,true> (fused remove + re-apply, one read + one write of "
-                               "all 16 builders per launch)",
+                     "kernel": "fused remove + re-apply pass, complex64, 16 builders per launch (register-direct "
+                               "k_pass_block or LDS-tiled k_pass, as tuned per gate class); one read + one write of "
+                               "every builder entry",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
-                     "launches_timed": tm["pass_launches"], "tile_columns": tm.get("pass_tcols"),
+                     "launches_timed": tm["pass_launches"], "pass_form_mid_gate": tm.get("pass_tcols"),
                      "traffic_source": "profiles/k_pass_n10_s16_c64_traffic.json (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
                                        "scaled by a 256 MiB copy)"},
         "breakdown": {"pass_avg_us": round(1e3 * pass_avg_ms, 2), "env_svd_avg_us": round(env_avg_us, 2),

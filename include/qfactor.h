@@ -140,8 +140,10 @@ typedef struct {
   double pass_ms;        /* out (timing): summed durations of those passes */
   double env_ms;         /* out (timing): summed durations of those launches */
   double sweep_ms;       /* out (timing): device time of the sweep loop */
-  int32_t pass_tcols;    /* out: tile width (columns) of the fused pass, chosen
-                            on first use per (precision, n) by timing the
+  int32_t pass_tcols;    /* out: form of the fused pass at a mid-circuit gate:
+                            tile width (columns) of the LDS-staged pass, or -1
+                            for the register-direct pass; chosen on first use
+                            per (precision, gate class, n) by timing the
                             candidates on the caller's builder */
 } qf_stats;
 
@@ -234,6 +236,18 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
                    const void* init_gates, int n_starts, double tol, const qf_options* opt,
                    void* workspace, size_t ws_bytes, void* out_gates, void* out_all_gates,
                    double* out_costs, qf_stats* stats);
+
+/* Form of the fused remove/re-apply pass (the hot loop of every gate update,
+ * Alg. 1) used for builders of n qubits in `precision`, for one class of
+ * gates: gate_class 0 = the higher of the gate's two column bits (bit
+ * n-1-q of a qubit q) is >= 3, gate_class 1 = both bits are among the three
+ * lowest.  tile: -1 = register-direct pass, one 4x4 block per thread (needs
+ * n >= 6, else the 512-column tile is used), 256 / 512 / 1024 (1024: QF_C64
+ * only) = columns of the LDS-staged tile, 0 = forget the choice (the next
+ * qf_instantiate times the candidates again).  Every form gives bitwise the
+ * same builder.
+ * Returns QF_EINVAL for other values. */
+int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile);
 
 /* Batched instantiation of many small independent problems (the partitions
  * of hierarchical synthesis, Sec. II "Partitioning and Resynthesis"), each

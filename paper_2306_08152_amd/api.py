@@ -76,6 +76,13 @@ def _c128(t: torch.Tensor, shape) -> torch.Tensor:
     return t
 
 
+def set_pass_tile(device, precision: int, n: int, gate_class: int, tile: int) -> None:
+    """Fix the pass form for (precision, n, gate class): -1 register-direct,
+    256/512/1024 LDS tile columns, 0 = tune again (qf_set_pass_tile)."""
+    ctx = _ctx(device)
+    nat.check(nat.load().qf_set_pass_tile(ctx, precision, n, gate_class, tile), ctx)
+
+
 def default_options(**kw) -> nat.QfOptions:
     o = nat.QfOptions()
     nat.load().qf_options_default(ctypes.byref(o))

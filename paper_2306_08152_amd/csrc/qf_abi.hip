@@ -31,7 +31,7 @@ struct qf_ctx {
   void* scratch = nullptr;      // device scratch for the stand-alone calls
   size_t scratch_bytes = 0;
   // Autotuned pass tile width per (precision, n); 0 = not tuned yet.
-  int tuned_tcols[2][17] = {};
+  int tuned_tcols[2][2][17] = {};
   double* identity = nullptr;   // one 4x4 c128 identity (tuning operand)
   std::string last_error;
 };
@@ -194,67 +194,81 @@ int ensure_scratch(qf_ctx* ctx, size_t bytes) {
   return QF_OK;
 }
 
-// Tile width of the fused pass for this precision and size: tuned once per
-// context by timing each candidate on the caller's builder with identity
+// Pass form of a gate: the tile width of the LDS-staged pass or kPassDirect
+// for the register-direct one.  Gates fall in two classes by where their two
+// column bits are (class 1: both among the three lowest bits, where the
+// direct form's loads stride by 2..8 elements); each (precision, class, n) is tuned once
+// per context by timing every candidate on the caller's builder with identity
 // operands on both sides (x * 1 + 0 * y = x exactly, so the builder is left
-// bit-for-bit unchanged), at a mid-circuit gate location.
-int pass_tcols(qf_ctx* ctx, int precision, int n) {
-  const int t = ctx->tuned_tcols[precision == QF_C64][n];
-  return t ? t : pass_max_tcols(precision);
+// bit-for-bit unchanged).  Untuned: the register-direct form for class 0 at
+// n >= 6, else the 512-column LDS tile.
+int pass_class(int n, int q0, int q1) {
+  const int hi = std::max(n - 1 - q0, n - 1 - q1);
+  return (n >= 6 && hi <= 2) ? 1 : 0;
+}
+
+int pass_tcols(qf_ctx* ctx, int precision, int n, int q0, int q1) {
+  const int cls = pass_class(n, q0, q1);
+  const int t = ctx->tuned_tcols[precision == QF_C64][cls][n];
+  if (t) return t;
+  return (n >= 6 && cls == 0) ? kPassDirect : 512;
 }
 
 int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
-  int& slot = ctx->tuned_tcols[precision == QF_C64][n];
-  if (slot) return QF_OK;
   const int N = 1 << n;
-  const int cands64[] = {256, 512, 1024}, cands128[] = {256, 512};
+  const int cands64[] = {kPassDirect, 256, 512, 1024}, cands128[] = {kPassDirect, 256, 512};
   const int* cands = precision == QF_C64 ? cands64 : cands128;
-  const int nc = precision == QF_C64 ? 3 : 2;
-  if (N < 512) {
-    slot = pass_max_tcols(precision);
-    return QF_OK;
-  }
+  const int nc = precision == QF_C64 ? 4 : 3;
   if (!ctx->identity) {
     QF_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->identity), 16 * 16));
     double id[32] = {};
     for (int k = 0; k < 4; ++k) id[2 * (5 * k)] = 1.0;
     QF_HIP(ctx, hipMemcpy(ctx->identity, id, sizeof id, hipMemcpyHostToDevice));
   }
-  hipEvent_t e0, e1;
-  QF_HIP(ctx, hipEventCreate(&e0));
-  QF_HIP(ctx, hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_t = pass_max_tcols(precision);
   const Operand I{ctx->identity, 0, 0};
-  // Two rounds over the candidates (warm-up launch, then 4 timed launches);
-  // each candidate keeps its better round.
-  float t_best[3] = {1e30f, 1e30f, 1e30f};
-  for (int round = 0; round < 2; ++round)
-    for (int c = 0; c < nc; ++c) {
-      if (cands[c] > N) continue;
-      const PassGeom geo = make_pass_geom(n, n / 2 - 1, n / 2, cands[c]);
-      hipError_t err = launch_pass(ctx->stream, precision, X, S, geo, I, I);
-      if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
-      for (int r = 0; r < 4 && err == hipSuccess; ++r) err = launch_pass(ctx->stream, precision, X, S, geo, I, I);
-      if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return fail(ctx, QF_EHIP, "pass autotune: %s", hipGetErrorString(err));
+  for (int cls = 0; cls < 2; ++cls) {
+    int& slot = ctx->tuned_tcols[precision == QF_C64][cls][n];
+    if (slot) continue;
+    if (N < 512) {
+      slot = pass_max_tcols(precision);
+      continue;
+    }
+    const int q0 = cls == 0 ? n / 2 - 1 : n - 2, q1 = q0 + 1;  // a mid-circuit pair / the two lowest bits
+    hipEvent_t e0, e1;
+    QF_HIP(ctx, hipEventCreate(&e0));
+    QF_HIP(ctx, hipEventCreate(&e1));
+    // Two rounds over the candidates (warm-up launch, then 4 timed launches);
+    // each candidate keeps its better round.
+    float t_best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    for (int round = 0; round < 2; ++round)
+      for (int c = 0; c < nc; ++c) {
+        if (cands[c] > N) continue;
+        const PassGeom geo = make_pass_geom(n, q0, q1, cands[c]);
+        hipError_t err = launch_pass(ctx->stream, precision, X, S, geo, I, I);
+        if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < 4 && err == hipSuccess; ++r) err = launch_pass(ctx->stream, precision, X, S, geo, I, I);
+        if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return fail(ctx, QF_EHIP, "pass autotune: %s", hipGetErrorString(err));
+        }
+        t_best[c] = std::min(t_best[c], ms);
       }
-      t_best[c] = std::min(t_best[c], ms);
-    }
-  for (int c = 0; c < nc; ++c)
-    if (t_best[c] < best) {
-      best = t_best[c];
-      best_t = cands[c];
-    }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  slot = best_t;
+    float best = 1e30f;
+    int best_t = pass_max_tcols(precision);
+    for (int c = 0; c < nc; ++c)
+      if (t_best[c] < best) {
+        best = t_best[c];
+        best_t = cands[c];
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    slot = best_t;
+  }
   return QF_OK;
 }
 
@@ -263,7 +277,7 @@ int build_builder(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
                   int64_t gstride, int S, int precision, void* X) {
   QF_HIP(ctx, launch_build_init(ctx->stream, precision, V, X, n, S));
   for (int g = 0; g < p; ++g) {
-    const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, precision, n));
+    const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, precision, n, locs[2 * g], locs[2 * g + 1]));
     Operand A{gates + 2 * 16 * (int64_t)g, gstride, 0};
     Operand B{nullptr, 0, 0};
     QF_HIP(ctx, launch_pass(ctx->stream, precision, X, S, geo, A, B));
@@ -379,7 +393,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   QF_HIP(ctx, launch_fill_i32(st, frozen, 0, (uint32_t)S));
 
   std::vector<PassGeom> geo(p);
-  for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n));
+  for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n, locs[2 * g], locs[2 * g + 1]));
 
   // The starts split into G groups whose sweeps run on separate streams:
   // while one group's latency-bound environment + SVD step runs, the other
@@ -487,14 +501,14 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   if (rc) return rc;
   // Tune the pass tile width on the freshly built builder (identity operands
   // leave it bit-for-bit unchanged), then lay out every gate's geometry.
-  if (!ctx->tuned_tcols[prec == QF_C64][n]) {
+  if (!ctx->tuned_tcols[prec == QF_C64][0][n] || !ctx->tuned_tcols[prec == QF_C64][1][n]) {
     if ((rc = autotune_pass(ctx, prec, n, X, S))) return rc;
     if (prec == QF_C64) {  // the FP64 rebuilds use complex128 passes
       if ((rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, QF_C128, R))) return rc;
       if ((rc = autotune_pass(ctx, QF_C128, n, R, S))) return rc;
     }
   }
-  for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n));
+  for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n, locs[2 * g], locs[2 * g + 1]));
   QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
   std::vector<double> c;
   rc = read_costs(ctx, costs, S, c);
@@ -761,7 +775,7 @@ int run_gradient(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, 
     ea.env_out = envP + (size_t)g * S * 32;
     QF_HIP(ctx, launch_env(st, prec, X, ea));
     if (g > 0) {  // move u_g to the input legs; the last move is not needed
-      const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n));
+      const PassGeom geo = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n, locs[2 * g], locs[2 * g + 1]));
       Operand ud{gates + 2 * 16 * (int64_t)g, gstride, 1};
       Operand u{gates + 2 * 16 * (int64_t)g, gstride, 0};
       QF_HIP(ctx, launch_pass(st, prec, X, S, geo, ud, u));
@@ -880,6 +894,17 @@ int qf_set_stream(qf_ctx* ctx, void* hip_stream) {
   return QF_OK;
 }
 
+int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile) {
+  if (!ctx) return QF_EINVAL;
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
+  if (gate_class != 0 && gate_class != 1) return fail(ctx, QF_EINVAL, "gate_class must be 0 or 1");
+  const bool ok = tile == 0 || tile == kPassDirect || tile == 256 || tile == 512 || (tile == 1024 && precision == QF_C64);
+  if (!ok) return fail(ctx, QF_EINVAL, "tile %d not supported", tile);
+  ctx->tuned_tcols[precision == QF_C64][gate_class][n] = tile;
+  return QF_OK;
+}
+
 size_t qf_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt) {
   qf_options o;
   if (opt)
@@ -914,7 +939,7 @@ int qf_apply_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precisi
   if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
   if (side != QF_LEFT && side != QF_RIGHT) return fail(ctx, QF_EINVAL, "side must be QF_LEFT or QF_RIGHT");
   DeviceGuard dg(ctx->device);
-  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_tcols(ctx, precision, n));
+  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_tcols(ctx, precision, n, loc[0], loc[1]));
   Operand G{reinterpret_cast<const double*>(gates), 16, dagger ? 1 : 0};
   Operand none{nullptr, 0, 0};
   QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, side == QF_LEFT ? G : none,
@@ -994,7 +1019,7 @@ int qf_update_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precis
   ea.counters = reinterpret_cast<int32_t*>(sc + part);
   QF_HIP(ctx, launch_fill_i32(ctx->stream, ea.counters, 0, (uint32_t)n_builders));
   QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
-  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_tcols(ctx, precision, n));
+  const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_tcols(ctx, precision, n, loc[0], loc[1]));
   Operand gnew{reinterpret_cast<const double*>(gates), 16, 0};
   Operand gold{ea.uold, 16, 1};
   if (half == 0)
@@ -1090,7 +1115,7 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
     stats->n_resets = out.resets;
     stats->n_rechecks = out.rechecks;
     stats->mode_used = mode;
-    stats->pass_tcols = mode == QF_MODE_STREAMING ? pass_tcols(ctx, o.precision, n) : 0;
+    stats->pass_tcols = mode == QF_MODE_STREAMING ? pass_tcols(ctx, o.precision, n, n / 2 - 1, n / 2) : 0;
     stats->best_cost = out.final_costs[best];
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -1510,7 +1535,7 @@ int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t*
     stats->pass_launches = evals;
     stats->env_launches = 0;
     stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
-    stats->pass_tcols = pass_tcols(ctx, o.precision, n);
+    stats->pass_tcols = pass_tcols(ctx, o.precision, n, n / 2 - 1, n / 2);
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;

@@ -26,7 +26,10 @@ struct PassGeom {
   uint32_t tb0, tb1, tblo, tbhi;  // local bit positions inside a tile column index
   uint32_t col_tiles;        // column tiles per row quad
   uint32_t tiles_per_start;  // (N/4) * col_tiles
+  uint32_t direct;           // 1: register-direct pass (no LDS tile), n >= 6 only
 };
+// Tile-width value that selects the register-direct pass.
+constexpr int kPassDirect = -1;
 
 PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols);
 

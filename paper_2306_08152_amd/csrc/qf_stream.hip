@@ -55,6 +55,11 @@ __device__ __forceinline__ uint32_t ilog2u(uint32_t v) { return 31u - __builtin_
 
 PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols) {
   PassGeom g{};
+  g.direct = 0;
+  if (max_tcols == kPassDirect) {
+    if (n >= 6) g.direct = 1u;
+    max_tcols = pass_max_tcols(QF_C128);  // the LDS tile serves n < 6
+  }
   g.n = (uint32_t)n;
   g.N = 1u << n;
   g.b0 = (uint32_t)(n - 1 - q0);
@@ -222,6 +227,110 @@ __global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g,
   }
 }
 
+// ------------------------------------------------------------ k_pass_block
+//
+// Register-direct form of the same pass for n >= 6, where a start owns a
+// whole number of 256-thread workgroups (so the start index, and with it the
+// operands, are uniform per workgroup and sit in scalar registers).  One 4x4
+// block per thread and no LDS: every thread loads its 16 entries straight
+// from HBM, which keeps many more bytes in flight per CU than an LDS-staged
+// tile can (LDS capacity bounds the staged form).  Consecutive threads take
+// consecutive block columns, so a wavefront's 64 loads of one block entry
+// cover long runs of columns, unless both gate bits are among the lowest
+// column bits (then they stride by 2..8 elements and the LDS-staged tile is
+// faster).  The runtime's tuner picks between the forms per (precision, n,
+// gate class).
+
+template <typename R>
+__device__ __forceinline__ R uniform_r(R v);
+template <>
+__device__ __forceinline__ float uniform_r<float>(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+template <>
+__device__ __forceinline__ double uniform_r<double>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Operand of a workgroup-uniform start s, held in scalar registers.
+template <typename R>
+__device__ __forceinline__ void load_operand_uniform(cx<R> m[16], const Operand& op, uint32_t s) {
+  const cd* src = reinterpret_cast<const cd*>(op.ptr) + (int64_t)s * op.stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cd v = op.dagger ? conj(src[4 * c + r]) : src[4 * r + c];
+      m[4 * r + c] = cx<R>{uniform_r<R>((R)v.re), uniform_r<R>((R)v.im)};
+    }
+}
+
+template <typename R, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassGeom g, uint32_t wg_per_start,
+                                                    Operand A, Operand B) {
+  const uint32_t N = g.N;
+  const uint32_t s = blockIdx.x / wg_per_start;
+  const uint32_t blk = (blockIdx.x - s * wg_per_start) * 256u + threadIdx.x;
+  const uint32_t rq = blk >> (g.n - 2), cq = blk & ((N >> 2) - 1u);
+  const uint32_t rb = insert00(rq, g.rlo, g.rhi), cb = insert00(cq, g.rlo, g.rhi);
+  uint32_t off[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) off[i] = local_off(i, g.b0, g.b1);
+  cx<R>* base = X + (size_t)s * N * N;
+  cx<R> a[16], b[16];
+  if (HA) load_operand_uniform<R>(a, A, s);
+  if (HB) load_operand_uniform<R>(b, B, s);
+  cx<R> x[16];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) x[4 * i + j] = base[(rb + off[i]) * N + cb + off[j]];
+  if (HA) {  // x <- A x
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cx<R> r[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cmac(acc, a[4 * i + k], x[4 * k + j]);
+        r[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[4 * i + j] = r[i];
+    }
+  }
+  if (HB) {  // x <- x B
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cx<R> r[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) cmac(acc, x[4 * i + l], b[4 * l + j]);
+        r[j] = acc;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[4 * i + j] = r[j];
+    }
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i)
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) base[(rb + off[i]) * N + cb + off[j]] = x[4 * i + j];
+}
+
+template <typename R, bool HA, bool HB>
+static hipError_t launch_pass_direct(hipStream_t st, cx<R>* x, int S, const PassGeom& g, Operand A, Operand B) {
+  const uint32_t wgps = g.N * g.N / 4096u;  // N^2/16 blocks, 256 per workgroup
+  hipLaunchKernelGGL((k_pass_block<R, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), 0, st, x, g, wgps, A, B);
+  return hipGetLastError();
+}
+
 template <typename R, bool HA, bool HB>
 static hipError_t launch_pass_v(hipStream_t st, cx<R>* x, uint32_t total, const PassGeom& g, Operand A,
                                 Operand B) {
@@ -239,6 +348,12 @@ static hipError_t launch_pass_t(hipStream_t st, void* X, int S, const PassGeom& 
                                 Operand B) {
   const uint32_t total = (uint32_t)S * g.tiles_per_start;
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
+  if (g.direct) {
+    if (A.ptr && B.ptr) return launch_pass_direct<R, true, true>(st, x, S, g, A, B);
+    if (A.ptr) return launch_pass_direct<R, true, false>(st, x, S, g, A, B);
+    if (B.ptr) return launch_pass_direct<R, false, true>(st, x, S, g, A, B);
+    return hipSuccess;
+  }
   if (A.ptr && B.ptr) return launch_pass_v<R, true, true>(st, x, total, g, A, B);
   if (A.ptr) return launch_pass_v<R, true, false>(st, x, total, g, A, B);
   if (B.ptr) return launch_pass_v<R, false, true>(st, x, total, g, A, B);

@@ -201,6 +201,54 @@ def test_update_gate_steps(qf, n, dtype):
         assert np.abs(host(X).astype(np.complex128) - ob.X).max() <= tol, (g, half)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_pass_forms_bitwise_equal(qf, dtype):
+    """Every form of the fused pass (register-direct, LDS tiles of every
+    width) gives bitwise the same builder for one-sided
+    products of both sides and for the two-sided update, at every qubit pair
+    of n = 6 and a spread of pairs (lowest bits included) of n = 10; the
+    one-sided products also match the oracle."""
+    prec = 0 if dtype == "c128" else 1
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    forms = [-1, 256, 512] + ([1024] if dtype == "c64" else [])
+    S = 2
+    try:
+        for n in (6, 10):
+            rng = np.random.default_rng(4000 + n)
+            X0 = I.random_builder(rng, S, n)
+            if dtype == "c64":
+                X0 = X0.astype(np.complex64).astype(np.complex128)
+            prs = pairs(n)
+            if n == 10:
+                prs = prs[::5] + [(8, 9), (9, 8), (7, 8), (8, 7), (7, 9), (9, 7), (0, 9), (9, 0)]
+            for k, loc in enumerate(prs):
+                u = np.stack([I.haar_unitary(rng, 4) for _ in range(S)])
+                w = np.stack([I.haar_unitary(rng, 4) for _ in range(S)])
+                gq = np.stack([I.haar_unitary(rng, 4) for _ in range(S)])
+                outs = []
+                for f in forms:
+                    for cls in (0, 1):
+                        qf.set_pass_tile("cuda", prec, n, cls, f)
+                    X = dev(X0).to(tdt)
+                    qf.apply_gate(X, loc, dev(u), 0, False)
+                    qf.apply_gate(X, loc, dev(w), 1, True)
+                    one = host(X).astype(np.complex128)
+                    G = dev(gq.copy())
+                    qf.update_gate(X, loc, k % 2, G)
+                    outs.append((one, host(X), host(G)))
+                ref = O.apply_right(O.apply_left(X0, u, loc, n), np.conj(np.swapaxes(w, -1, -2)), loc, n)
+                tol = C128_TOL if dtype == "c128" else C64_REL * np.abs(ref).max()
+                assert np.abs(outs[0][0] - ref).max() <= tol, (n, loc)
+                for f, o in zip(forms[1:], outs[1:]):
+                    assert np.array_equal(o[0], outs[0][0]), (n, loc, f)
+                    assert np.array_equal(o[1], outs[0][1]), (n, loc, f)
+                    assert np.array_equal(o[2], outs[0][2]), (n, loc, f)
+    finally:
+        for n in (6, 10):
+            for cls in (0, 1):
+                qf.set_pass_tile("cuda", prec, n, cls, 0)
+
+
 def test_cost_kernel(qf):
     rng = np.random.default_rng(5)
     X0 = I.random_builder(rng, 4, 9)
