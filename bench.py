@@ -15,10 +15,10 @@ full n = 6 / n = 3 instantiations (converged instantiations per second), and
 the batched workload of 4096 independent 3- and 4-qubit blocks x 8 starts in
 one persistent launch (converged blocks per second), and at n = 12 the
 gradient (evaluations per second) and the L-BFGS baseline against QFactor
-sweeps from the same initial circuit.
+sweeps from the same initial circuit, and a gate-deletion sweep (n = 5).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
-                       [--probe copy|batch|gradient]
+                       [--probe copy|batch|gradient|deletion]
 """
 from __future__ import annotations
 
@@ -65,10 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy", "batch", "gradient"], default=None,
+    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion"], default=None,
                     help="copy: only a plain device copy of known size (traffic-counter calibration); "
                          "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
-                         "and L-BFGS workload")
+                         "and L-BFGS workload; deletion: only the gate-deletion sweep")
     return ap.parse_args()
 
 
@@ -197,6 +197,22 @@ def gradient_workload(qf, torch) -> dict:
     return out
 
 
+def deletion_workload(qf, torch) -> dict:
+    """Gate-deletion sweep (re-synthesis workflow): n = 5, a 24-gate chain
+    whose first 10 gates are identities, 4 starts per attempt, complex64."""
+    import qfinputs as I
+    locs, V, g, pool = I.deletion_problem(6, 5, 24, 14, 4)
+    Vd, gd, pd = (torch.from_numpy(a).to("cuda") for a in (V, g, pool))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = qf.delete_gates(Vd, locs, gd, pd, tol=1e-8, precision=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"deletion_n5_p24": {"deleted": r.deleted, "kept": int(r.keep.sum()), "attempts": r.attempts,
+                                "sweeps": r.sweeps, "seconds": round(dt, 3),
+                                "attempts_per_s": round(r.attempts / dt, 2), "final_cost": r.cost}}
+
+
 def cpu_baseline(n_sweeps=3):
     """The FP64 oracle (builder mode) on the host: 3 sweeps of one start of the
     n = 10 headline problem."""
@@ -240,6 +256,9 @@ def main():
         return
     if args.probe == "gradient":
         print(json.dumps(gradient_workload(qf, torch)), flush=True)
+        return
+    if args.probe == "deletion":
+        print(json.dumps(deletion_workload(qf, torch)), flush=True)
         return
 
     K, W = max(1, args.steps), max(0, args.warmup)
@@ -339,6 +358,7 @@ def main():
         extra["n3_p4_c128_status"] = int(r3.status)
         extra.update(batch_workload(qf, torch))
         extra.update(gradient_workload(qf, torch))
+        extra.update(deletion_workload(qf, torch))
         out["extra"] = extra
 
     if not args.no_cpu:

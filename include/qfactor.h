@@ -337,6 +337,35 @@ int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t*
              int n_starts, double tol, const qf_lbfgs_options* opt, void* workspace, size_t ws_bytes,
              double* theta_out, double* out_costs, qf_stats* stats);
 
+/* Gate deletion (the re-synthesis workflow QFactor drives in Sec. V,
+ * "Circuit Optimization Scaling"): one uni-directional sweep over the gates
+ * of a partition, g = 0..p-1; each step deletes gate g from the current
+ * circuit and re-instantiates the reduced structure (qf_instantiate with
+ * `opt`) to the partition's own unitary; the deletion is kept when the best
+ * start's cost is below tol, and the re-instantiated gates become the
+ * current circuit.  Start 0 of every attempt is the current circuit without
+ * gate g (a warm start); starts 1..n_starts-1 take their gates from the
+ * caller's pool at the positions still present.
+ *   target:     device, N x N c128, the partition's unitary
+ *   locations:  host, n_gates x 2
+ *   gates:      device, n_gates x 4 x 4 c128: a circuit of this structure
+ *               that realises target (cost below tol); not modified
+ *   pool:       device, n_starts x n_gates x 4 x 4 c128 (start 0 unused)
+ *   workspace:  device, >= qf_delete_gates_workspace_size(...)
+ *   keep:       host, n_gates int32 out: 1 kept, 0 deleted
+ *   out_gates:  device, n_gates x 4 x 4 c128 out: the kept gates in order,
+ *               compacted to the front (the rest left unspecified)
+ *   out_cost:   host, FP64 cost of the final circuit
+ *   stats:      optional: sweeps = total sweeps of all attempts,
+ *               n_resets = attempts, n_rechecks = deletions kept,
+ *               elapsed_ms
+ * Returns QF_EINVAL if `gates` does not realise target within tol. */
+size_t qf_delete_gates_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt);
+int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                    const void* gates, const void* pool, int n_starts, double tol, const qf_options* opt,
+                    void* workspace, size_t ws_bytes, int32_t* keep, void* out_gates, double* out_cost,
+                    qf_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ EXPORTED = [
     "qf_workspace_size", "qf_build", "qf_apply_gate", "qf_environment", "qf_optimize_gate",
     "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
     "qf_gradient_workspace_size", "qf_gradient", "qf_su4_gates", "qf_su4_vjp", "qf_lbfgs_options_default",
-    "qf_lbfgs_workspace_size", "qf_lbfgs", "qf_set_pass_tile",
+    "qf_lbfgs_workspace_size", "qf_lbfgs", "qf_set_pass_tile", "qf_delete_gates_workspace_size", "qf_delete_gates",
 ]
 
 
@@ -109,6 +109,11 @@ _SIGS = {
     "qf_su4_vjp": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "qf_lbfgs_options_default": (None, [ctypes.POINTER(QfLbfgsOptions)]),
     "qf_set_pass_tile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "qf_delete_gates_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                         ctypes.POINTER(QfOptions)]),
+    "qf_delete_gates": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, _VP, ctypes.c_int,
+                                       ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _I32P, _VP,
+                                       _DP, ctypes.POINTER(QfStats)]),
     "qf_lbfgs_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.POINTER(QfLbfgsOptions)]),
     "qf_lbfgs": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int, ctypes.c_double,

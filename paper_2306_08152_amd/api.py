@@ -460,3 +460,47 @@ def lbfgs(target: torch.Tensor, locs, theta0: torch.Tensor, tol: float = 1e-10, 
     h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
     return LbfgsResult(out, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.pass_launches,
                        st.elapsed_ms, h)
+
+
+@dataclass
+class DeletionResult:
+    keep: np.ndarray         # (p,) 1 kept, 0 deleted
+    gates: torch.Tensor      # (kept, 4, 4) the final circuit's gates in order
+    locs: np.ndarray         # (kept, 2)
+    cost: float              # FP64 cost of the final circuit
+    attempts: int
+    deleted: int
+    sweeps: int
+    elapsed_ms: float
+
+
+def delete_gates(target: torch.Tensor, locs, gates: torch.Tensor, pool: torch.Tensor, tol: float = 1e-10,
+                 options: nat.QfOptions | None = None, **kw) -> DeletionResult:
+    """Uni-directional gate-deletion sweep (qf_delete_gates): gates (p, 4, 4)
+    realise target on `locs`; pool (S, p, 4, 4) seeds starts 1..S-1."""
+    opt = options if options is not None else default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 2)
+    p = locs.shape[0]
+    S = pool.shape[0]
+    _c128(target, (N, N))
+    _c128(gates, (p, 4, 4))
+    _c128(pool, (S, p, 4, 4))
+    lib = nat.load()
+    need = int(lib.qf_delete_gates_workspace_size(n, p, S, ctypes.byref(opt))) or 1
+    workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
+    out = torch.empty((p, 4, 4), dtype=torch.complex128, device=target.device)
+    keep = (ctypes.c_int32 * p)()
+    cost_out = ctypes.c_double()
+    st = nat.QfStats()
+    ctx = _ctx(target.device)
+    nat.check(lib.qf_delete_gates(ctx, n, _ptr(target), p, _loc(locs), _ptr(gates), _ptr(pool), S, float(tol),
+                                  ctypes.byref(opt), _ptr(workspace), need, keep, _ptr(out),
+                                  ctypes.byref(cost_out), ctypes.byref(st)), ctx)
+    km = np.array(keep[:], np.int32)
+    kcount = int(km.sum())
+    return DeletionResult(km, out[:kcount].clone(), locs[km == 1], float(cost_out.value), st.n_resets,
+                          st.n_rechecks, st.sweeps, st.elapsed_ms)

@@ -294,6 +294,20 @@ __global__ void k_cast_c128_c64(const double2* __restrict__ src, float2* __restr
   }
 }
 
+// dst[s][k] = src[s][idx[k]] for 4x4 c128 gates (S starts, p source gates,
+// q selected); src_start0 (optional) replaces the source of start 0.
+__global__ void k_gather_gates(const double2* __restrict__ src, const double2* __restrict__ src_start0,
+                               int S, int p, const int32_t* __restrict__ idx, int q, double2* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)S * q * 16) return;
+  const int k16 = (int)(e & 15);
+  const int64_t sk = e >> 4;
+  const int k = (int)(sk % q), s = (int)(sk / q);
+  const double2* from = (s == 0 && src_start0) ? src_start0 + (int64_t)idx[k] * 16
+                                               : src + ((int64_t)s * p + idx[k]) * 16;
+  dst[e] = from[k16];
+}
+
 int cast_to_c64(qf_ctx* ctx, const void* R, void* X, size_t count) {
   const unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
   hipLaunchKernelGGL(k_cast_c128_c64, dim3(blocks), dim3(256), 0, ctx->stream,
@@ -1536,6 +1550,119 @@ int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t*
     stats->env_launches = 0;
     stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
     stats->pass_tcols = pass_tcols(ctx, o.precision, n, n / 2 - 1, n / 2);
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return QF_OK;
+}
+
+size_t qf_delete_gates_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt) {
+  const size_t inner = qf_workspace_size(n, n_gates, n_starts, opt);
+  if (!inner) return 0;
+  const size_t g = align_up((size_t)n_gates * 256);
+  return align_up(inner) + 2 * g + 2 * align_up((size_t)n_starts * n_gates * 256) + align_up((size_t)n_gates * 4);
+}
+
+int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                    const void* gates, const void* pool, int n_starts, double tol, const qf_options* opt,
+                    void* workspace, size_t ws_bytes, int32_t* keep, void* out_gates, double* out_cost,
+                    qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int p = n_gates, S = n_starts;
+  int rc = validate_problem(ctx, n, p, locations, S);
+  if (rc) return rc;
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, QF_EINVAL, "tol must be finite and > 0");
+  if (!target || !gates || !pool || !keep || !out_gates || !out_cost) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if ((rc = validate_options(ctx, o))) return rc;
+  const size_t need = qf_delete_gates_workspace_size(n, p, S, &o);
+  if (!workspace || ws_bytes < need)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = ctx->stream;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  const size_t inner = align_up(qf_workspace_size(n, p, S, &o));
+  const size_t gsz = align_up((size_t)p * 256), psz = align_up((size_t)S * p * 256);
+  double2* cur = reinterpret_cast<double2*>(ws + inner);            // current circuit (compacted)
+  double2* best = reinterpret_cast<double2*>(ws + inner + gsz);     // attempt result
+  double2* init = reinterpret_cast<double2*>(ws + inner + 2 * gsz);  // attempt initial gates
+  double2* all = reinterpret_cast<double2*>(ws + inner + 2 * gsz + psz);
+  int32_t* d_idx = reinterpret_cast<int32_t*>(ws + inner + 2 * gsz + 2 * psz);
+
+  // the given circuit must realise the target
+  std::vector<double> c0(1);
+  {
+    qf_options o1 = o;
+    o1.max_iter = 0;
+    QF_HIP(ctx, hipMemcpyAsync(cur, gates, (size_t)p * 256, hipMemcpyDeviceToDevice, st));
+    rc = qf_instantiate(ctx, n, target, p, locations, cur, 1, tol, &o1, ws, inner, best, nullptr, c0.data(), nullptr);
+    if (rc) return rc;
+    if (!(c0[0] < tol)) return fail(ctx, QF_EINVAL, "the given gates do not realise the target (cost %.3g)", c0[0]);
+  }
+  std::vector<int> kept;  // original indices of the gates of the current circuit
+  for (int g = 0; g < p; ++g) kept.push_back(g);
+  double cost_now = c0[0];
+  int attempts = 0, deleted = 0, sweeps = 0;
+  std::vector<int32_t> idx, sub_locs;
+  for (int g = 0; g < p; ++g) {
+    if (kept.size() <= 1) break;  // an empty circuit is not instantiated
+    const int pos = (int)(std::find(kept.begin(), kept.end(), g) - kept.begin());
+    const int q = (int)kept.size() - 1;
+    idx.clear();
+    sub_locs.clear();
+    std::vector<int32_t> idx_cur;  // positions in the current (compacted) circuit
+    for (int k = 0; k < (int)kept.size(); ++k) {
+      if (k == pos) continue;
+      idx.push_back(kept[k]);
+      idx_cur.push_back(k);
+      sub_locs.push_back(locations[2 * kept[k]]);
+      sub_locs.push_back(locations[2 * kept[k] + 1]);
+    }
+    // start 0: the current circuit without gate g; starts 1..: the pool at the gates still present
+    QF_HIP(ctx, hipMemcpyAsync(d_idx, idx.data(), (size_t)q * 4, hipMemcpyHostToDevice, st));
+    {
+      const int64_t tot = (int64_t)S * q * 16;
+      hipLaunchKernelGGL(k_gather_gates, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                         reinterpret_cast<const double2*>(pool), (const double2*)nullptr, S, p, d_idx, q, all);
+      QF_HIP(ctx, hipGetLastError());
+      QF_HIP(ctx, hipMemcpyAsync(d_idx, idx_cur.data(), (size_t)q * 4, hipMemcpyHostToDevice, st));
+      const int64_t tot0 = (int64_t)q * 16;
+      hipLaunchKernelGGL(k_gather_gates, dim3((unsigned)((tot0 + 255) / 256)), dim3(256), 0, st,
+                         reinterpret_cast<const double2*>(cur), (const double2*)nullptr, 1, (int)kept.size(), d_idx, q,
+                         init);
+      QF_HIP(ctx, hipGetLastError());
+      QF_HIP(ctx, hipMemcpyAsync(all, init, (size_t)q * 256, hipMemcpyDeviceToDevice, st));
+    }
+    std::vector<double> costs(S);
+    qf_stats ist{};
+    rc = qf_instantiate(ctx, n, target, q, sub_locs.data(), all, S, tol, &o, ws, inner, best, nullptr, costs.data(),
+                        &ist);
+    if (rc && rc != QF_ENUMERIC) return rc;
+    ++attempts;
+    sweeps += ist.sweeps;
+    if (rc == QF_OK && ist.best_cost < tol) {
+      QF_HIP(ctx, hipMemcpyAsync(cur, best, (size_t)q * 256, hipMemcpyDeviceToDevice, st));
+      kept.erase(kept.begin() + pos);
+      cost_now = ist.best_cost;
+      ++deleted;
+    }
+  }
+  for (int g = 0; g < p; ++g) keep[g] = 0;
+  for (int k : kept) keep[k] = 1;
+  QF_HIP(ctx, hipMemcpyAsync(out_gates, cur, kept.size() * 256, hipMemcpyDeviceToDevice, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  *out_cost = cost_now;
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->n_resets = attempts;
+    stats->n_rechecks = deleted;
+    stats->best_start = 0;
+    stats->status = QF_CONVERGED;
+    stats->best_cost = cost_now;
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;

@@ -176,6 +176,19 @@ def su4_params(config_id: int, n_starts: int, count: int, scale: float = 1.0) ->
                      for s in range(n_starts)])
 
 
+def deletion_problem(config_id: int, n: int, p: int, p_target: int, n_starts: int):
+    """Gate-deletion workload: a nearest-neighbour chain of p gates on n
+    qubits (gate k on (k mod (n-1), k mod (n-1) + 1)) whose first p - p_target
+    gates are identities and the last p_target Haar-random (role 0), the
+    target is that circuit's unitary, and a pool of Haar starts (role 1)."""
+    locs = np.array([(k % (n - 1), k % (n - 1) + 1) for k in range(p)], np.int32)
+    rt = rng_for(config_id, ROLE_TARGET, 0)
+    g = np.stack([haar_unitary(rt, 4) if k >= p - p_target else np.eye(4, dtype=np.complex128) for k in range(p)])
+    V = circuit_unitary(g, locs, n)
+    pool = np.stack([haar_gates(rng_for(config_id, ROLE_INIT, s), p) for s in range(n_starts)])
+    return locs, V, g, pool
+
+
 def random_builder(rng: np.random.Generator, n_starts: int, n: int) -> np.ndarray:
     """Generic complex test matrices (S, N, N) with entries ~ CN(0, 1/N)."""
     N = 1 << n
