@@ -71,6 +71,7 @@ __all__ = [
     "STATUS_CONVERGED", "STATUS_PLATEAU", "STATUS_MAX_ITER", "STATUS_NUMERIC",
     "nuclear_norm", "frobenius_distance_sq", "optimize_gate_batched", "builder_rows",
     "cost_gradient", "PAULI2", "su4_hermitian", "su4_gate", "su4_theta_gradient", "param_cost_gradient",
+    "KIND_U4", "KIND_FIXED", "KIND_U2", "KIND_RZ", "KIND_GPI", "optimize_gate_kind", "rz", "gpi",
 ]
 
 STATUS_CONVERGED = 0
@@ -301,6 +302,72 @@ def optimize_gate(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.nda
     return Yh.conj().T @ Xs.conj().T
 
 
+# ---------------------------------------------------------------------------
+# Gate kinds (Sec. III-A-3, Specializing Gate Sets; the paper's U3 + CNOT
+# evaluation set, Sec. V).  Every gate is stored as a 4 x 4 matrix on its two
+# locations; single-qubit kinds act on loc[0] and are stored as g (x) I_2
+# (loc[1] is only a partner qubit for the embedding).  With
+# E2 = Tr over the partner of E (E2[a, b] = sum_c E[2a + c, 2b + c]),
+# Re Tr(E (g (x) I)) = Re Tr(E2 g), so each single-qubit update maximises
+# Re Tr(M2 g) with M2 = (1 - beta) E2 + beta g_old^dagger.
+#   KIND_U4    general U(4): the SVD update above
+#   KIND_FIXED applied but never optimised (e.g. CNOT)
+#   KIND_U2    general U(2): SVD of M2 (maximiser Y X^dagger)
+#   KIND_RZ    Rz(t) = diag(1, e^{it}): Re Tr(M2 Rz) = Re M2[0,0] +
+#              |M2[1,1]| cos(t + arg M2[1,1]), maximal at t = -arg M2[1,1]
+#   KIND_GPI   GPI(f) = [[0, e^{-if}], [e^{if}, 0]]: Re Tr(M2 GPI) =
+#              Re((M2[0,1] + conj(M2[1,0])) e^{if}), maximal at
+#              f = -arg(M2[0,1] + conj(M2[1,0]))
+# A zero quantity to take the argument of (modulus below 1e-300) keeps the
+# old gate, like a zero environment (Q15).
+# ---------------------------------------------------------------------------
+
+KIND_U4, KIND_FIXED, KIND_U2, KIND_RZ, KIND_GPI = 0, 1, 2, 3, 4
+
+
+def rz(t: float) -> np.ndarray:
+    return np.array([[1.0, 0.0], [0.0, np.exp(1j * t)]], np.complex128)
+
+
+def gpi(f: float) -> np.ndarray:
+    return np.array([[0.0, np.exp(-1j * f)], [np.exp(1j * f), 0.0]], np.complex128)
+
+
+def _partner_trace(E: np.ndarray) -> np.ndarray:
+    return np.einsum("acbc->ab", E.reshape(2, 2, 2, 2))
+
+
+def optimize_gate_kind(E: np.ndarray, u_old: np.ndarray, kind: int, beta: float = 0.0) -> np.ndarray:
+    """Gate update for every kind (see the table above); returns the 4 x 4
+    stored matrix."""
+    if kind == KIND_U4:
+        return optimize_gate(E, u_old, beta)
+    if kind == KIND_FIXED:
+        return u_old.copy()
+    g_old = u_old[::2, ::2]  # g of g (x) I_2
+    M = (1.0 - beta) * _partner_trace(E) + beta * g_old.conj().T
+    if not np.all(np.isfinite(M)):
+        return np.full_like(u_old, np.nan)
+    if kind == KIND_U2:
+        scale = np.max(np.abs(M))
+        if scale < 1e-300:
+            return u_old.copy()
+        Xs, _, Yh = np.linalg.svd(M / scale)
+        g = Yh.conj().T @ Xs.conj().T
+    elif kind == KIND_RZ:
+        if abs(M[1, 1]) < 1e-300:
+            return u_old.copy()
+        g = rz(-np.angle(M[1, 1]))
+    elif kind == KIND_GPI:
+        w = M[0, 1] + np.conj(M[1, 0])
+        if abs(w) < 1e-300:
+            return u_old.copy()
+        g = gpi(-np.angle(w))
+    else:
+        raise ValueError(kind)
+    return np.kron(g, np.eye(2))
+
+
 def optimize_gate_batched(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.ndarray:
     """optimize_gate over a leading batch axis (one stacked LAPACK SVD call;
     the zero and non-finite guards are applied per entry afterwards)."""
@@ -319,7 +386,7 @@ def optimize_gate_batched(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -
 # Definition mode: every environment from scratch (Alg. 1 order, Q5).
 # ---------------------------------------------------------------------------
 
-def sweep_definition(V, gates, locs, n: int, beta: float = 0.0, record: list | None = None):
+def sweep_definition(V, gates, locs, n: int, beta: float = 0.0, record: list | None = None, kinds=None):
     """One TwoSidedSweep with environments recomputed from scratch.  Returns
     the new gate list; if `record` is a list, appends (g, half, E, u_new, T)
     per update, T being Tr(V^dagger C) after the update."""
@@ -328,7 +395,8 @@ def sweep_definition(V, gates, locs, n: int, beta: float = 0.0, record: list | N
     order = [(g, 0) for g in range(p - 1, -1, -1)] + [(g, 1) for g in range(p)]
     for g, half in order:
         E = environment(V, gates, locs, n, g)
-        gates[g] = optimize_gate(E, gates[g], beta)
+        k = KIND_U4 if kinds is None else int(kinds[g])
+        gates[g] = optimize_gate_kind(E, gates[g], k, beta)
         if record is not None:
             record.append((g, half, E, gates[g].copy(), complex(np.trace(E @ gates[g]))))
     return np.stack(gates)
@@ -346,7 +414,8 @@ class BuilderOracle:
     X <- X G_g'.  Second half (g = 1..p): X <- X G_g'^dagger, E = Tr_rest X,
     update, X <- G_g'' X."""
 
-    def __init__(self, V: np.ndarray, gates: np.ndarray, locs, n: int, beta: float = 0.0):
+    def __init__(self, V: np.ndarray, gates: np.ndarray, locs, n: int, beta: float = 0.0, kinds=None):
+        self.kinds = None if kinds is None else [int(k) for k in kinds]
         self.V = np.asarray(V, np.complex128)
         self.n = n
         self.N = 1 << n
@@ -379,7 +448,11 @@ class BuilderOracle:
         else:
             self.X = apply_right(self.X, ud, loc, self.n)
         E = partial_trace(self.X, loc, self.n)
-        unew = optimize_gate_batched(E, u, self.beta)
+        kind = KIND_U4 if self.kinds is None else self.kinds[g]
+        if kind == KIND_U4:
+            unew = optimize_gate_batched(E, u, self.beta)
+        else:
+            unew = np.stack([optimize_gate_kind(E[s], u[s], kind, self.beta) for s in range(self.S)])
         if active is not None:
             unew = np.where(active[:, None, None], unew, u)
         self.gates[:, g] = unew
@@ -440,7 +513,7 @@ def _plateau_flags(hist: list, i: int, opt: Options) -> np.ndarray:
 
 
 def instantiate(V: np.ndarray, init_gates: np.ndarray, locs, n: int, tol: float | None = None,
-                opt: Options | None = None, mode: str = "builder") -> Result:
+                opt: Options | None = None, mode: str = "builder", kinds=None) -> Result:
     """Multistart QFactor in lockstep.  mode='builder' runs Alg. 1's circuit
     tensor (with resets); mode='definition' recomputes every environment."""
     opt = opt or Options()
@@ -453,7 +526,7 @@ def instantiate(V: np.ndarray, init_gates: np.ndarray, locs, n: int, tol: float 
     locs = [tuple(int(q) for q in l) for l in locs]
 
     if mode == "builder":
-        b = BuilderOracle(V, init_gates, locs, n, opt.beta)
+        b = BuilderOracle(V, init_gates, locs, n, opt.beta, kinds)
         cur = lambda: b.costs()  # noqa: E731
         gates_of = lambda: b.gates  # noqa: E731
     elif mode == "definition":
@@ -481,7 +554,7 @@ def instantiate(V: np.ndarray, init_gates: np.ndarray, locs, n: int, tol: float 
         else:
             for s in range(S):
                 if active[s]:
-                    G[s] = sweep_definition(V, G[s], locs, n, opt.beta)
+                    G[s] = sweep_definition(V, G[s], locs, n, opt.beta, kinds=kinds)
         c = cur()
         bad = ~np.isfinite(c)
         numeric |= bad

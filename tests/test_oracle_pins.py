@@ -563,3 +563,118 @@ def test_param_cost_gradient_finite_differences():
             tm[g, k] -= h
             fd = (O.cost(V, O.su4_gate(tp), locs, n) - O.cost(V, O.su4_gate(tm), locs, n)) / (2 * h)
             assert abs(fd - d[g, k]) < 1e-8, (g, k)
+
+
+# ----------------------------------------------------------------- gate kinds
+
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], np.complex128)
+
+
+def dense_single(g, q, n):
+    """I (x) g (x) I on qubit q (qubit 0 most significant), by Kronecker products."""
+    return np.kron(np.kron(np.eye(1 << q), g), np.eye(1 << (n - q - 1)))
+
+
+@pytest.mark.parametrize("q,partner", [(0, 1), (1, 0), (1, 2), (2, 0), (2, 1)])
+def test_single_qubit_kind_embedding(q, partner):
+    """A single-qubit gate stored as g (x) I on (q, partner) is the gate g on
+    qubit q, whatever the partner."""
+    rng = np.random.default_rng(1000 + 10 * q + partner)
+    g = haar(2, rng)
+    n = 3
+    X = haar(8, rng)
+    got = O.apply_left(X, np.kron(g, np.eye(2)), (q, partner), n)
+    assert np.abs(got - dense_single(g, q, n) @ X).max() < 1e-14
+
+
+def test_partner_trace_identity():
+    rng = np.random.default_rng(1010)
+    for _ in range(5):
+        E = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        g = haar(2, rng)
+        E2 = np.array([[sum(E[2 * a + c, 2 * b + c] for c in range(2)) for b in range(2)] for a in range(2)])
+        assert abs(np.trace(E @ np.kron(g, np.eye(2))) - np.trace(E2 @ g)) < 1e-13
+
+
+def test_kind_updates_are_maximisers():
+    """The U(2) update attains the nuclear norm of M2 and beats Haar U(2)
+    trials; the Rz and GPI updates attain the maximum of a dense grid over
+    their angle; the fixed kind returns the gate unchanged."""
+    rng = np.random.default_rng(1020)
+    ts = np.linspace(-np.pi, np.pi, 200001)
+    for _ in range(4):
+        E = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        u_old = np.kron(haar(2, rng), np.eye(2))
+        E2 = np.array([[E[2 * a, 2 * b] + E[2 * a + 1, 2 * b + 1] for b in range(2)] for a in range(2)])
+        val = lambda u: np.real(np.trace(E @ u))  # noqa: E731
+        u2 = O.optimize_gate_kind(E, u_old, O.KIND_U2)
+        assert abs(val(u2) - np.sum(np.linalg.svd(E2, compute_uv=False))) < 1e-12
+        assert all(val(u2) >= val(np.kron(haar(2, rng), np.eye(2))) - 1e-12 for _ in range(200))
+        assert np.abs(u2[::2, 1::2]).max() < 1e-15 and np.abs(u2[::2, ::2] - u2[1::2, 1::2]).max() < 1e-15
+        urz = O.optimize_gate_kind(E, u_old, O.KIND_RZ)
+        grid = np.real(E2[0, 0]) + np.real(E2[1, 1] * np.exp(1j * ts))
+        assert abs(val(urz) - grid.max()) < 1e-9 and val(urz) >= grid.max() - 1e-12
+        ugp = O.optimize_gate_kind(E, u_old, O.KIND_GPI)
+        grid = np.real(E2[0, 1] * np.exp(1j * ts) + E2[1, 0] * np.exp(-1j * ts))
+        assert abs(val(ugp) - grid.max()) < 1e-9 and val(ugp) >= grid.max() - 1e-12
+        assert np.array_equal(O.optimize_gate_kind(E, CNOT, O.KIND_FIXED), CNOT)
+
+
+def mixed_circuit(rng, n):
+    """A U3 + CNOT style circuit with every kind: CNOTs (fixed), single-qubit
+    U(2), Rz and GPI gates (partner = a neighbour), and one general U(4)."""
+    locs, gates, kinds = [], [], []
+    for q in range(n):
+        locs.append((q, (q + 1) % n))
+        gates.append(np.kron(haar(2, rng), np.eye(2)))
+        kinds.append(O.KIND_U2)
+    for q in range(n - 1):
+        locs.append((q, q + 1))
+        gates.append(CNOT)
+        kinds.append(O.KIND_FIXED)
+        locs.append((q + 1, q))
+        gates.append(np.kron(O.rz(rng.uniform(-3, 3)), np.eye(2)))
+        kinds.append(O.KIND_RZ)
+    locs.append((0, n - 1))
+    gates.append(np.kron(O.gpi(rng.uniform(-3, 3)), np.eye(2)))
+    kinds.append(O.KIND_GPI)
+    locs.append((n - 2, n - 1))
+    gates.append(haar(4, rng))
+    kinds.append(O.KIND_U4)
+    return np.array(locs, np.int32), np.stack(gates), np.array(kinds, np.int32)
+
+
+def test_kinds_builder_equals_definition_and_fixed_stay():
+    """With every kind in one circuit, builder mode equals definition mode
+    update by update, fixed gates never change, and Re Tr(E u) never
+    decreases across an update."""
+    rng = np.random.default_rng(1030)
+    n = 4
+    locs, g0, kinds = mixed_circuit(rng, n)
+    V = haar(16, rng)
+    rec_d = []
+    gd = O.sweep_definition(V, g0, locs, n, record=rec_d, kinds=kinds)
+    rec_b = []
+    b = O.BuilderOracle(V, g0, locs, n, kinds=kinds)
+    b.sweep(record=rec_b)
+    assert len(rec_d) == len(rec_b)
+    for (gi, h, E, u, T), (gj, hb, Eb, ub, Tb) in zip(rec_d, rec_b):
+        assert gi == gj and h == hb
+        assert np.abs(E - Eb[0]).max() < 1e-11 and np.abs(u - ub[0]).max() < 1e-10
+    for k in np.where(kinds == O.KIND_FIXED)[0]:
+        assert np.array_equal(gd[k], g0[k]) and np.array_equal(b.gates[0, k], g0[k])
+    cur = [u.copy() for u in g0]
+    for gi, h, E, u, T in rec_d:
+        assert np.real(np.trace(E @ u)) >= np.real(np.trace(E @ cur[gi])) - 1e-12
+        cur[gi] = u
+
+
+def test_kinds_fixed_point_of_own_circuit():
+    """A target built from a mixed-kind circuit is a fixed point: one sweep
+    from the true gates keeps the cost at zero."""
+    rng = np.random.default_rng(1040)
+    n = 3
+    locs, g0, kinds = mixed_circuit(rng, n)
+    V = O.circuit_unitary(g0, locs, n)
+    g1 = O.sweep_definition(V, g0, locs, n, kinds=kinds)
+    assert O.cost(V, g1, locs, n) < 1e-13
