@@ -68,6 +68,20 @@ typedef enum {
 
 typedef enum { QF_LEFT = 0, QF_RIGHT = 1 } qf_side;
 
+/* Gate kinds (Sec. III-A-3, Specializing Gate Sets; the evaluation's U3 +
+ * CNOT gate set).  Every gate is passed as a 4 x 4 matrix on its two
+ * locations.  Single-qubit kinds act on location 0 and must be given as
+ * g (x) I_2 (location 1 is only a partner qubit for the embedding); their
+ * update maximises Re Tr(E2 g) over the kind's set, E2 being the partial
+ * trace of the environment over the partner:
+ *   QF_KIND_U4    general U(4) (SVD update, Sec. III-A-1)
+ *   QF_KIND_FIXED applied, never optimised (e.g. CNOT)
+ *   QF_KIND_U2    general U(2) (unitary polar factor, closed form for 2 x 2)
+ *   QF_KIND_RZ    diag(1, e^{it}), t = -arg M2[1][1]
+ *   QF_KIND_GPI   [[0, e^{-if}], [e^{if}, 0]], f = -arg(M2[0][1] + conj M2[1][0])
+ * (M2 = (1-beta) E2 + beta g_old^dagger; a zero argument keeps the gate.) */
+typedef enum { QF_KIND_U4 = 0, QF_KIND_FIXED = 1, QF_KIND_U2 = 2, QF_KIND_RZ = 3, QF_KIND_GPI = 4 } qf_gate_kind;
+
 typedef enum {
   QF_CONVERGED = 0,  /* best start's final cost < tol */
   QF_PLATEAU = 1,    /* every start met a plateau test */
@@ -79,7 +93,7 @@ typedef enum {
  * paper recommends: dist_tol 1e-10, diff_tol_a 0, diff_tol_r 1e-5,
  * long_diff_count 100, long_diff_r 0.1, min_iter 0, max_iter 1e5,
  * reset_iter 40, beta 0; plus precision QF_C128, mode QF_MODE_AUTO,
- * recheck_below 1e-3 and stream_groups 0 (automatic).
+ * recheck_below 1e-3, stream_groups 0 (automatic) and gate_kinds NULL.
  * Readings of the garbled tests (c_i = cost after sweep i, c_0 = initial):
  *   short plateau: c_{i-1} - c_i <= diff_tol_a + diff_tol_r * c_i
  *                  (off when both are 0);
@@ -114,6 +128,9 @@ typedef struct {
                             staggered so one group's environment + SVD step
                             runs under another's pass (0 = automatic; at most
                             4 and at most n_starts) */
+  const int32_t* gate_kinds; /* host, one qf_gate_kind per gate (for
+                                qf_instantiate_batch: per gate of the whole
+                                batch); NULL = every gate QF_KIND_U4 */
 } qf_options;
 
 /* Outcome of qf_instantiate (host memory). */

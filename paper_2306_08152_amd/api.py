@@ -83,6 +83,25 @@ def set_pass_tile(device, precision: int, n: int, gate_class: int, tile: int) ->
     nat.check(nat.load().qf_set_pass_tile(ctx, precision, n, gate_class, tile), ctx)
 
 
+def _apply_kw(opt: nat.QfOptions, kw: dict):
+    """Set option fields; gate_kinds (sequence of qf_gate_kind) becomes a
+    ctypes array that the caller keeps alive for the call."""
+    keep = None
+    for k, v in kw.items():
+        if k == "gate_kinds":
+            if v is None:
+                opt.gate_kinds = None
+            else:
+                a = np.ascontiguousarray(v, np.int32).reshape(-1)
+                keep = (ctypes.c_int32 * max(1, a.size))(*a.tolist())
+                opt.gate_kinds = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+        else:
+            if not hasattr(opt, k):
+                raise AttributeError(k)
+            setattr(opt, k, v)
+    return keep
+
+
 def default_options(**kw) -> nat.QfOptions:
     o = nat.QfOptions()
     nat.load().qf_options_default(ctypes.byref(o))
@@ -183,10 +202,10 @@ def workspace_size(n: int, p: int, S: int, opt: nat.QfOptions) -> int:
 def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float = 1e-10,
                 options: nat.QfOptions | None = None, history_rows: int = 0,
                 workspace: torch.Tensor | None = None, timing: bool = False, **kw) -> Result:
-    """QFactor multistart instantiation (qf_instantiate)."""
+    """QFactor multistart instantiation (qf_instantiate); gate_kinds=[...]
+    selects restricted gate kinds (QF_KIND_*)."""
     opt = options if options is not None else default_options()
-    for k, v in kw.items():
-        setattr(opt, k, v)
+    _kinds_keep = _apply_kw(opt, kw)  # noqa: F841
     N = target.shape[0]
     n = _n_of(N)
     locs = np.asarray(locs, np.int32).reshape(-1, 2)
@@ -272,8 +291,7 @@ def instantiate_batch(block_n, gate_offsets, locations, targets: torch.Tensor, i
     """Batched QFactor over many small blocks (qf_instantiate_batch); the
     arguments are in the flat layout that pack_batch produces."""
     opt = options if options is not None else default_options()
-    for k, v in kw.items():
-        setattr(opt, k, v)
+    _kinds_keep = _apply_kw(opt, kw)  # noqa: F841
     bn = np.ascontiguousarray(block_n, np.int32)
     go = np.ascontiguousarray(gate_offsets, np.int32)
     lf = np.ascontiguousarray(locations, np.int32).reshape(-1)
@@ -479,8 +497,7 @@ def delete_gates(target: torch.Tensor, locs, gates: torch.Tensor, pool: torch.Te
     """Uni-directional gate-deletion sweep (qf_delete_gates): gates (p, 4, 4)
     realise target on `locs`; pool (S, p, 4, 4) seeds starts 1..S-1."""
     opt = options if options is not None else default_options()
-    for k, v in kw.items():
-        setattr(opt, k, v)
+    _kinds_keep = _apply_kw(opt, kw)  # noqa: F841
     N = target.shape[0]
     n = _n_of(N)
     locs = np.asarray(locs, np.int32).reshape(-1, 2)

@@ -88,7 +88,7 @@ int resolve_mode(int n, const qf_options& o) {
 // Workspace layout of qf_instantiate.
 struct Layout {
   size_t X = 0, R = 0, gates = 0, uold = 0, partials = 0, counters = 0, costs = 0, trace = 0,
-         frozen = 0, locs = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0;
+         frozen = 0, locs = 0, kinds = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0;
   size_t total = 0;
   int ring = 2;
 };
@@ -114,6 +114,7 @@ Layout make_layout(int n, int p, int S, const qf_options& o, int mode, int histo
   L.gates = take((size_t)S * p * 16 * 16);
   L.costs = take((size_t)S * 8);
   L.locs = take((size_t)p * 2 * 4);
+  L.kinds = take((size_t)p * 4);
   L.ring = std::max(2, o.long_diff_count + 1);
   if (mode == QF_MODE_RESIDENT) {
     L.hist = take((size_t)S * L.ring * 8);
@@ -157,6 +158,14 @@ int validate_problem(qf_ctx* ctx, int n, int p, const int32_t* locs, int S) {
     if (!valid_loc(n, locs + 2 * g))
       return fail(ctx, QF_EINVAL, "gate %d: location (%d, %d) invalid for n=%d", g, locs[2 * g], locs[2 * g + 1], n);
   if (S < 1) return fail(ctx, QF_EINVAL, "n_starts must be >= 1");
+  return QF_OK;
+}
+
+int validate_kinds(qf_ctx* ctx, const int32_t* kinds, int count) {
+  if (!kinds) return QF_OK;
+  for (int g = 0; g < count; ++g)
+    if (kinds[g] < QF_KIND_U4 || kinds[g] > QF_KIND_GPI)
+      return fail(ctx, QF_EINVAL, "gate %d: unknown gate kind %d", g, kinds[g]);
   return QF_OK;
 }
 
@@ -454,6 +463,20 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
 
   auto update = [&](Group& q, int g, int half, hipEvent_t after_env) -> int {
     EnvArgs& ea = q.ea;
+    const int kind = o.gate_kinds ? o.gate_kinds[g] : QF_KIND_U4;
+    if (kind == QF_KIND_FIXED) {  // never optimised: move the gate across, no environment
+      Operand ud{ea.gates + 2 * 16 * (int64_t)g, gstride, 1};
+      Operand u{ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
+      if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
+      QF_HIP(ctx, timer.begin(q.st, 0));
+      if (half == 0)
+        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], ud, u));
+      else
+        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], u, ud));
+      QF_HIP(ctx, timer.end(q.st));
+      return QF_OK;
+    }
+    ea.kind = kind;
     ea.q0 = locs[2 * g];
     ea.q1 = locs[2 * g + 1];
     ea.half = half;
@@ -653,6 +676,7 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
   a.out_info = reinterpret_cast<int32_t*>(ws + L.info);
   a.history_out = history_rows > 0 ? reinterpret_cast<double*>(ws + L.histo) : nullptr;
   a.history_rows = history_rows;
+  a.kinds = o.gate_kinds ? reinterpret_cast<const int32_t*>(ws + L.kinds) : nullptr;
   QF_HIP(ctx, launch_fill_i32(st, a.sync, 0, 16));
   QF_HIP(ctx, launch_fill_i32(st, a.out_info, 0, 16));
   int ok = 0;
@@ -687,7 +711,7 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
 
 // Workspace layout of qf_instantiate_batch.
 struct BatchLayout {
-  size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, hist = 0, scratch = 0, cost = 0,
+  size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, kinds = 0, hist = 0, scratch = 0, cost = 0,
          best = 0, status = 0, sweeps = 0, queue = 0;
   size_t total = 0;
   int ring = 2, groups = 0;
@@ -707,6 +731,7 @@ BatchLayout make_batch_layout(int n_blocks, int total_gates, int S, const qf_opt
   L.gate_off = take((nb + 1) * 4);
   L.tgt_off = take(nb * 8);
   L.locs = take((size_t)total_gates * 8);
+  L.kinds = take((size_t)total_gates * 4);
   L.ring = std::max(2, o.long_diff_count + 1);
   L.hist = take(nb * S * L.ring * 8);
   L.groups = batch_groups(n_blocks, S);
@@ -860,6 +885,7 @@ void qf_options_default(qf_options* o) {
   o->mode = QF_MODE_AUTO;
   o->recheck_below = 1e-3;
   o->stream_groups = 0;
+  o->gate_kinds = nullptr;
 }
 
 int qf_create(qf_ctx** out, int device, void* hip_stream) {
@@ -1072,6 +1098,7 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
   if (rc) return rc;
   rc = validate_problem(ctx, n, n_gates, locations, n_starts);
   if (rc) return rc;
+  if ((rc = validate_kinds(ctx, o.gate_kinds, n_gates))) return rc;
   if (!target || !init_gates || !out_gates || !out_costs)
     return fail(ctx, QF_EINVAL, "NULL pointer argument");
   if (stats && stats->cost_history && stats->cost_history_rows < 0)
@@ -1088,6 +1115,8 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
   const size_t gate_bytes = (size_t)n_starts * n_gates * 256;
   QF_HIP(ctx, hipMemcpyAsync(ws + L.gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
   QF_HIP(ctx, hipMemcpyAsync(ws + L.locs, locations, (size_t)n_gates * 8, hipMemcpyHostToDevice, st));
+  if (o.gate_kinds)
+    QF_HIP(ctx, hipMemcpyAsync(ws + L.kinds, o.gate_kinds, (size_t)n_gates * 4, hipMemcpyHostToDevice, st));
 
   if (stats) {
     stats->pass_launches = stats->env_launches = 0;
@@ -1169,6 +1198,7 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   if (rc) return rc;
   rc = validate_batch(ctx, n_blocks, block_n, gate_offsets, locations, n_starts);
   if (rc) return rc;
+  if ((rc = validate_kinds(ctx, o.gate_kinds, gate_offsets[n_blocks]))) return rc;
   if (!targets || !init_gates || !out_gates || !out_costs) return fail(ctx, QF_EINVAL, "NULL pointer argument");
   const int total_gates = gate_offsets[n_blocks];
   const BatchLayout L = make_batch_layout(n_blocks, total_gates, n_starts, o);
@@ -1195,6 +1225,8 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   QF_HIP(ctx, hipMemcpyAsync(ws + L.gate_off, gate_offsets, (size_t)(n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
   QF_HIP(ctx, hipMemcpyAsync(ws + L.tgt_off, tgt_off.data(), (size_t)n_blocks * 8, hipMemcpyHostToDevice, st));
   QF_HIP(ctx, hipMemcpyAsync(ws + L.locs, locations, (size_t)total_gates * 8, hipMemcpyHostToDevice, st));
+  if (o.gate_kinds)
+    QF_HIP(ctx, hipMemcpyAsync(ws + L.kinds, o.gate_kinds, (size_t)total_gates * 4, hipMemcpyHostToDevice, st));
   const size_t gate_bytes = (size_t)total_gates * n_starts * 256;
   if (out_gates != init_gates)
     QF_HIP(ctx, hipMemcpyAsync(out_gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
@@ -1221,6 +1253,7 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   a.out_status = reinterpret_cast<int32_t*>(ws + L.status);
   a.out_sweeps = reinterpret_cast<int32_t*>(ws + L.sweeps);
   a.queue = queue;
+  a.kinds = o.gate_kinds ? reinterpret_cast<const int32_t*>(ws + L.kinds) : nullptr;
   // grid <= min(groups, kBatchMaxGrid), the count the scratch was sized for
   const int grid = batch_grid(o.precision, L.groups);
   const bool timed = stats && stats->timing;
@@ -1579,6 +1612,7 @@ int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const i
   else
     qf_options_default(&o);
   if ((rc = validate_options(ctx, o))) return rc;
+  if ((rc = validate_kinds(ctx, o.gate_kinds, p))) return rc;
   const size_t need = qf_delete_gates_workspace_size(n, p, S, &o);
   if (!workspace || ws_bytes < need)
     return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
@@ -1639,7 +1673,13 @@ int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const i
     }
     std::vector<double> costs(S);
     qf_stats ist{};
-    rc = qf_instantiate(ctx, n, target, q, sub_locs.data(), all, S, tol, &o, ws, inner, best, nullptr, costs.data(),
+    qf_options oa = o;
+    std::vector<int32_t> sub_kinds;
+    if (o.gate_kinds) {
+      for (int k : idx) sub_kinds.push_back(o.gate_kinds[k]);
+      oa.gate_kinds = sub_kinds.data();
+    }
+    rc = qf_instantiate(ctx, n, target, q, sub_locs.data(), all, S, tol, &oa, ws, inner, best, nullptr, costs.data(),
                         &ist);
     if (rc && rc != QF_ENUMERIC) return rc;
     ++attempts;

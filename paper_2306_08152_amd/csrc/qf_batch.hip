@@ -100,6 +100,7 @@ struct BatchDev {
   double* out_cost;         // (block, start)
   int32_t* out_best, *out_status, *out_sweeps;
   int32_t* queue;           // work counter (zero before launch)
+  const int32_t* kinds;     // gate kinds over all gates (nullptr = all general U(4))
 };
 
 // Per-quad problem description.
@@ -110,6 +111,7 @@ struct QuadJob {
   const int32_t* locs;  // this block's locations
   const cd* V;          // this block's target
   cd* g;                // this start's gates (p x 16)
+  const int32_t* kinds; // this block's gate kinds (nullptr = all general U(4))
 };
 
 // Builder <- G_p ... G_1 V^dagger for one quad, in precision Q, at X
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(64) void k_batch(BatchDev d) {
     jb.locs = d.locs + 2 * (size_t)d.gate_off[jb.b];
     jb.V = d.V + (jb.valid ? d.tgt_off[jb.b] : 0);
     jb.g = d.gates + ((size_t)d.gate_off[jb.b] * d.S + (size_t)jb.s * jb.p) * 16;
+    jb.kinds = d.kinds ? d.kinds + d.gate_off[jb.b] : nullptr;
     const int pmax = wave_max_int(jb.p);
     double* hist = d.hist + ((size_t)jb.b * d.S + jb.s) * d.ring;
 
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(64) void k_batch(BatchDev d) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) unew[c] = at_rk(uold, r, c);
           } else {
-            optimize_gate_f64_quad(erow, uold, r, o.beta, unew);
+            update_gate_quad(jb.kinds ? jb.kinds[g] : kKindU4, erow, uold, r, o.beta, unew);
           }
 #pragma unroll
           for (int c = 0; c < 4; ++c) jb.g[16 * g + 4 * r + c] = unew[c];
@@ -414,6 +417,7 @@ hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs
   d.out_status = a.out_status;
   d.out_sweeps = a.out_sweeps;
   d.queue = a.queue;
+  d.kinds = a.kinds;
   if (precision == QF_C64)
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(64), 0, st, d);
   else

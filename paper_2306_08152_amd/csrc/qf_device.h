@@ -375,4 +375,122 @@ __device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[1
   }
 }
 
+// ---------------------------------------------------------------- gate kinds
+//
+// Restricted gates (Sec. III-A-3, Specializing Gate Sets; the U3 + CNOT set
+// of the evaluation).  Every gate is stored as a 4 x 4 matrix on its two
+// locations; single-qubit kinds act on the first and are stored as g (x) I,
+// the second location being only a partner qubit.  For them
+// Re Tr(E (g (x) I)) = Re Tr(E2 g) with E2[a][b] = E[2a][2b] + E[2a+1][2b+1],
+// and the update maximises Re Tr(M2 g), M2 = (1-beta) E2 + beta g_old^dagger:
+//   U(2): g = W^dagger, W the unitary polar factor of M2.  For a 2 x 2 matrix
+//         M = W P (P = diag(s1, s2) in its eigenbasis), P + s1 s2 P^-1 =
+//         (s1 + s2) I, hence M + |det M| M^-dagger = (s1 + s2) W, and
+//         |det M| M^-dagger = e^{i arg det M} adj(M)^dagger; W is that sum
+//         divided by its Frobenius norm / sqrt 2.  A singular M (det = 0)
+//         gives a rank-one M plus the orthogonal rank-one completion, which
+//         attains the same maximum.
+//   Rz:   g = diag(1, e^{it}), t = -arg M2[1][1]
+//   GPI:  g = [[0, e^{-if}], [e^{if}, 0]], f = -arg(M2[0][1] + conj(M2[1][0]))
+//   fixed: the gate is kept.
+// A zero M2 (or a zero quantity to take the argument of) keeps the gate.
+enum : int { kKindU4 = 0, kKindFixed = 1, kKindU2 = 2, kKindRz = 3, kKindGpi = 4 };
+
+// Lane r of a quad passes row r of E and the whole u_old; receives row r of
+// the new stored matrix.  Every lane computes the same 2 x 2 update.
+__device__ inline void update_gate_quad(int kind, const cd e_row[4], const cd uold[16], int r, double beta,
+                                        cd unew_row[4]) {
+  if (kind == kKindU4) {
+    optimize_gate_f64_quad(e_row, uold, r, beta, unew_row);
+    return;
+  }
+  if (kind == kKindFixed) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unew_row[c] = at_rk(uold, r, c);
+    return;
+  }
+  cd col[4][4];  // col[j][k] = E[k][j]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) quad_gather(e_row[j], col[j]);
+  const double we = 1.0 - beta;
+  cd m[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const cd e2 = col[2 * b][2 * a] + col[2 * b + 1][2 * a + 1];
+      m[a][b] = scale(e2, we) + scale(conj(uold[4 * (2 * b) + 2 * a]), beta);  // + beta g_old^dagger
+    }
+  bool finite = true;
+  double amax = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      finite = finite && finite_d(m[a][b].re) && finite_d(m[a][b].im);
+      amax = fmax(amax, fmax(fabs(m[a][b].re), fabs(m[a][b].im)));
+    }
+  cd g[2][2];
+  bool keep = false;
+  if (kind == kKindU2) {
+    keep = !(amax >= 1e-300);
+    const double inv = keep ? 1.0 : rcp_nr(amax);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) m[a][b] = scale(m[a][b], inv);
+    const cd det = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+    const double ad = sqrt(norm2(det));
+    const cd ph = ad > 0.0 ? scale(det, 1.0 / ad) : mk(1.0, 0.0);
+    // B = M + ph adj(M)^dagger, adj(M) = [[m11, -m01], [-m10, m00]]
+    cd bm[2][2];
+    bm[0][0] = m[0][0] + ph * conj(m[1][1]);
+    bm[0][1] = m[0][1] - ph * conj(m[1][0]);
+    bm[1][0] = m[1][0] - ph * conj(m[0][1]);
+    bm[1][1] = m[1][1] + ph * conj(m[0][0]);
+    const double nb = sqrt(0.5 * (norm2(bm[0][0]) + norm2(bm[0][1]) + norm2(bm[1][0]) + norm2(bm[1][1])));
+    const double inb = 1.0 / nb;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) g[a][b] = scale(conj(bm[b][a]), inb);  // W^dagger
+  } else if (kind == kKindRz) {
+    const double a11 = sqrt(norm2(m[1][1]));
+    keep = !(a11 >= 1e-300);
+    g[0][0] = mk(1.0, 0.0);
+    g[0][1] = mk(0.0, 0.0);
+    g[1][0] = mk(0.0, 0.0);
+    g[1][1] = keep ? mk(1.0, 0.0) : scale(conj(m[1][1]), 1.0 / a11);
+  } else {  // GPI
+    const cd w = m[0][1] + conj(m[1][0]);
+    const double aw = sqrt(norm2(w));
+    keep = !(aw >= 1e-300);
+    const cd e = keep ? mk(1.0, 0.0) : scale(w, 1.0 / aw);  // e^{-if}
+    g[0][0] = mk(0.0, 0.0);
+    g[0][1] = e;
+    g[1][0] = conj(e);
+    g[1][1] = mk(0.0, 0.0);
+  }
+  if (!finite) {
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unew_row[c] = mk(nan, nan);
+    return;
+  }
+  if (keep) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unew_row[c] = at_rk(uold, r, c);
+    return;
+  }
+  // row r = (a, c) of g (x) I: entry (b, d) is g[a][b] when d = c
+  const int a = r >> 1, cbit = r & 1;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const cd v = sel(a == 0, g[0][b], g[1][b]);
+      unew_row[2 * b + d] = sel(d == cbit, v, mk(0.0, 0.0));
+    }
+}
+
 }  // namespace qf

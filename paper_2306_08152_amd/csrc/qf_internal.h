@@ -64,6 +64,7 @@ struct EnvArgs {
   const int32_t* frozen;  // optional per-start flag: nonzero keeps the gate
   double* partials;       // c128 S x env_workgroups(n) x 16 (needed when > 1 workgroup)
   int32_t* counters;      // S ints, zero before the first launch; left zero
+  int kind;               // qf_gate_kind of the updated gate (update mode)
 };
 uint32_t env_workgroups(int n);
 // Small fill kernel (used instead of hipMemsetAsync so the enqueued work can
@@ -97,6 +98,7 @@ struct ResidentArgs {
   int32_t* out_info;      // [0]=sweeps [1]=decision [2]=resets [3]=rechecks [4]=timeout
   double* history_out;    // optional (rows x S)
   int32_t history_rows;
+  const int32_t* kinds;   // device, p gate kinds (nullptr = all general U(4))
 };
 hipError_t launch_resident(hipStream_t st, const ResidentArgs& a, int* ok_coresident);
 
@@ -120,6 +122,7 @@ struct BatchArgs {
   int32_t* out_status;      // device, n_blocks
   int32_t* out_sweeps;      // device, n_blocks
   int32_t* queue;           // device, 1 (zero before launch)
+  const int32_t* kinds;     // device, total_gates gate kinds (nullptr = all general U(4))
 };
 // Quads of one wavefront hold (block, start) pairs: 16 / S blocks per group
 // of work; at most kBatchMaxGrid workgroups, each with its own FP64 scratch.

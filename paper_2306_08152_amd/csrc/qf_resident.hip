@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) unew[c] = urow[c];
         } else {
-          optimize_gate_f64_quad(erow, uold, r, o.beta, unew);
+          update_gate_quad(a.kinds ? a.kinds[g] : kKindU4, erow, uold, r, o.beta, unew);
         }
         // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored.
         // Row r of u_old^dagger is conj(column r of u_old).

@@ -467,7 +467,7 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
 #pragma unroll
     for (int c = 0; c < 4; ++c) unew[c] = urow[c];
   } else {
-    optimize_gate_f64_quad(erow, uold, r, a.beta, unew);
+    update_gate_quad(a.kind, erow, uold, r, a.beta, unew);
   }
   cd* uo = reinterpret_cast<cd*>(a.uold) + 16 * (size_t)s;
 #pragma unroll

@@ -189,6 +189,38 @@ def deletion_problem(config_id: int, n: int, p: int, p_target: int, n_starts: in
     return locs, V, g, pool
 
 
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], np.complex128)
+
+
+def u3cx_problem(config_id: int, n: int, layers: int, n_starts: int, build_target: bool = True):
+    """The evaluation's U3 + CNOT gate set (kinds: 2 = U(2) variable stored as
+    g (x) I on (q, partner), 1 = fixed CNOT): every layer puts a U(2) gate on
+    each qubit (partner = the next qubit, the last one's the previous) and
+    then CNOTs on (q, q+1) for q of the layer's parity; a final U(2) layer
+    closes the circuit.  Target gates Haar (role 0), initial U(2) gates Haar
+    per start (role 1).  Returns locs, kinds, target gates, target, init."""
+    locs, kinds = [], []
+    for layer in range(layers + 1):
+        for q in range(n):
+            locs.append((q, q + 1 if q + 1 < n else q - 1))
+            kinds.append(2)
+        if layer == layers:
+            break
+        for q in range(layer % 2, n - 1, 2):
+            locs.append((q, q + 1))
+            kinds.append(1)
+    locs = np.array(locs, np.int32)
+    kinds = np.array(kinds, np.int32)
+
+    def draw(rng):
+        return np.stack([np.kron(haar_unitary(rng, 2), np.eye(2)) if k == 2 else CNOT for k in kinds])
+
+    tg = draw(rng_for(config_id, ROLE_TARGET, 0))
+    init = np.stack([draw(rng_for(config_id, ROLE_INIT, s)) for s in range(n_starts)])
+    target = circuit_unitary(tg, locs, n) if build_target else None
+    return locs, kinds, tg, target, init
+
+
 def random_builder(rng: np.random.Generator, n_starts: int, n: int) -> np.ndarray:
     """Generic complex test matrices (S, N, N) with entries ~ CN(0, 1/N)."""
     N = 1 << n
