@@ -79,8 +79,15 @@ typedef enum { QF_LEFT = 0, QF_RIGHT = 1 } qf_side;
  *   QF_KIND_U2    general U(2) (unitary polar factor, closed form for 2 x 2)
  *   QF_KIND_RZ    diag(1, e^{it}), t = -arg M2[1][1]
  *   QF_KIND_GPI   [[0, e^{-if}], [e^{if}, 0]], f = -arg(M2[0][1] + conj M2[1][0])
+ *   QF_KIND_MS    two-qubit Molmer-Sorensen MS(f1, f2) = exp(-i pi/4
+ *                 sigma_f1 (x) sigma_f2) on both locations: e^{i(f1+f2)} =
+ *                 conj(w_s)/|w_s|, e^{i(f1-f2)} = conj(w_d)/|w_d| with
+ *                 w_s = -i M[0][3] + i conj M[3][0], w_d = -i M[1][2] +
+ *                 i conj M[2][1], M = (1-beta) E + beta u_old^dagger
  * (M2 = (1-beta) E2 + beta g_old^dagger; a zero argument keeps the gate.) */
-typedef enum { QF_KIND_U4 = 0, QF_KIND_FIXED = 1, QF_KIND_U2 = 2, QF_KIND_RZ = 3, QF_KIND_GPI = 4 } qf_gate_kind;
+typedef enum {
+  QF_KIND_U4 = 0, QF_KIND_FIXED = 1, QF_KIND_U2 = 2, QF_KIND_RZ = 3, QF_KIND_GPI = 4, QF_KIND_MS = 5
+} qf_gate_kind;
 
 typedef enum {
   QF_CONVERGED = 0,  /* best start's final cost < tol */

@@ -71,7 +71,8 @@ __all__ = [
     "STATUS_CONVERGED", "STATUS_PLATEAU", "STATUS_MAX_ITER", "STATUS_NUMERIC",
     "nuclear_norm", "frobenius_distance_sq", "optimize_gate_batched", "builder_rows",
     "cost_gradient", "PAULI2", "su4_hermitian", "su4_gate", "su4_theta_gradient", "param_cost_gradient",
-    "KIND_U4", "KIND_FIXED", "KIND_U2", "KIND_RZ", "KIND_GPI", "optimize_gate_kind", "rz", "gpi",
+    "KIND_U4", "KIND_FIXED", "KIND_U2", "KIND_RZ", "KIND_GPI", "KIND_MS", "optimize_gate_kind", "rz", "gpi",
+    "ms",
 ]
 
 STATUS_CONVERGED = 0
@@ -318,11 +319,17 @@ def optimize_gate(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -> np.nda
 #   KIND_GPI   GPI(f) = [[0, e^{-if}], [e^{if}, 0]]: Re Tr(M2 GPI) =
 #              Re((M2[0,1] + conj(M2[1,0])) e^{if}), maximal at
 #              f = -arg(M2[0,1] + conj(M2[1,0]))
+#   KIND_MS    the two-qubit Molmer-Sorensen gate MS(f1, f2) (both qubits):
+#              with s = f1 + f2 and d = f1 - f2, Re Tr(M MS) is a constant
+#              plus Re(w_s e^{is}) + Re(w_d e^{id}) (over sqrt 2), where
+#              w_s = -i M[0,3] + i conj(M[3,0]) and w_d = -i M[1,2] +
+#              i conj(M[2,1]), M = (1 - beta) E + beta u_old^dagger; s and d
+#              are independent, so e^{is} = conj(w_s)/|w_s|, e^{id} likewise.
 # A zero quantity to take the argument of (modulus below 1e-300) keeps the
 # old gate, like a zero environment (Q15).
 # ---------------------------------------------------------------------------
 
-KIND_U4, KIND_FIXED, KIND_U2, KIND_RZ, KIND_GPI = 0, 1, 2, 3, 4
+KIND_U4, KIND_FIXED, KIND_U2, KIND_RZ, KIND_GPI, KIND_MS = 0, 1, 2, 3, 4, 5
 
 
 def rz(t: float) -> np.ndarray:
@@ -331,6 +338,18 @@ def rz(t: float) -> np.ndarray:
 
 def gpi(f: float) -> np.ndarray:
     return np.array([[0.0, np.exp(-1j * f)], [np.exp(1j * f), 0.0]], np.complex128)
+
+
+def ms(f1: float, f2: float) -> np.ndarray:
+    """MS(f1, f2) = exp(-i pi/4 sigma_f1 (x) sigma_f2), sigma_f = cos f X + sin f Y."""
+    es, ed = np.exp(1j * (f1 + f2)), np.exp(1j * (f1 - f2))
+    return np.array([[1, 0, 0, -1j / es], [0, 1, -1j / ed, 0], [0, -1j * ed, 1, 0], [-1j * es, 0, 0, 1]],
+                    np.complex128) / np.sqrt(2.0)
+
+
+def _ms_from_phases(us: complex, ud: complex) -> np.ndarray:
+    return np.array([[1, 0, 0, -1j * np.conj(us)], [0, 1, -1j * np.conj(ud), 0], [0, -1j * ud, 1, 0],
+                     [-1j * us, 0, 0, 1]], np.complex128) / np.sqrt(2.0)
 
 
 def _partner_trace(E: np.ndarray) -> np.ndarray:
@@ -344,6 +363,15 @@ def optimize_gate_kind(E: np.ndarray, u_old: np.ndarray, kind: int, beta: float 
         return optimize_gate(E, u_old, beta)
     if kind == KIND_FIXED:
         return u_old.copy()
+    if kind == KIND_MS:
+        M = (1.0 - beta) * E + beta * u_old.conj().T
+        if not np.all(np.isfinite(M)):
+            return np.full_like(u_old, np.nan)
+        ws = -1j * M[0, 3] + 1j * np.conj(M[3, 0])
+        wd = -1j * M[1, 2] + 1j * np.conj(M[2, 1])
+        if abs(ws) < 1e-300 or abs(wd) < 1e-300:
+            return u_old.copy()
+        return _ms_from_phases(np.conj(ws) / abs(ws), np.conj(wd) / abs(wd))
     g_old = u_old[::2, ::2]  # g of g (x) I_2
     M = (1.0 - beta) * _partner_trace(E) + beta * g_old.conj().T
     if not np.all(np.isfinite(M)):

@@ -12,7 +12,7 @@ QF_C128, QF_C64 = 0, 1
 QF_MODE_AUTO, QF_MODE_RESIDENT, QF_MODE_STREAMING = 0, 1, 2
 QF_LEFT, QF_RIGHT = 0, 1
 QF_CONVERGED, QF_PLATEAU, QF_MAX_ITER, QF_NUMERIC = 0, 1, 2, 3
-QF_KIND_U4, QF_KIND_FIXED, QF_KIND_U2, QF_KIND_RZ, QF_KIND_GPI = 0, 1, 2, 3, 4
+QF_KIND_U4, QF_KIND_FIXED, QF_KIND_U2, QF_KIND_RZ, QF_KIND_GPI, QF_KIND_MS = 0, 1, 2, 3, 4, 5
 
 EXPORTED = [
     "qf_create", "qf_destroy", "qf_set_stream", "qf_strerror", "qf_last_error", "qf_options_default",

@@ -164,7 +164,7 @@ int validate_problem(qf_ctx* ctx, int n, int p, const int32_t* locs, int S) {
 int validate_kinds(qf_ctx* ctx, const int32_t* kinds, int count) {
   if (!kinds) return QF_OK;
   for (int g = 0; g < count; ++g)
-    if (kinds[g] < QF_KIND_U4 || kinds[g] > QF_KIND_GPI)
+    if (kinds[g] < QF_KIND_U4 || kinds[g] > QF_KIND_MS)
       return fail(ctx, QF_EINVAL, "gate %d: unknown gate kind %d", g, kinds[g]);
   return QF_OK;
 }

@@ -393,8 +393,13 @@ __device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[1
 //   Rz:   g = diag(1, e^{it}), t = -arg M2[1][1]
 //   GPI:  g = [[0, e^{-if}], [e^{if}, 0]], f = -arg(M2[0][1] + conj(M2[1][0]))
 //   fixed: the gate is kept.
+// The two-qubit Molmer-Sorensen kind MS(f1, f2) acts on both locations; with
+// M = (1-beta) E + beta u_old^dagger, s = f1 + f2 and d = f1 - f2,
+// Re Tr(M MS) = const + (Re(w_s e^{is}) + Re(w_d e^{id})) / sqrt 2 with
+// w_s = -i M[0][3] + i conj(M[3][0]), w_d = -i M[1][2] + i conj(M[2][1]);
+// s and d are independent, so e^{is} = conj(w_s) / |w_s| and likewise d.
 // A zero M2 (or a zero quantity to take the argument of) keeps the gate.
-enum : int { kKindU4 = 0, kKindFixed = 1, kKindU2 = 2, kKindRz = 3, kKindGpi = 4 };
+enum : int { kKindU4 = 0, kKindFixed = 1, kKindU2 = 2, kKindRz = 3, kKindGpi = 4, kKindMs = 5 };
 
 // Lane r of a quad passes row r of E and the whole u_old; receives row r of
 // the new stored matrix.  Every lane computes the same 2 x 2 update.
@@ -413,6 +418,38 @@ __device__ inline void update_gate_quad(int kind, const cd e_row[4], const cd uo
 #pragma unroll
   for (int j = 0; j < 4; ++j) quad_gather(e_row[j], col[j]);
   const double we = 1.0 - beta;
+  if (kind == kKindMs) {
+    // M[j][k] = we E[j][k] + beta conj(u_old[k][j])
+    const cd m03 = scale(col[3][0], we) + scale(conj(uold[4 * 3 + 0]), beta);
+    const cd m30 = scale(col[0][3], we) + scale(conj(uold[4 * 0 + 3]), beta);
+    const cd m12 = scale(col[2][1], we) + scale(conj(uold[4 * 2 + 1]), beta);
+    const cd m21 = scale(col[1][2], we) + scale(conj(uold[4 * 1 + 2]), beta);
+    const cd mi = mk(0.0, -1.0), pi = mk(0.0, 1.0);
+    const cd ws = mi * m03 + pi * conj(m30), wd = mi * m12 + pi * conj(m21);
+    const bool fin = finite_d(ws.re) && finite_d(ws.im) && finite_d(wd.re) && finite_d(wd.im);
+    const double as = sqrt(norm2(ws)), adn = sqrt(norm2(wd));
+    if (!fin) {
+      const double nan = __builtin_nan("");
+#pragma unroll
+      for (int c = 0; c < 4; ++c) unew_row[c] = mk(nan, nan);
+      return;
+    }
+    if (!(as >= 1e-300) || !(adn >= 1e-300)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) unew_row[c] = at_rk(uold, r, c);
+      return;
+    }
+    const cd us = scale(conj(ws), 1.0 / as), ud = scale(conj(wd), 1.0 / adn);  // e^{is}, e^{id}
+    const double h = 0.70710678118654752440;  // 1 / sqrt 2
+    const cd z = mk(0.0, 0.0), dg = mk(h, 0.0);
+    const cd a03 = scale(mi * conj(us), h), a30 = scale(mi * us, h);
+    const cd a12 = scale(mi * conj(ud), h), a21 = scale(mi * ud, h);
+    unew_row[0] = sel(r == 0, dg, sel(r == 3, a30, z));
+    unew_row[1] = sel(r == 1, dg, sel(r == 2, a21, z));
+    unew_row[2] = sel(r == 1, a12, sel(r == 2, dg, z));
+    unew_row[3] = sel(r == 0, a03, sel(r == 3, dg, z));
+    return;
+  }
   cd m[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)

@@ -1,6 +1,7 @@
 """GPU parity of the gate kinds (Sec. III-A-3 and the U3 + CNOT gate set):
-fixed gates, U(2), Rz and GPI single-qubit gates beside general U(4), in the
-streaming, resident and batched paths, against the oracle."""
+fixed gates, U(2), Rz and GPI single-qubit gates and the Molmer-Sorensen
+gate beside general U(4), in the streaming, resident and batched paths,
+against the oracle."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,7 @@ def host(t):
 
 def mixed_problem(seed, n, S, reachable=False):
     """Every kind in one circuit: U(2) on each qubit, CNOTs and Rz gates along
-    the chain, a GPI and a general U(4)."""
+    the chain, a GPI, a general U(4) and an MS gate."""
     rng = np.random.default_rng(seed)
     locs, kinds = [], []
     for q in range(n):
@@ -40,6 +41,8 @@ def mixed_problem(seed, n, S, reachable=False):
     kinds.append(O.KIND_GPI)
     locs.append((n - 2, n - 1))
     kinds.append(O.KIND_U4)
+    locs.append((1, 0))
+    kinds.append(O.KIND_MS)
     locs = np.array(locs, np.int32)
     kinds = np.array(kinds, np.int32)
 
@@ -54,6 +57,8 @@ def mixed_problem(seed, n, S, reachable=False):
                 out.append(np.kron(O.rz(rng.uniform(-3, 3)), np.eye(2)))
             elif k == O.KIND_GPI:
                 out.append(np.kron(O.gpi(rng.uniform(-3, 3)), np.eye(2)))
+            elif k == O.KIND_MS:
+                out.append(O.ms(*rng.uniform(-3, 3, 2)))
             else:
                 out.append(I.haar_unitary(rng, 4))
         return np.stack(out)

@@ -678,3 +678,29 @@ def test_kinds_fixed_point_of_own_circuit():
     V = O.circuit_unitary(g0, locs, n)
     g1 = O.sweep_definition(V, g0, locs, n, kinds=kinds)
     assert O.cost(V, g1, locs, n) < 1e-13
+
+
+def test_ms_definition_and_update():
+    """MS(f1, f2) equals exp(-i pi/4 sigma_f1 (x) sigma_f2) (matrix exponential
+    of the defining Hamiltonian), and the MS update attains the maximum of
+    Re Tr(E MS(f1, f2)) over a dense grid of both angles."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(1050)
+    X = np.array([[0, 1], [1, 0]], np.complex128)
+    Y = np.array([[0, -1j], [1j, 0]], np.complex128)
+    for _ in range(3):
+        f1, f2 = rng.uniform(-3, 3, 2)
+        s1 = np.cos(f1) * X + np.sin(f1) * Y
+        s2 = np.cos(f2) * X + np.sin(f2) * Y
+        assert np.abs(O.ms(f1, f2) - expm(-1j * np.pi / 4 * np.kron(s1, s2))).max() < 1e-14
+    f = np.linspace(-np.pi, np.pi, 721)
+    F1, F2 = np.meshgrid(f, f, indexing="ij")
+    for _ in range(3):
+        E = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        u = O.optimize_gate_kind(E, O.ms(0.3, -1.1), O.KIND_MS)
+        best = np.real(np.trace(E @ u))
+        es, ed = np.exp(1j * (F1 + F2)), np.exp(1j * (F1 - F2))
+        grid = (np.real(np.trace(E)) + np.real(-1j * E[3, 0] / es - 1j * E[0, 3] * es)
+                + np.real(-1j * E[2, 1] / ed - 1j * E[1, 2] * ed)) / np.sqrt(2.0)
+        assert best >= grid.max() - 1e-12 and best - grid.max() < 1e-4
+        assert np.abs(u.conj().T @ u - np.eye(4)).max() < 1e-14
