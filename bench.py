@@ -15,10 +15,11 @@ full n = 6 / n = 3 instantiations (converged instantiations per second), and
 the batched workload of 4096 independent 3- and 4-qubit blocks x 8 starts in
 one persistent launch (converged blocks per second), and at n = 12 the
 gradient (evaluations per second) and the L-BFGS baseline against QFactor
-sweeps from the same initial circuit, and a gate-deletion sweep (n = 5).
+sweeps from the same initial circuit, a gate-deletion sweep (n = 5), and the
+U3 + CNOT gate set (n = 6, converged instantiations per second).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
-                       [--probe copy|batch|gradient|deletion]
+                       [--probe copy|batch|gradient|deletion|u3cx]
 """
 from __future__ import annotations
 
@@ -65,10 +66,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion"], default=None,
+    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion", "u3cx"], default=None,
                     help="copy: only a plain device copy of known size (traffic-counter calibration); "
                          "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
-                         "and L-BFGS workload; deletion: only the gate-deletion sweep")
+                         "and L-BFGS workload; deletion: only the gate-deletion sweep; u3cx: only the U3 + CNOT "
+                         "instantiations")
     return ap.parse_args()
 
 
@@ -197,6 +199,32 @@ def gradient_workload(qf, torch) -> dict:
     return out
 
 
+def u3cx_workload(qf, torch) -> dict:
+    """The evaluation's U3 + CNOT gate set: n = 6, 4 layers (U(2) variables
+    on every qubit, fixed CNOTs), 8 starts, reachable target, tol 1e-8;
+    converged instantiations per second in both precisions."""
+    import qfinputs as I
+    locs, kinds, _, V, init = I.u3cx_problem(8, 6, 4, 8)
+    Vd, gd = torch.from_numpy(V).to("cuda"), torch.from_numpy(init).to("cuda")
+    out = {}
+    for prec, tag in ((0, "c128"), (1, "c64")):
+        qf.instantiate(Vd, locs, gd, tol=1e-8, precision=prec, gate_kinds=kinds)  # warm-up
+        times, conv, sw = [], 0, 0
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = qf.instantiate(Vd, locs, gd, tol=1e-8, precision=prec, gate_kinds=kinds)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            conv += int(r.costs[r.best_start] < 1e-8)
+            sw = r.sweeps
+        med = float(np.median(times))
+        out[f"u3cx_n6_l4_s8_{tag}_converged_inst_per_s"] = round((conv / 3) / med, 2)
+        out[f"u3cx_n6_l4_s8_{tag}_ms_per_inst"] = round(1e3 * med, 3)
+        out[f"u3cx_n6_l4_s8_{tag}_sweeps"] = sw
+    return out
+
+
 def deletion_workload(qf, torch) -> dict:
     """Gate-deletion sweep (re-synthesis workflow): n = 5, a 24-gate chain
     whose first 10 gates are identities, 4 starts per attempt, complex64."""
@@ -256,6 +284,9 @@ def main():
         return
     if args.probe == "gradient":
         print(json.dumps(gradient_workload(qf, torch)), flush=True)
+        return
+    if args.probe == "u3cx":
+        print(json.dumps(u3cx_workload(qf, torch)), flush=True)
         return
     if args.probe == "deletion":
         print(json.dumps(deletion_workload(qf, torch)), flush=True)
@@ -342,7 +373,7 @@ def main():
                 times.append(time.perf_counter() - t0)
                 conv += int(r6.costs[r6.best_start] < 1e-8)
                 sw = r6.sweeps
-            extra[f"n6_s32_{tag}_converged_inst_per_s"] = round(conv / sum(times), 3)
+            extra[f"n6_s32_{tag}_converged_inst_per_s"] = round((conv / 3) / float(np.median(times)), 3)
             extra[f"n6_s32_{tag}_ms_per_inst"] = round(1e3 * float(np.median(times)), 3)
             extra[f"n6_s32_{tag}_sweeps"] = sw
         p1 = I.config1()
@@ -359,6 +390,7 @@ def main():
         extra.update(batch_workload(qf, torch))
         extra.update(gradient_workload(qf, torch))
         extra.update(deletion_workload(qf, torch))
+        extra.update(u3cx_workload(qf, torch))
         out["extra"] = extra
 
     if not args.no_cpu:
