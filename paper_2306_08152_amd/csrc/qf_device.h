@@ -167,22 +167,26 @@ __device__ __forceinline__ void quad_gather(cd v, cd o[4]) {
 // follows the symmetric 2x2 Schur step (Golub and Van Loan): with
 // zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 // c = 1 / sqrt(1 + t^2), s = c t, after the phase of g is moved onto column q.
-// Returns 1 if it rotated, 0 if the pair is orthogonal to round-off.
+// The tangent t only steers convergence (any t gives an exact rotation once c
+// and s are consistent with it), so it comes from single-precision hardware
+// estimates; the phase of g and c are computed in FP64 (Newton-refined), so
+// the applied rotation is unitary to FP64 round-off.
+// Returns 1 for a large rotation, 0 for a small one or none (see below).
 __device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, double a, double b, cd g) {
   const double tol2 = 1.6e-31;  // (4e-16)^2: |g| <= 4e-16 sqrt(a b) counts as orthogonal
   const double g2 = norm2(g);
   if (!(g2 > tol2 * (a * b))) return 0.0;
   const double rg = rsqrt_nr(g2);              // 1 / |g|
-  const double zeta = 0.5 * (b - a) * rg;
-  const double az = fabs(zeta);
-  double t;
-  if (az < 1e150) {
-    const double q2 = fma(zeta, zeta, 1.0);
-    t = rcp_nr(az + q2 * rsqrt_nr(q2));        // 1 / (|zeta| + sqrt(1 + zeta^2))
+  const float zeta = (float)(0.5 * (b - a) * rg);
+  const float az = fabsf(zeta);
+  float tf;
+  if (az < 1e18f) {
+    const float q2 = fmaf(zeta, zeta, 1.0f);
+    tf = __builtin_amdgcn_rcpf(az + q2 * __builtin_amdgcn_rsqf(q2));  // 1 / (|zeta| + sqrt(1 + zeta^2))
   } else {
-    t = 0.5 * rcp_nr(az);
+    tf = 0.5f * __builtin_amdgcn_rcpf(az);
   }
-  t = zeta >= 0.0 ? t : -t;
+  const double t = zeta >= 0.0f ? (double)tf : -(double)tf;
   const double c = rsqrt_nr(fma(t, t, 1.0));
   const double s = c * t;
   const cd ph = mk(g.re * rg, -g.im * rg);     // e^{-i arg g}
@@ -316,63 +320,19 @@ __device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4],
 
 // Quad form of OptimizeGate (Sec. III-A-1, Eq. opt_u; beta of Sec. III-A-2).
 // Lane r passes row r of E and the whole u_old (16 entries) and receives row
-// r of u_new.  The maximiser of Re Tr(M u), M = (1-beta) E + beta u_old^dagger,
-// is found as u_new = u_old w* with w* the maximiser of Re Tr(M u_old w):
-// substituting u = u_old w is exact (w ranges over all unitaries), and once
-// the gates change slowly M u_old = (1-beta) E u_old + beta I is close to a
-// positive multiple of the identity, where the Jacobi iteration needs one or
-// two sweeps.
+// r of u_new, the maximiser of Re Tr(M u) for M = (1-beta) E + beta
+// u_old^dagger.  The result is Y X^dagger from the Jacobi step, unitary to
+// round-off whatever the gate's history; a zero M keeps u_old exactly.
 __device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[16], int r, double beta,
                                               cd unew_row[4]) {
-  cd m[4], one[4];
+  cd m[4], keep[4];
   const double we = 1.0 - beta;  // exact 1 for beta = 0
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    cd acc = mk(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cmac(acc, e_row[k], uold[4 * k + c]);
-    m[c] = scale(acc, we);
-    m[c].re += (c == r) ? beta : 0.0;  // + beta I
-    one[c] = mk(c == r ? 1.0 : 0.0, 0.0);
+    m[c] = scale(e_row[c], we) + scale(conj(at_kr(uold, c, r)), beta);  // + beta (u_old^dagger)[r][c]
+    keep[c] = at_rk(uold, r, c);
   }
-  cd w[4];
-  const int st = nearest_unitary_f64_quad(m, one, r, w);  // row r of w*
-  if (st == 1) {  // zero M: keep u_old exactly (uniform over the quad)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) unew_row[c] = at_rk(uold, r, c);
-    return;
-  }
-  // u_new row r = sum_k u_old[r][k] w*[k][.]; rows of w* from the quad
-  cd urow[4], v[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) urow[k] = at_rk(uold, r, k);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) v[c] = mk(0.0, 0.0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cd wall[4];  // wall[k] = w*[k][c]
-    quad_gather(w[c], wall);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cmac(v[c], urow[k], wall[k]);
-  }
-  // u_old w* carries u_old's own distance from unitarity; one Newton-Schulz
-  // step u <- u (3I - u^dagger u) / 2 squares that distance, so the returned
-  // gate is unitary to round-off whatever the history.  (NaN passes through.)
-  cd g[16];  // u^dagger u from every lane's row: g[i][j] = sum_k conj(u[k][i]) u[k][j]
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const cd pr = conj(v[i]) * v[j];
-      g[4 * i + j] = mk(quad_sum(pr.re), quad_sum(pr.im));
-    }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cd acc = scale(v[c], 3.0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc = acc - v[k] * g[4 * k + c];
-    unew_row[c] = scale(acc, 0.5);
-  }
+  nearest_unitary_f64_quad(m, keep, r, unew_row);
 }
 
 // ---------------------------------------------------------------- gate kinds

@@ -421,7 +421,8 @@ struct EnvDev {
 
 // Finish one start on the 4 lanes of a quad (lane r = row r): P (16 FP64
 // complex, LDS) -> env_out and/or the gate update.
-__device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P, int r) {
+__device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
+                                       int r) {
   const EnvArgs& a = d.a;
   if (!a.do_update) {
     if (a.env_out) {
@@ -432,9 +433,9 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
     return;
   }
   cd* gp = reinterpret_cast<cd*>(a.gates) + (int64_t)s * a.gstride + 16 * (int64_t)a.gidx;
-  cd uold[16];
+  cd uold[16];  // loaded into LDS at kernel start, under the partial trace
 #pragma unroll
-  for (int k = 0; k < 16; ++k) uold[k] = gp[k];
+  for (int k = 0; k < 16; ++k) uold[k] = u_sh[k];
   // E = u_old^dagger P (half 0) or P u_old^dagger (half 1): the removal of the
   // old gate commutes with the partial trace.  Row r of E:
   cd erow[4], urow[4], unew[4];
@@ -462,7 +463,6 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
 #pragma unroll
     for (int c = 0; c < 4; ++c) eo[4 * r + c] = erow[c];
   }
-  const bool frozen = a.frozen && a.frozen[s];
   if (frozen) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) unew[c] = urow[c];
@@ -485,10 +485,16 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
 template <typename R>
 __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
   __shared__ cd red[kEnvThreads];
-  __shared__ int last;
+  __shared__ cd u_sh[16];
+  __shared__ int last, frz;
   const uint32_t t = threadIdx.x;
   const uint32_t s = blockIdx.x / d.nwg;
   const uint32_t w = blockIdx.x - s * d.nwg;
+  // Gate update: fetch the old gate and the frozen flag now, so their latency
+  // hides under the partial trace (the reduction's barriers publish them).
+  if (d.a.do_update && t < 16)
+    u_sh[t] = reinterpret_cast<const cd*>(d.a.gates)[(int64_t)s * d.a.gstride + 16 * (int64_t)d.a.gidx + t];
+  if (t == 16) frz = (d.a.do_update && d.a.frozen && d.a.frozen[s]) ? 1 : 0;
   const uint32_t ij = t & 15u, i = ij >> 2, j = ij & 3u;
   const uint32_t ro = local_off(i, d.b0, d.b1), co = local_off(j, d.b0, d.b1);
   const cx<R>* Xs = X + (size_t)s * d.N * d.N;
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
     __syncthreads();
   }
   if (d.nwg == 1) {
-    if (t < 4) env_finish_quad(d, s, red, (int)t);
+    if (t < 4) env_finish_quad(d, s, red, u_sh, frz != 0, (int)t);
     return;
   }
   cd* part = reinterpret_cast<cd*>(d.a.partials) + ((size_t)s * d.nwg + w) * 16;
@@ -547,7 +553,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
   }
   __syncthreads();
   if (t == 0) __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (t < 4) env_finish_quad(d, s, red, (int)t);
+  if (t < 4) env_finish_quad(d, s, red, u_sh, frz != 0, (int)t);
 }
 
 uint32_t env_workgroups(int n) {
