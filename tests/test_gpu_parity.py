@@ -213,7 +213,7 @@ def test_pass_forms_bitwise_equal(qf, dtype):
     forms = [-1, 256, 512] + ([1024] if dtype == "c64" else [])
     S = 2
     try:
-        for n in (6, 10):
+        for n in (6, 7, 10):
             rng = np.random.default_rng(4000 + n)
             X0 = I.random_builder(rng, S, n)
             if dtype == "c64":
@@ -244,7 +244,7 @@ def test_pass_forms_bitwise_equal(qf, dtype):
                     assert np.array_equal(o[1], outs[0][1]), (n, loc, f)
                     assert np.array_equal(o[2], outs[0][2]), (n, loc, f)
     finally:
-        for n in (6, 10):
+        for n in (6, 7, 10):
             for cls in (0, 1):
                 qf.set_pass_tile("cuda", prec, n, cls, 0)
 
