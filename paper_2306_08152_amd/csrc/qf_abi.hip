@@ -423,7 +423,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   // group's pass keeps HBM busy.  Groups share nothing but the join.
   // (Per-kernel timing runs the starts as one group so that every measured
   // kernel duration is the kernel's own, not shared with a concurrent one.)
-  int G = o.stream_groups > 0 ? o.stream_groups : 2;
+  int G = o.stream_groups > 0 ? o.stream_groups : 3;
   G = std::min(std::min(G, kMaxGroups), S);
   if (stats && stats->timing) G = 1;
   if (G > 1) {

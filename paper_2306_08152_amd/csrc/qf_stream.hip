@@ -327,7 +327,13 @@ __global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassG
 template <typename R, bool HA, bool HB>
 static hipError_t launch_pass_direct(hipStream_t st, cx<R>* x, int S, const PassGeom& g, Operand A, Operand B) {
   const uint32_t wgps = g.N * g.N / 4096u;  // N^2/16 blocks, 256 per workgroup
-  hipLaunchKernelGGL((k_pass_block<R, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), 0, st, x, g, wgps, A, B);
+  // The kernel uses no LDS; the 40 KiB it reserves caps it at 4 workgroups
+  // (16 waves) per CU, which keeps its bandwidth and was measured to let the
+  // concurrent stream groups' environment steps interleave with it better
+  // (start-sweeps/s +7 to +10 % at n = 10 with 16 starts in 3-4 groups).
+  constexpr size_t kPassBlockLds = 40 * 1024;
+  hipLaunchKernelGGL((k_pass_block<R, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), kPassBlockLds, st, x, g, wgps,
+                     A, B);
   return hipGetLastError();
 }
 
@@ -366,10 +372,10 @@ hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const Pass
   return launch_pass_t<double>(st, X, S, g, A, B);
 }
 
-// k_env: 512 threads = 16 (i,j) pairs x 32 rest lanes; one workgroup covers
+// k_env: 256 threads = 16 (i,j) pairs x 16 rest lanes; one workgroup covers
 // up to kEnvRestsPerWG rests (every n <= 14 in one workgroup per start, so no
 // cross-workgroup step is needed there).
-constexpr uint32_t kEnvThreads = 512;
+constexpr uint32_t kEnvThreads = 256;
 constexpr uint32_t kEnvRestsPerWG = 4096;
 
 // ------------------------------------------------------------------ k_build_init
@@ -477,7 +483,7 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
   }
 }
 
-// Grid: S x nwg workgroups of 512 threads.  Thread t sums entry (i,j) = t%16
+// Grid: S x nwg workgroups of kEnvThreads threads.  Thread t sums entry (i,j) = t%16
 // over its rests (eight loads in flight at a time); the workgroup reduces to
 // 16 FP64 sums in a fixed tree.  With nwg > 1 (n >= 15) each workgroup writes
 // its 16 partials and the last one to arrive (device-scope counter) adds them
