@@ -98,6 +98,31 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(0.5 * y, e, y);
 }
 
+// Complex products of the FP64 gate update with every fused multiply-add
+// spelled out, so that each kernel that inlines the update rounds the same
+// way whatever contractions the compiler would choose for it.
+__device__ __forceinline__ double nrm2x(cd a) { return fma(a.re, a.re, a.im * a.im); }
+__device__ __forceinline__ cd mulx(cd a, cd b) {  // a b
+  return mk(fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re));
+}
+__device__ __forceinline__ cd cjmulx(cd a, cd b) {  // conj(a) b
+  return mk(fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re)));
+}
+__device__ __forceinline__ cd axpbyx(cd x, double a, cd y, double b) {  // a x + b y
+  return mk(fma(x.re, a, y.re * b), fma(x.im, a, y.im * b));
+}
+
+// Rank tolerance of the update: a column of the orthogonalised M whose
+// squared norm is at most 1e-30 of another's (singular value ratio 1e-15,
+// about 4.5 machine epsilons, numpy's matrix_rank tolerance for 4 x 4) is a
+// numerically vanishing singular direction.  Such a column is round-off
+// that lies in the span of the others and cannot be orthogonalised (the
+// rotations would only shrink it, down to angles the float tangent cannot
+// represent); it takes no rotation and is replaced at the end by the
+// Gram-Schmidt completion (any completion attains the same Re Tr(M u) to
+// within the neglected singular value).
+constexpr double kRankTol2 = 1e-30;
+
 // Entry (k, r) of a 4x4 row-major array for a runtime r, by a select chain
 // (keeps the array in registers).
 __device__ __forceinline__ cd at_kr(const cd u[16], int k, int r) {
@@ -163,19 +188,29 @@ __device__ __forceinline__ void quad_gather(cd v, cd o[4]) {
 }
 
 // Jacobi rotation of columns (p, q) given the summed norms a, b and inner
-// product g; applies to this lane's row of M and Y.  The rotation angle
-// follows the symmetric 2x2 Schur step (Golub and Van Loan): with
-// zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-// c = 1 / sqrt(1 + t^2), s = c t, after the phase of g is moved onto column q.
-// The tangent t only steers convergence (any t gives an exact rotation once c
-// and s are consistent with it), so it comes from single-precision hardware
-// estimates; the phase of g and c are computed in FP64 (Newton-refined), so
-// the applied rotation is unitary to FP64 round-off.
-// Returns 1 for a large rotation, 0 for a small one or none (see below).
-__device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, double a, double b, cd g) {
+// product g.  The rotation angle follows the symmetric 2x2 Schur step (Golub
+// and Van Loan): with zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t, after the phase of g is
+// moved onto column q.  The tangent t only steers convergence (any t gives an
+// exact rotation once c and s are consistent with it), so it comes from
+// single-precision hardware estimates; the phase of g and c are computed in
+// FP64 (Newton-refined), so the applied rotation is unitary to FP64
+// round-off.  Returns false when the pair is already orthogonal (no
+// rotation); `large` is 1 for a large rotation, 0 for a small one: cosine of
+// the pair and tan of the angle both below 1e-8.  A later rotation (p, r)
+// moves the cosine of an orthogonalised pair (p, q) by at most about
+// max(tan, cosine of (p, r)) times the cosine of (r, q), so a sweep of small
+// rotations leaves every cosine below ~4e-16, the round-off threshold: no
+// confirming sweep.
+struct JacobiRot {
+  double c, s, large;
+  cd ph;  // e^{-i arg g}
+};
+__device__ __forceinline__ bool jacobi_params(double a, double b, cd g, JacobiRot& q) {
   const double tol2 = 1.6e-31;  // (4e-16)^2: |g| <= 4e-16 sqrt(a b) counts as orthogonal
-  const double g2 = norm2(g);
-  if (!(g2 > tol2 * (a * b))) return 0.0;
+  const double g2 = nrm2x(g);
+  if (!(g2 > tol2 * (a * b))) return false;
+  if (!(fmin(a, b) > kRankTol2 * fmax(a, b))) return false;  // a vanishing column
   const double rg = rsqrt_nr(g2);              // 1 / |g|
   const float zeta = (float)(0.5 * (b - a) * rg);
   const float az = fabsf(zeta);
@@ -187,34 +222,40 @@ __device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, do
     tf = 0.5f * __builtin_amdgcn_rcpf(az);
   }
   const double t = zeta >= 0.0f ? (double)tf : -(double)tf;
-  const double c = rsqrt_nr(fma(t, t, 1.0));
-  const double s = c * t;
-  const cd ph = mk(g.re * rg, -g.im * rg);     // e^{-i arg g}
-  const cd xp = m[p], xq = ph * m[q];
-  m[p] = scale(xp, c) - scale(xq, s);
-  m[q] = scale(xp, s) + scale(xq, c);
-  const cd yp = y[p], yq = ph * y[q];
-  y[p] = scale(yp, c) - scale(yq, s);
-  y[q] = scale(yp, s) + scale(yq, c);
-  // 1 = a large rotation; 0 = a small one: cosine of the pair and tan of the
-  // angle both below 1e-8.  A later rotation (p, r) moves the cosine of an
-  // orthogonalised pair (p, q) by at most about max(tan, cosine of (p, r))
-  // times the cosine of (r, q), so a sweep of small rotations leaves every
-  // cosine below ~4e-16, the round-off threshold above: no confirming sweep.
-  return (g2 > 1e-16 * (a * b) || fabs(t) > 1e-8) ? 1.0 : 0.0;
+  q.c = rsqrt_nr(fma(t, t, 1.0));
+  q.s = q.c * t;
+  q.ph = mk(g.re * rg, -g.im * rg);
+  q.large = (g2 > 1e-16 * (a * b) || fabs(t) > 1e-8) ? 1.0 : 0.0;
+  return true;
+}
+// (xp, xq) <- (c xp - s ph xq, s xp + c ph xq): one row of the rotated pair.
+__device__ __forceinline__ void jacobi_apply(const JacobiRot& q, cd xp, cd mq, cd& np, cd& nq) {
+  const cd xq = mulx(q.ph, mq);
+  np = axpbyx(xp, q.c, xq, -q.s);
+  nq = axpbyx(xp, q.s, xq, q.c);
+}
+
+// Quad form: applies the rotation of columns (p, q) to this lane's row of M
+// and Y; returns 1 for a large rotation, 0 for a small one or none.
+__device__ __forceinline__ double quad_rotate(cd m[4], cd y[4], int p, int q, double a, double b, cd g) {
+  JacobiRot j;
+  if (!jacobi_params(a, b, g, j)) return 0.0;
+  jacobi_apply(j, m[p], m[q], m[p], m[q]);
+  jacobi_apply(j, y[p], y[q], y[p], y[q]);
+  return j.large;
 }
 
 template <int P0, int Q0, int P1, int Q1>
 __device__ __forceinline__ double quad_round(cd m[4], cd y[4]) {
   double v[8];
-  v[0] = norm2(m[P0]);
-  v[1] = norm2(m[Q0]);
-  const cd g0 = conj(m[P0]) * m[Q0];
+  v[0] = nrm2x(m[P0]);
+  v[1] = nrm2x(m[Q0]);
+  const cd g0 = cjmulx(m[P0], m[Q0]);
   v[2] = g0.re;
   v[3] = g0.im;
-  v[4] = norm2(m[P1]);
-  v[5] = norm2(m[Q1]);
-  const cd g1 = conj(m[P1]) * m[Q1];
+  v[4] = nrm2x(m[P1]);
+  v[5] = nrm2x(m[Q1]);
+  const cd g1 = cjmulx(m[P1], m[Q1]);
   v[6] = g1.re;
   v[7] = g1.im;
 #pragma unroll
@@ -263,23 +304,23 @@ __device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4],
   double sig2[4], smax2 = 0.0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    sig2[j] = quad_sum(norm2(mrow[j]));
+    sig2[j] = quad_sum(nrm2x(mrow[j]));
     smax2 = fmax(smax2, sig2[j]);
   }
   bool acc[4];
   bool singular = false;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    acc[j] = sig2[j] > smax2 * 1e-290;  // singular value above 1e-145 of the largest
+    acc[j] = sig2[j] > smax2 * kRankTol2;
     singular = singular || !acc[j];
   }
   cd x[4];  // row r of X
 #pragma unroll
   for (int j = 0; j < 4; ++j) x[j] = sel(acc[j], scale(mrow[j], rsqrt_nr(acc[j] ? sig2[j] : 1.0)), mk(0.0, 0.0));
   if (singular) {
-    // An exactly vanishing singular direction: complete X by Gram-Schmidt
-    // of e_0..e_3 against the accepted columns (any completion attains the
-    // same Re Tr(M u)); lane r holds component r of each vector.
+    // A vanishing singular direction (see kRankTol2): complete X by
+    // Gram-Schmidt of e_0..e_3 against the accepted columns (any completion
+    // attains the same Re Tr(M u)); lane r holds component r of each vector.
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (!acc[j]) {
@@ -290,12 +331,12 @@ __device__ inline int nearest_unitary_f64_quad(cd mrow[4], const cd keep_row[4],
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
             if (acc[jj]) {
-              const cd pr = conj(x[jj]) * v;
+              const cd pr = cjmulx(x[jj], v);
               const cd d = mk(quad_sum(pr.re), quad_sum(pr.im));
-              v = v - x[jj] * d;
+              v = v - mulx(x[jj], d);
             }
           }
-          const double nv = quad_sum(norm2(v));
+          const double nv = quad_sum(nrm2x(v));
           const bool take = !found && nv >= 0.25;
           if (take) x[j] = scale(v, rsqrt_nr(nv));
           found = found || take;
@@ -329,10 +370,178 @@ __device__ inline void optimize_gate_f64_quad(const cd e_row[4], const cd uold[1
   const double we = 1.0 - beta;  // exact 1 for beta = 0
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    m[c] = scale(e_row[c], we) + scale(conj(at_kr(uold, c, r)), beta);  // + beta (u_old^dagger)[r][c]
+    m[c] = axpbyx(e_row[c], we, conj(at_kr(uold, c, r)), beta);  // + beta (u_old^dagger)[r][c]
     keep[c] = at_rk(uold, r, c);
   }
   nearest_unitary_f64_quad(m, keep, r, unew_row);
+}
+
+// ---------------------------------------------------------------- hex form
+//
+// The same nearest-unitary step on 16 lanes (lanes 16k..16k+15 of a
+// wavefront, all active): lane i holds entry (r, c) of M and of Y, with
+// c = i & 3 and r the two-bit reversal of i >> 2 (rows 0, 2, 1, 3 on the
+// four quads).  A round's two disjoint column pairs run on different lanes at
+// once, so a round costs one rotation's dependent chain and about half the
+// instructions of the quad form.  The row placement makes a column sum
+// (rotate by 8, then by 4 lanes within the row of 16) add in the order
+// (r0 + r1) + (r2 + r3), the quad form's order, and every other operation is
+// the quad form's expression on the same operands, so the two forms give
+// bitwise-identical results.
+constexpr int kQuadXor3 = 3 | (2 << 2) | (1 << 4) | (0 << 6);  // [3,2,1,0]
+constexpr int kRowRor4 = 0x124;                                 // DPP row_ror:4
+constexpr int kRowRor8 = 0x128;                                 // DPP row_ror:8
+
+__host__ __device__ __forceinline__ int hex_row(int i) { return (((i >> 2) & 1) << 1) | ((i >> 3) & 1); }
+__host__ __device__ __forceinline__ int hex_lane(int r, int c) { return c + 4 * ((((r & 1) << 1) | (r >> 1))); }
+
+template <int CTRL>
+__device__ __forceinline__ cd dpp_cx(cd v) {
+  return mk(dpp_quad<CTRL>(v.re), dpp_quad<CTRL>(v.im));
+}
+// Sum over the 4 rows of this lane's column; bitwise the same in every lane.
+__device__ __forceinline__ double hex_colsum(double v) {
+  v += dpp_quad<kRowRor8>(v);
+  return v + dpp_quad<kRowRor4>(v);
+}
+__device__ __forceinline__ double hex_max(double v) {
+  v = quad_max(v);
+  v = fmax(v, dpp_quad<kRowRor8>(v));
+  return fmax(v, dpp_quad<kRowRor4>(v));
+}
+// Entry (r, j) of the quad's row (lane j of this quad) for a compile-time j
+// after unrolling.
+__device__ __forceinline__ cd quad_bcast(cd v, int j) {
+  if (j == 0) return dpp_cx<0x00>(v);
+  if (j == 1) return dpp_cx<0x55>(v);
+  if (j == 2) return dpp_cx<0xAA>(v);
+  return dpp_cx<0xFF>(v);
+}
+
+// One round: the pair (c, c ^ K) of this lane's column; XK is the quad_perm
+// selector of lane ^ K.  Returns 1 for a large rotation, 0 otherwise.
+template <int K, int XK>
+__device__ __forceinline__ double hex_round(cd& m, cd& y, int c) {
+  const bool pside = c < (c ^ K);
+  const cd mo = dpp_cx<XK>(m);
+  const cd yo = dpp_cx<XK>(y);
+  const cd mP = sel(pside, m, mo), mQ = sel(pside, mo, m);
+  const double na = hex_colsum(nrm2x(m));
+  const cd gl = cjmulx(mP, mQ);
+  const cd g = mk(hex_colsum(gl.re), hex_colsum(gl.im));
+  const double nb = dpp_quad<XK>(na);
+  JacobiRot j;
+  if (!jacobi_params(pside ? na : nb, pside ? nb : na, g, j)) return 0.0;
+  cd np, nq;
+  jacobi_apply(j, mP, mQ, np, nq);
+  m = sel(pside, np, nq);
+  jacobi_apply(j, sel(pside, y, yo), sel(pside, yo, y), np, nq);
+  y = sel(pside, np, nq);
+  return j.large;
+}
+
+// m: this lane's entry (r, c) of M (overwritten); keep: entry (r, c) of the
+// result for a zero M; unew: entry (r, c) of the maximiser of Re Tr(M u).
+// Same results and return codes as nearest_unitary_f64_quad.
+__device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& unew) {
+  double amax = fmax(fabs(m.re), fabs(m.im));
+  double bad = (finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0;
+  amax = hex_max(amax);
+  bad = hex_max(bad);
+  if (bad != 0.0) {
+    const double nan = __builtin_nan("");
+    unew = mk(nan, nan);
+    return 2;
+  }
+  if (!(amax >= 1e-300)) {
+    unew = keep;
+    return 1;
+  }
+  const double inv = rcp_nr(amax);
+  m = scale(m, inv);
+  cd y = mk(c == r ? 1.0 : 0.0, 0.0);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double rel = hex_round<1, kQuadXor1>(m, y, c);
+    rel = fmax(rel, hex_round<2, kQuadXor2>(m, y, c));
+    rel = fmax(rel, hex_round<3, kQuadXor3>(m, y, c));
+    if (!(quad_max(rel) > 0.0)) break;
+  }
+  const double sig2 = hex_colsum(nrm2x(m));
+  const double smax2 = quad_max(sig2);
+  const bool acc = sig2 > smax2 * kRankTol2;
+  double accv[4];
+  quad_gather(acc ? 1.0 : 0.0, accv);
+  cd x = sel(acc, scale(m, rsqrt_nr(acc ? sig2 : 1.0)), mk(0.0, 0.0));  // X[r][c]
+  if (accv[0] == 0.0 || accv[1] == 0.0 || accv[2] == 0.0 || accv[3] == 0.0) {
+    // Gram-Schmidt completion as in the quad form, each row's component
+    // computed by the four lanes of its quad alike.
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (accv[j] == 0.0) {
+        bool found = false;
+        cd xj = mk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cd v = mk(r == k ? 1.0 : 0.0, 0.0);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            if (accv[jj] != 0.0) {
+              const cd xjj = quad_bcast(x, jj);
+              const cd pr = cjmulx(xjj, v);
+              const cd d = mk(hex_colsum(pr.re), hex_colsum(pr.im));
+              v = v - mulx(xjj, d);
+            }
+          }
+          const double nv = hex_colsum(nrm2x(v));
+          const bool take = !found && nv >= 0.25;
+          if (take) xj = scale(v, rsqrt_nr(nv));
+          found = found || take;
+        }
+        if (c == j) x = xj;
+        accv[j] = 1.0;
+      }
+    }
+  }
+  // u_new[r][c] = sum_j Y[r][j] conj(X[c][j]); row r of Y from the quad, row
+  // c of X from the quad that holds it.
+  cd yr[4];
+  quad_gather(y, yr);
+  const int base = (int)(__lane_id() & ~15u);
+  cd a = mk(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int src = base + hex_lane(c, j);
+    const cd xcj = mk(__shfl(x.re, src, 64), __shfl(x.im, src, 64));
+    cmac(a, yr[j], conj(xcj));
+  }
+  unew = a;
+  return 0;
+}
+
+// Entry (r, c) of the environment E of the gate being updated, from the
+// partial trace P and u_old (row-major 4 x 4 arrays readable by every lane):
+// E = u_old^dagger P in the first half of a sweep, P u_old^dagger in the
+// second (the removal of the old gate commutes with the partial trace); the
+// quad form's sum order.
+__device__ __forceinline__ cd env_entry(const cd* P, const cd* uold, int half, int r, int c) {
+  cd acc = mk(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (half == 0)
+      cmac(acc, conj(uold[4 * k + r]), P[4 * k + c]);
+    else
+      cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
+  }
+  return acc;
+}
+
+// Hex form of OptimizeGate (Sec. III-A-1, Eq. opt_u; beta of Sec. III-A-2):
+// lane (r, c) passes E[r][c], u_old[c][r] and u_old[r][c] and receives
+// u_new[r][c]; bitwise the quad form's result.
+__device__ inline void optimize_gate_f64_hex(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew) {
+  const double we = 1.0 - beta;  // exact 1 for beta = 0
+  cd m = axpbyx(e, we, conj(uold_cr), beta);
+  nearest_unitary_f64_hex(m, uold_rc, r, c, unew);
 }
 
 // ---------------------------------------------------------------- gate kinds

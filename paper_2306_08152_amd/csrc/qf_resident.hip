@@ -246,7 +246,21 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
       const int g = half == 0 ? a.p - 1 - step : step - a.p;
       const uint32_t b0 = n - 1 - a.locs[2 * g], b1 = n - 1 - a.locs[2 * g + 1];
       lds_ptrace<R>(L.X, n, b0, b1, L.red);
-      if (t < 4) {  // FP64 gate update on one quad, lane r = row r
+      const int kind = a.kinds ? a.kinds[g] : kKindU4;
+      if (kind == kKindU4) {
+        if (t < 16) {  // general U(4) update on one hex, lane t = entry (hex_row(t), t & 3)
+          const int r = hex_row((int)t), c = (int)t & 3;
+          const cd ucr = gates[16 * g + 4 * c + r], urc = gates[16 * g + 4 * r + c];
+          const cd e = env_entry(L.red, gates + 16 * g, half, r, c);
+          cd unew = urc;
+          if (!frozen) optimize_gate_f64_hex(e, ucr, urc, r, c, o.beta, unew);
+          gates[16 * g + 4 * r + c] = unew;
+          const cd udc = conj(ucr);  // (u_old^dagger)[r][c]
+          const cd Av = sel(half == 0, udc, unew), Bv = sel(half == 0, unew, udc);
+          L.opsR[4 * r + c] = cx<R>{(R)Av.re, (R)Av.im};
+          L.opsR[16 + 4 * r + c] = cx<R>{(R)Bv.re, (R)Bv.im};
+        }
+      } else if (t < 4) {  // restricted kinds on one quad, lane r = row r
         const int r = (int)t;
         cd uold[16], erow[4], urow[4], unew[4];
 #pragma unroll
@@ -271,7 +285,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) unew[c] = urow[c];
         } else {
-          update_gate_quad(a.kinds ? a.kinds[g] : kKindU4, erow, uold, r, o.beta, unew);
+          update_gate_quad(kind, erow, uold, r, o.beta, unew);
         }
         // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored.
         // Row r of u_old^dagger is conj(column r of u_old).

@@ -483,6 +483,32 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
   }
 }
 
+// The general U(4) update on the 16 lanes of a hex (lane i = entry
+// (hex_row(i), i & 3)); bitwise the quad form's result in about two thirds of
+// its time.
+__device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
+                                      int i) {
+  const EnvArgs& a = d.a;
+  const int r = hex_row(i), c = i & 3;
+  const cd e = env_entry(P, u_sh, a.half, r, c);
+  const cd urc = u_sh[4 * r + c];
+  if (a.env_out) reinterpret_cast<cd*>(a.env_out)[16 * (size_t)s + 4 * r + c] = e;
+  cd unew = urc;
+  if (!frozen) optimize_gate_f64_hex(e, u_sh[4 * c + r], urc, r, c, a.beta, unew);
+  reinterpret_cast<cd*>(a.uold)[16 * (size_t)s + 4 * r + c] = urc;
+  reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 16 * (int64_t)a.gidx + 4 * r + c] = unew;
+}
+
+// The finishing step of one start by the lanes it needs.
+__device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
+                                          uint32_t t) {
+  if (d.a.do_update && d.a.kind == kKindU4) {
+    if (t < 16) env_finish_hex(d, s, P, u_sh, frozen, (int)t);
+  } else if (t < 4) {
+    env_finish_quad(d, s, P, u_sh, frozen, (int)t);
+  }
+}
+
 // Grid: S x nwg workgroups of kEnvThreads threads.  Thread t sums entry (i,j) = t%16
 // over its rests (eight loads in flight at a time); the workgroup reduces to
 // 16 FP64 sums in a fixed tree.  With nwg > 1 (n >= 15) each workgroup writes
@@ -529,7 +555,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
     __syncthreads();
   }
   if (d.nwg == 1) {
-    if (t < 4) env_finish_quad(d, s, red, u_sh, frz != 0, (int)t);
+    env_finish(d, s, red, u_sh, frz != 0, t);
     return;
   }
   cd* part = reinterpret_cast<cd*>(d.a.partials) + ((size_t)s * d.nwg + w) * 16;
@@ -559,7 +585,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
   }
   __syncthreads();
   if (t == 0) __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (t < 4) env_finish_quad(d, s, red, u_sh, frz != 0, (int)t);
+  env_finish(d, s, red, u_sh, frz != 0, t);
 }
 
 uint32_t env_workgroups(int n) {
@@ -646,27 +672,25 @@ hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int 
 
 // ------------------------------------------------------------------ k_optimize
 
-// Four lanes (one quad) per environment: lane r owns row r.
+// Sixteen lanes (one hex) per environment: lane i owns entry
+// (hex_row(i), i & 3).
 __global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict__ env,
                                                  const cd* __restrict__ uold, double beta,
                                                  cd* __restrict__ unew) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = gt >> 2, r = gt & 3;
-  if (s >= count) return;  // whole quads leave together
-  cd e[4], u[16], un[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) e[c] = env[16 * s + 4 * r + c];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) u[k] = uold[16 * s + k];
-  optimize_gate_f64_quad(e, u, r, beta, un);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) unew[16 * s + 4 * r + c] = un[c];
+  const int s = gt >> 4, i = gt & 15;
+  if (s >= count) return;  // whole hexes leave together
+  const int r = hex_row(i), c = i & 3;
+  const cd* u = uold + 16 * (size_t)s;
+  cd un;
+  optimize_gate_f64_hex(env[16 * (size_t)s + 4 * r + c], u[4 * c + r], u[4 * r + c], r, c, beta, un);
+  unew[16 * (size_t)s + 4 * r + c] = un;
 }
 
 hipError_t launch_optimize(hipStream_t st, int count, const double* env, const double* uold,
                            double beta, double* unew) {
   const int threads = 64;
-  const long long lanes = 4ll * count;
+  const long long lanes = 16ll * count;
   hipLaunchKernelGGL(k_optimize, dim3((unsigned)((lanes + threads - 1) / threads)), dim3(threads), 0, st,
                      count, reinterpret_cast<const cd*>(env), reinterpret_cast<const cd*>(uold), beta,
                      reinterpret_cast<cd*>(unew));

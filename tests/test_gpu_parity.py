@@ -141,6 +141,11 @@ def test_optimize_gate_vs_lapack(qf):
             E = I.haar_unitary(rng, 4) @ d @ I.haar_unitary(rng, 4)  # ill conditioned
         if k % 8 == 4:
             E = 1e-200 * E                                       # tiny scale
+        if k % 8 == 5:
+            E[k % 4, :] = 0.0                                    # zero row: rank 3 that no column shows
+        if k % 8 == 6:
+            E[[0, 3], :] = 0.0                                   # two zero rows and a zero column
+            E[:, 1] = 0.0
         envs.append(E)
     E = np.stack(envs)
     U0 = np.stack([I.haar_unitary(rng, 4) for _ in range(64)])
