@@ -133,8 +133,9 @@ typedef struct {
   int32_t stream_groups; /* streaming mode: starts are split into this many
                             groups whose sweeps run on separate streams,
                             staggered so one group's environment + SVD step
-                            runs under another's pass (0 = automatic: 3,
-                            so that with the caller's stream they fit the
+                            runs under another's pass; group 0 runs on the
+                            caller's stream (qf_set_stream), the others on
+                            the library's own (0 = automatic: 4, the
                             device's 4 hardware queues; at most 4 and at most
                             n_starts) */
   const int32_t* gate_kinds; /* host, one qf_gate_kind per gate (for

@@ -182,7 +182,8 @@ int ensure_pinned(qf_ctx* ctx, size_t count) {
 int ensure_aux_streams(qf_ctx* ctx) {
   if (ctx->aux[0]) return QF_OK;
   for (int i = 0; i < kMaxGroups; ++i) {
-    QF_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+    // group 0 runs on the caller's stream: kMaxGroups - 1 streams of our own
+    if (i + 1 < kMaxGroups) QF_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
     QF_HIP(ctx, hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming));
     QF_HIP(ctx, hipEventCreateWithFlags(&ctx->stagger[i], hipEventDisableTiming));
   }
@@ -420,10 +421,13 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
 
   // The starts split into G groups whose sweeps run on separate streams:
   // while one group's latency-bound environment + SVD step runs, the other
-  // group's pass keeps HBM busy.  Groups share nothing but the join.
+  // group's pass keeps HBM busy.  Groups share nothing but the join.  Group
+  // 0 runs on the caller's stream and groups 1.. on the library's own, so
+  // that four groups occupy the device's four hardware queues (a fifth
+  // stream would share a queue with another and serialise behind it).
   // (Per-kernel timing runs the starts as one group so that every measured
   // kernel duration is the kernel's own, not shared with a concurrent one.)
-  int G = o.stream_groups > 0 ? o.stream_groups : 3;
+  int G = o.stream_groups > 0 ? o.stream_groups : kMaxGroups;
   G = std::min(std::min(G, kMaxGroups), S);
   if (stats && stats->timing) G = 1;
   if (G > 1) {
@@ -442,7 +446,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     Group& q = grp[gi];
     q.s0 = gi * S / G;
     q.ns = (gi + 1) * S / G - q.s0;
-    q.st = G > 1 ? ctx->aux[gi] : st;
+    q.st = gi == 0 ? st : ctx->aux[gi - 1];
     q.X = reinterpret_cast<unsigned char*>(X) + (size_t)q.s0 * N * N * elem_bytes(prec);
     EnvArgs& ea = q.ea;
     ea.n = n;
@@ -500,7 +504,8 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   auto sweep_on = [&](hipStream_t home) -> int {
     if (G > 1) {
       QF_HIP(ctx, hipEventRecord(ctx->fork, home));
-      for (int gi = 0; gi < G; ++gi) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->fork, 0));
+      for (int gi = 0; gi < G; ++gi)
+        if (grp[gi].st != home) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->fork, 0));
     }
     // Stagger: group k starts once group k-1's first environment + SVD step
     // is done, so the groups' latency-bound steps fall under each other's
@@ -517,6 +522,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
         if ((rc1 = update(grp[gi], g, 1, nullptr))) return rc1;
     if (G > 1) {
       for (int gi = 0; gi < G; ++gi) {
+        if (grp[gi].st == home) continue;
         QF_HIP(ctx, hipEventRecord(ctx->join[gi], grp[gi].st));
         QF_HIP(ctx, hipStreamWaitEvent(home, ctx->join[gi], 0));
       }
