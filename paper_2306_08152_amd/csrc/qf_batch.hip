@@ -1,15 +1,19 @@
 // Batched QFactor: many independent small problems (n <= 4 qubits, builders
 // up to 16 x 16) in one persistent launch.
 //
-// One workgroup is one wavefront of 16 quads.  Each quad owns one (block,
-// start) instantiation: its builder lives in LDS, lane r of the quad sums row
-// r of the partial trace, the quad runs the FP64 nearest-unitary step of
-// Sec. III-A-1 (one row per lane), and the lanes share the 4x4 block updates
-// of the fused remove/re-apply.  The starts of one block sit in adjacent
-// quads of the same wavefront and take the multistart decision of Sec. IV-A
-// together after every sweep (flags exchanged through LDS).  Wavefronts take
-// groups of blocks from a device-side counter until the queue is empty, so
-// every wavefront reaches the exit.
+// One workgroup is four wavefronts, 16 hexes of 16 lanes.  Each hex owns one
+// (block, start) instantiation: its builder lives in LDS, lane (r, c) of the
+// hex (r = hex_row(i), c = i & 3 for lane i) sums entry (r, c) of the partial
+// trace and holds that entry in the FP64 nearest-unitary step of
+// Sec. III-A-1, and the 16 lanes share the 4x4 block updates of the fused
+// remove/re-apply.  A sweep of a block is a chain of gate updates, so the
+// time of the slowest blocks (the launch time) is set by the latency of one
+// update: sixteen lanes per instantiation shorten it over one row per lane.
+// The starts of one block sit in adjacent hexes of the same workgroup and
+// take the multistart decision of Sec. IV-A together after every sweep
+// (flags exchanged through LDS).  Workgroups take groups of blocks from a
+// device-side counter until the queue is empty, so every workgroup reaches
+// the exit.
 #include <hip/hip_runtime.h>
 
 #include "qf_device.h"
@@ -18,68 +22,62 @@
 
 namespace qf {
 
-constexpr int kBQuads = 16;     // quads per wavefront
-constexpr int kBNmax = 16;      // largest builder side (n <= 4)
+constexpr int kBSlots = 16;                    // hexes (instantiations) per workgroup
+constexpr int kBLanes = 16;                    // lanes per hex
+constexpr int kBThreads = kBSlots * kBLanes;   // four wavefronts
+constexpr int kBNmax = 16;                     // largest builder side (n <= 4)
 
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }  // one-wave workgroup
-
-__device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
-  return v;
-}
-
-// Left product by a 4x4 gate (A) and right product (B) on one quad's N x N
-// builder in LDS; lane r takes blocks r, r + 4, ...
+// Left product by a 4x4 gate (A) and right product (B) on one hex's N x N
+// builder; lane i takes blocks i, i + 16, ...
 template <typename R, bool HA, bool HB>
-__device__ inline void quad_pass(cx<R>* X, uint32_t N, uint32_t b0, uint32_t b1, const cx<R> a[16],
-                                 const cx<R> b[16], int r) {
+__device__ inline void hex_pass(cx<R>* X, uint32_t N, uint32_t b0, uint32_t b1, const cx<R> a[16],
+                                const cx<R> b[16], int i) {
   const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
   const uint32_t q = N >> 2, nblk = q * q;
   uint32_t off[4];
 #pragma unroll
-  for (uint32_t i = 0; i < 4; ++i) off[i] = local_off(i, b0, b1);
-  for (uint32_t blk = (uint32_t)r; blk < nblk; blk += 4) {
+  for (uint32_t k = 0; k < 4; ++k) off[k] = local_off(k, b0, b1);
+  for (uint32_t blk = (uint32_t)i; blk < nblk; blk += kBLanes) {
     const uint32_t rb = insert00(blk / q, lo, hi), cb = insert00(blk % q, lo, hi);
     cx<R> x[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[4 * i + j] = X[(rb + off[i]) * N + cb + off[j]];
+      for (int j = 0; j < 4; ++j) x[4 * k + j] = X[(rb + off[k]) * N + cb + off[j]];
     if (HA) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         cx<R> t[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int k = 0; k < 4; ++k) {
           cx<R> acc = mk<R>(0, 0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cmac(acc, a[4 * i + k], x[4 * k + j]);
-          t[i] = acc;
+          for (int l = 0; l < 4; ++l) cmac(acc, a[4 * k + l], x[4 * l + j]);
+          t[k] = acc;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[4 * i + j] = t[i];
+        for (int k = 0; k < 4; ++k) x[4 * k + j] = t[k];
       }
     }
     if (HB) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int k = 0; k < 4; ++k) {
         cx<R> t[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           cx<R> acc = mk<R>(0, 0);
 #pragma unroll
-          for (int l = 0; l < 4; ++l) cmac(acc, x[4 * i + l], b[4 * l + j]);
+          for (int l = 0; l < 4; ++l) cmac(acc, x[4 * k + l], b[4 * l + j]);
           t[j] = acc;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = t[j];
+        for (int j = 0; j < 4; ++j) x[4 * k + j] = t[j];
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) X[(rb + off[i]) * N + cb + off[j]] = x[4 * i + j];
+      for (int j = 0; j < 4; ++j) X[(rb + off[k]) * N + cb + off[j]] = x[4 * k + j];
   }
 }
 
@@ -96,15 +94,15 @@ struct BatchDev {
   qf_options opt;
   double* hist;             // (block, start) x ring
   int ring;
-  cd* scratch;              // FP64 builder per (workgroup, quad): N_max^2 each
+  cd* scratch;              // FP64 builder per (workgroup, hex): N_max^2 each
   double* out_cost;         // (block, start)
   int32_t* out_best, *out_status, *out_sweeps;
   int32_t* queue;           // work counter (zero before launch)
   const int32_t* kinds;     // gate kinds over all gates (nullptr = all general U(4))
 };
 
-// Per-quad problem description.
-struct QuadJob {
+// Per-hex problem description.
+struct HexJob {
   bool valid;
   int b, s, n, p;
   uint32_t N;
@@ -114,21 +112,21 @@ struct QuadJob {
   const int32_t* kinds; // this block's gate kinds (nullptr = all general U(4))
 };
 
-// Builder <- G_p ... G_1 V^dagger for one quad, in precision Q, at X
-// (LDS or global).  All quads of the wavefront call it with the same
-// pmax (uniform barriers); inactive quads only take part in the barriers.
+// Builder <- G_p ... G_1 V^dagger for one hex, in precision Q, at X (LDS or
+// global).  Every thread of the workgroup calls it with the same pmax
+// (uniform barriers); inactive hexes only take part in the barriers.
 template <typename Q>
-__device__ inline void quad_build(cx<Q>* X, const QuadJob& jb, int r, int pmax) {
+__device__ inline void hex_build(cx<Q>* X, const HexJob& jb, int i, int pmax) {
   if (jb.valid) {
     const uint32_t N = jb.N;
-    for (uint32_t e = (uint32_t)r; e < N * N; e += 4) {
+    for (uint32_t e = (uint32_t)i; e < N * N; e += kBLanes) {
       const uint32_t row = e / N, col = e - row * N;
       const cd v = conj(jb.V[col * N + row]);
       X[e] = cx<Q>{(Q)v.re, (Q)v.im};
     }
   }
   for (int g = 0; g < pmax; ++g) {
-    wave_sync();
+    __syncthreads();
     if (jb.valid && g < jb.p) {
       cx<Q> a[16];
 #pragma unroll
@@ -137,17 +135,19 @@ __device__ inline void quad_build(cx<Q>* X, const QuadJob& jb, int r, int pmax) 
         a[k] = cx<Q>{(Q)v.re, (Q)v.im};
       }
       const uint32_t b0 = (uint32_t)(jb.n - 1 - jb.locs[2 * g]), b1 = (uint32_t)(jb.n - 1 - jb.locs[2 * g + 1]);
-      quad_pass<Q, true, false>(X, jb.N, b0, b1, a, a, r);
+      hex_pass<Q, true, false>(X, jb.N, b0, b1, a, a, i);
     }
   }
-  wave_sync();
+  __syncthreads();
 }
 
-// 1 - |Tr X| / N for one quad (all lanes get the same value).
+// 1 - |Tr X| / N for one hex; every quad of the hex forms the same sum (lane
+// c adds diagonal entries c, c + 4, ..., the quad adds the four pairwise), so
+// all 16 lanes get bitwise the same value.
 template <typename Q>
-__device__ inline double quad_cost(const cx<Q>* X, uint32_t N, int r) {
+__device__ inline double hex_cost(const cx<Q>* X, uint32_t N, int c) {
   double re = 0.0, im = 0.0;
-  for (uint32_t d = (uint32_t)r; d < N; d += 4) {
+  for (uint32_t d = (uint32_t)c; d < N; d += 4) {
     re += (double)X[d * N + d].re;
     im += (double)X[d * N + d].im;
   }
@@ -157,27 +157,41 @@ __device__ inline double quad_cost(const cx<Q>* X, uint32_t N, int r) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(64) void k_batch(BatchDev d) {
-  __shared__ __align__(16) cx<R> Xs[kBQuads][kBNmax * kBNmax];
-  __shared__ int flags_sh[kBQuads];
+__global__ __launch_bounds__(kBThreads) void k_batch(BatchDev d) {
+  __shared__ __align__(16) cx<R> Xs[kBSlots][kBNmax * kBNmax];
+  __shared__ cd Us[kBSlots][16];   // u_old of the gate being updated
+  __shared__ cd PUs[kBSlots][16];  // its partial trace, then u_new
+  __shared__ int flags_sh[kBSlots];
+  __shared__ int p_sh[kBSlots];
   __shared__ int grp_sh;
-  const int t = threadIdx.x, q = t >> 2, r = t & 3;
+  const int t = threadIdx.x, h = t / kBLanes, i = t % kBLanes;
+  const int r = hex_row(i), c = i & 3;
   const qf_options& o = d.opt;
-  cx<R>* X = Xs[q];
-  cd* Y = d.scratch + ((size_t)blockIdx.x * kBQuads + q) * (kBNmax * kBNmax);
+  cx<R>* X = Xs[h];
+  cd* Y = d.scratch + ((size_t)blockIdx.x * kBSlots + h) * (kBNmax * kBNmax);
   const bool c64 = sizeof(R) == 4;
+  // Largest per-hex value over the workgroup (v uniform within each hex).
+  auto wg_max = [&](int v) -> int {
+    __syncthreads();
+    if (i == 0) p_sh[h] = v;
+    __syncthreads();
+    int m = p_sh[0];
+#pragma unroll
+    for (int k = 1; k < kBSlots; ++k) m = max(m, p_sh[k]);
+    return m;
+  };
 
   for (;;) {
+    __syncthreads();
     if (t == 0) grp_sh = __hip_atomic_fetch_add(d.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wave_sync();
+    __syncthreads();
     const int grp = grp_sh;
-    wave_sync();
     if (grp >= d.n_groups) break;
 
-    // ---- this quad's job
-    QuadJob jb;
-    const int slot = q / d.S;
-    jb.s = q - slot * d.S;
+    // ---- this hex's job
+    HexJob jb;
+    const int slot = h / d.S;
+    jb.s = h - slot * d.S;
     const int idx = grp * d.B + slot;
     jb.valid = (slot < d.B) && (idx < d.n_blocks);
     jb.b = jb.valid ? d.order[idx] : 0;
@@ -188,172 +202,160 @@ __global__ __launch_bounds__(64) void k_batch(BatchDev d) {
     jb.V = d.V + (jb.valid ? d.tgt_off[jb.b] : 0);
     jb.g = d.gates + ((size_t)d.gate_off[jb.b] * d.S + (size_t)jb.s * jb.p) * 16;
     jb.kinds = d.kinds ? d.kinds + d.gate_off[jb.b] : nullptr;
-    const int pmax = wave_max_int(jb.p);
+    const int pmax = wg_max(jb.p);
     double* hist = d.hist + ((size_t)jb.b * d.S + jb.s) * d.ring;
 
     // ---- InitCircuitTensor and initial cost
     auto rebuild = [&]() {
       if (c64) {
-        quad_build<double>(reinterpret_cast<cx<double>*>(Y), jb, r, pmax);
+        hex_build<double>(reinterpret_cast<cx<double>*>(Y), jb, i, pmax);
         if (jb.valid)
-          for (uint32_t e = (uint32_t)r; e < jb.N * jb.N; e += 4) X[e] = cx<R>{(R)Y[e].re, (R)Y[e].im};
-        wave_sync();
+          for (uint32_t e = (uint32_t)i; e < jb.N * jb.N; e += kBLanes) X[e] = cx<R>{(R)Y[e].re, (R)Y[e].im};
+        __syncthreads();
       } else {
-        quad_build<R>(X, jb, r, pmax);
+        hex_build<R>(X, jb, i, pmax);
       }
     };
-    auto fp64_cost = [&]() -> double {  // fresh complex128 builder in the quad's scratch
-      quad_build<double>(reinterpret_cast<cx<double>*>(Y), jb, r, pmax);
-      return jb.valid ? quad_cost<double>(reinterpret_cast<cx<double>*>(Y), jb.N, r) : 0.0;
+    auto fp64_cost = [&]() -> double {  // fresh complex128 builder in the hex's scratch
+      hex_build<double>(reinterpret_cast<cx<double>*>(Y), jb, i, pmax);
+      return jb.valid ? hex_cost<double>(reinterpret_cast<cx<double>*>(Y), jb.N, c) : 0.0;
     };
     rebuild();
-    double c_cur = jb.valid ? quad_cost<R>(X, jb.N, r) : 0.0;
+    double c_cur = jb.valid ? hex_cost<R>(X, jb.N, c) : 0.0;
     int32_t my_flags = 0;
     if (c64 && jb.valid && c_cur < o.recheck_below)
-      c_cur = quad_cost<double>(reinterpret_cast<cx<double>*>(Y), jb.N, r);
+      c_cur = hex_cost<double>(reinterpret_cast<cx<double>*>(Y), jb.N, c);
     if (!isfinite(c_cur)) {
       c_cur = __builtin_inf();
       my_flags = kFlagNumeric | kFlagPlateau;
     }
-    if (jb.valid && r == 0) hist[0] = c_cur;
+    if (jb.valid && i == 0) hist[0] = c_cur;
 
     bool running = jb.valid && o.max_iter > 0;
     int32_t decision = kStopMaxIter;
-    int i = 0, sweeps = 0;
-    while (__any(running ? 1 : 0)) {
-      ++i;
-      // ---- one TwoSidedSweep (Alg. 1 order); quads of smaller blocks idle
-      const int steps = 2 * wave_max_int(running ? jb.p : 0);
+    int it = 0, sweeps = 0;
+    while (__syncthreads_or(running ? 1 : 0)) {
+      ++it;
+      // ---- one TwoSidedSweep (Alg. 1 order); hexes of smaller blocks idle
+      const int steps = 2 * wg_max(running ? jb.p : 0);
       for (int step = 0; step < steps; ++step) {
         const bool act = running && step < 2 * jb.p;
         const int half = (act && step >= jb.p) ? 1 : 0;
         const int g = act ? (half == 0 ? jb.p - 1 - step : step - jb.p) : 0;
         const uint32_t b0 = act ? (uint32_t)(jb.n - 1 - jb.locs[2 * g]) : 0u;
         const uint32_t b1 = act ? (uint32_t)(jb.n - 1 - jb.locs[2 * g + 1]) : 1u;
-        cx<R> A[16], Bm[16];
         if (act) {
-          // partial trace, row r: P[r][j] = sum_rest X[(r, rest), (j, rest)]
+          // partial trace, entry (r, c): P[r][c] = sum_rest X[(r, rest), (c, rest)]
           const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
-          const uint32_t ro = local_off((uint32_t)r, b0, b1);
-          cd prow[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const uint32_t co = local_off((uint32_t)j, b0, b1);
-            double re = 0.0, im = 0.0;
-            for (uint32_t rest = 0; rest < (jb.N >> 2); ++rest) {
-              const uint32_t base = insert00(rest, lo, hi);
-              const cx<R> v = X[(base + ro) * jb.N + base + co];
-              re += (double)v.re;
-              im += (double)v.im;
-            }
-            prow[j] = mk(re, im);
+          const uint32_t ro = local_off((uint32_t)r, b0, b1), co = local_off((uint32_t)c, b0, b1);
+          double re = 0.0, im = 0.0;
+          for (uint32_t rest = 0; rest < (jb.N >> 2); ++rest) {
+            const uint32_t base = insert00(rest, lo, hi);
+            const cx<R> v = X[(base + ro) * jb.N + base + co];
+            re += (double)v.re;
+            im += (double)v.im;
           }
-          cd P[4][4];  // P[k][c], gathered over the quad
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cd col[4];
-            quad_gather(prow[c], col);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) P[k][c] = col[k];
-          }
-          cd uold[16];
-#pragma unroll
-          for (int k = 0; k < 16; ++k) uold[k] = jb.g[16 * g + k];
-          cd erow[4], unew[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cd acc = mk(0.0, 0.0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              if (half == 0)
-                cmac(acc, conj(at_kr(uold, k, r)), P[k][c]);
-              else {
-                cd prk = P[0][k];  // P[r][k] by a select chain
-#pragma unroll
-                for (int rr = 1; rr < 4; ++rr) prk = sel(r == rr, P[rr][k], prk);
-                cmac(acc, prk, conj(uold[4 * c + k]));
-              }
-            }
-            erow[c] = acc;
-          }
-          if (my_flags & kFlagNumeric) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) unew[c] = at_rk(uold, r, c);
-          } else {
-            update_gate_quad(jb.kinds ? jb.kinds[g] : kKindU4, erow, uold, r, o.beta, unew);
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c) jb.g[16 * g + 4 * r + c] = unew[c];
-          // full u_new in every lane, then the pass operands
-          cd un[16];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cd col[4];
-            quad_gather(unew[c], col);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) un[4 * k + c] = col[k];
-          }
-#pragma unroll
-          for (int i2 = 0; i2 < 4; ++i2)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const cd ud = conj(uold[4 * c + i2]);  // (u_old^dagger)[i2][c]
-              const cd nv = un[4 * i2 + c];
-              const cd av = sel(half == 0, ud, nv), bv = sel(half == 0, nv, ud);
-              A[4 * i2 + c] = cx<R>{(R)av.re, (R)av.im};
-              Bm[4 * i2 + c] = cx<R>{(R)bv.re, (R)bv.im};
-            }
+          PUs[h][4 * r + c] = mk(re, im);
+          Us[h][i] = jb.g[16 * g + i];
         }
-        wave_sync();  // every lane's trace reads are done before any block is rewritten
-        if (act) quad_pass<R, true, true>(X, jb.N, b0, b1, A, Bm, r);
-        wave_sync();
+        __syncthreads();  // P and u_old in LDS; every trace read is done
+        if (act) {
+          const cd* U = Us[h];
+          const cd* P = PUs[h];
+          const int kind = jb.kinds ? jb.kinds[g] : kKindU4;
+          const bool frozen = (my_flags & kFlagNumeric) != 0;
+          // Every lane of the hex (one wavefront) reads P before any lane
+          // overwrites it with u_new below.
+          if (kind == kKindU4) {
+            const cd e = env_entry(P, U, half, r, c);
+            const cd urc = U[4 * r + c];
+            cd un = urc;
+            if (!frozen) optimize_gate_f64_hex(e, U[4 * c + r], urc, r, c, o.beta, un);
+            PUs[h][4 * r + c] = un;
+            jb.g[16 * g + 4 * r + c] = un;
+          } else if (i < 4) {  // restricted kinds: the quad form on lanes 0..3, lane i = row i
+            cd uold[16], erow[4], unew[4];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) uold[k] = U[k];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) erow[cc] = env_entry(P, U, half, i, cc);
+            if (frozen) {
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) unew[cc] = at_rk(uold, i, cc);
+            } else {
+              update_gate_quad(kind, erow, uold, i, o.beta, unew);
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              PUs[h][4 * i + cc] = unew[cc];
+              jb.g[16 * g + 4 * i + cc] = unew[cc];
+            }
+          }
+        }
+        __syncthreads();  // u_new in LDS
+        if (act) {
+          // half 0: X <- (u_old^dagger (x) I) X (u_new (x) I); half 1 mirrored
+          cx<R> A[16], Bm[16];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const cd ud = conj(Us[h][4 * j + k]);  // (u_old^dagger)[k][j]
+              const cd nv = PUs[h][4 * k + j];
+              const cd av = sel(half == 0, ud, nv), bv = sel(half == 0, nv, ud);
+              A[4 * k + j] = cx<R>{(R)av.re, (R)av.im};
+              Bm[4 * k + j] = cx<R>{(R)bv.re, (R)bv.im};
+            }
+          hex_pass<R, true, true>(X, jb.N, b0, b1, A, Bm, i);
+        }
+        __syncthreads();  // the pass is done before the next trace and LDS reuse
       }
       // ---- cost, reset, recheck, per-start tests
-      if (o.reset_iter > 0 && (i % o.reset_iter) == 0) rebuild();
-      double c_i = running ? quad_cost<R>(X, jb.N, r) : c_cur;
+      if (o.reset_iter > 0 && (it % o.reset_iter) == 0) rebuild();
+      double c_i = running ? hex_cost<R>(X, jb.N, c) : c_cur;
       const bool need = c64 && running && c_i < o.recheck_below;
-      if (__any(need ? 1 : 0)) {
+      if (__syncthreads_or(need ? 1 : 0)) {
         const double cf = fp64_cost();
         if (need) {
           c_i = cf;
-          for (uint32_t e = (uint32_t)r; e < jb.N * jb.N; e += 4) X[e] = cx<R>{(R)Y[e].re, (R)Y[e].im};
+          for (uint32_t e = (uint32_t)i; e < jb.N * jb.N; e += kBLanes) X[e] = cx<R>{(R)Y[e].re, (R)Y[e].im};
         }
-        wave_sync();
+        __syncthreads();
       }
       if (running) {
         const int32_t Lh = o.long_diff_count;
-        const double c_prev = hist[(i - 1) % d.ring];
-        const double c_back = (Lh > 0 && i >= Lh) ? hist[(i - Lh) % d.ring] : 0.0;
+        const double c_prev = hist[(it - 1) % d.ring];
+        const double c_back = (Lh > 0 && it >= Lh) ? hist[(it - Lh) % d.ring] : 0.0;
         if (!isfinite(c_i)) c_i = __builtin_inf();
-        if (!(my_flags & kFlagNumeric)) my_flags = start_flags_after_sweep(o, d.tol, i, my_flags, c_i, c_prev, c_back);
+        if (!(my_flags & kFlagNumeric)) my_flags = start_flags_after_sweep(o, d.tol, it, my_flags, c_i, c_prev, c_back);
         if (my_flags & kFlagNumeric) c_i = __builtin_inf();
         c_cur = c_i;
-        if (r == 0) hist[i % d.ring] = c_i;  // other lanes read other ring slots
       }
-      if (r == 0) flags_sh[q] = my_flags;
-      wave_sync();
+      __syncthreads();  // every lane has read the ring slots it needs
+      if (running && i == 0) hist[it % d.ring] = c_cur;
+      if (i == 0) flags_sh[h] = my_flags;
+      __syncthreads();
       if (running) {
-        decision = job_decision(o, i, &flags_sh[slot * d.S], d.S);
+        decision = job_decision(o, it, &flags_sh[slot * d.S], d.S);
         if (decision != kContinue) {
           running = false;
-          sweeps = i;
+          sweeps = it;
         }
       }
-      wave_sync();
     }
     // ---- final FP64 cost of every start, best start per block
     const double cf = fp64_cost();
     double cfin = (my_flags & kFlagNumeric) || !isfinite(cf) ? __builtin_inf() : cf;
-    if (jb.valid && r == 0) d.out_cost[(size_t)jb.b * d.S + jb.s] = cfin;
-    if (r == 0) flags_sh[q] = my_flags;
-    wave_sync();
-    if (jb.valid && jb.s == 0 && r == 0) {
+    if (jb.valid && i == 0) d.out_cost[(size_t)jb.b * d.S + jb.s] = cfin;
+    if (i == 0) flags_sh[h] = my_flags;
+    __syncthreads();
+    if (jb.valid && jb.s == 0 && i == 0) {
       int best = 0;
       double bc = d.out_cost[(size_t)jb.b * d.S];
-      bool all_numeric = (flags_sh[q] & kFlagNumeric) != 0;
+      bool all_numeric = (flags_sh[h] & kFlagNumeric) != 0;
       for (int k = 1; k < d.S; ++k) {
         const double ck = d.out_cost[(size_t)jb.b * d.S + k];
-        all_numeric = all_numeric && (flags_sh[q + k] & kFlagNumeric);
+        all_numeric = all_numeric && (flags_sh[h + k] & kFlagNumeric);
         if (ck < bc) {
           bc = ck;
           best = k;
@@ -370,14 +372,13 @@ __global__ __launch_bounds__(64) void k_batch(BatchDev d) {
       d.out_status[jb.b] = st;
       d.out_sweeps[jb.b] = sweeps;
     }
-    wave_sync();
   }
 }
 
-size_t batch_scratch_entries(int grid) { return (size_t)grid * kBQuads * kBNmax * kBNmax; }
+size_t batch_scratch_entries(int grid) { return (size_t)grid * kBSlots * kBNmax * kBNmax; }
 
 int batch_groups(int n_blocks, int S) {
-  const int B = kBQuads / S;
+  const int B = kBSlots / S;
   return (n_blocks + B - 1) / B;
 }
 
@@ -387,7 +388,7 @@ int batch_grid(int precision, int n_groups) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const void* fn = precision == QF_C64 ? reinterpret_cast<const void*>(&k_batch<float>)
                                        : reinterpret_cast<const void*>(&k_batch<double>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 64, 0) != hipSuccess || per < 1) per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBThreads, 0) != hipSuccess || per < 1) per = 1;
   int g = cus * per;
   if (g > kBatchMaxGrid) g = kBatchMaxGrid;
   return g < n_groups ? g : n_groups;
@@ -397,7 +398,7 @@ hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs
   BatchDev d;
   d.n_blocks = a.n_blocks;
   d.S = a.S;
-  d.B = kBQuads / a.S;
+  d.B = kBSlots / a.S;
   d.n_groups = batch_groups(a.n_blocks, a.S);
   if (grid < 1 || grid > kBatchMaxGrid || grid > d.n_groups) return hipErrorInvalidValue;
   d.order = a.order;
@@ -419,9 +420,9 @@ hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs
   d.queue = a.queue;
   d.kinds = a.kinds;
   if (precision == QF_C64)
-    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBThreads), 0, st, d);
   else
-    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBThreads), 0, st, d);
   return hipGetLastError();
 }
 
