@@ -269,10 +269,12 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
  * gates: gate_class 0 = the higher of the gate's two column bits (bit
  * n-1-q of a qubit q) is >= 3, gate_class 1 = both bits are among the three
  * lowest.  tile: -1 = register-direct pass, one 4x4 block per thread (needs
- * n >= 6, else the 512-column tile is used), 256 / 512 / 1024 (1024: QF_C64
- * only) = columns of the LDS-staged tile, 0 = forget the choice (the next
- * qf_instantiate times the candidates again).  Every form gives bitwise the
- * same builder.
+ * n >= 6, else the 512-column tile is used), -2 = micro-tile register pass,
+ * the two blocks of 8 adjacent columns per quad of lanes with 16-byte loads
+ * (QF_C64 only; for gate_class 1 at n >= 9, else the 512-column tile is
+ * used), 256 / 512 / 1024 (1024: QF_C64 only) = columns of the LDS-staged
+ * tile, 0 = forget the choice (the next qf_instantiate times the candidates
+ * again).  Every form gives bitwise the same builder.
  * Returns QF_EINVAL for other values. */
 int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile);
 

@@ -204,8 +204,9 @@ int ensure_scratch(qf_ctx* ctx, size_t bytes) {
   return QF_OK;
 }
 
-// Pass form of a gate: the tile width of the LDS-staged pass or kPassDirect
-// for the register-direct one.  Gates fall in two classes by where their two
+// Pass form of a gate: the tile width of the LDS-staged pass, kPassDirect
+// for the register-direct one or kPassMicro for the micro-tile register one
+// (complex64 class-1 gates at n >= 9).  Gates fall in two classes by where their two
 // column bits are (class 1: both among the three lowest bits, where the
 // direct form's loads stride by 2..8 elements); each (precision, class, n) is tuned once
 // per context by timing every candidate on the caller's builder with identity
@@ -226,9 +227,9 @@ int pass_tcols(qf_ctx* ctx, int precision, int n, int q0, int q1) {
 
 int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
   const int N = 1 << n;
-  const int cands64[] = {kPassDirect, 256, 512, 1024}, cands128[] = {kPassDirect, 256, 512};
+  const int cands64[] = {kPassDirect, kPassMicro, 256, 512, 1024}, cands128[] = {kPassDirect, 256, 512};
   const int* cands = precision == QF_C64 ? cands64 : cands128;
-  const int nc = precision == QF_C64 ? 4 : 3;
+  const int nc = precision == QF_C64 ? 5 : 3;
   if (!ctx->identity) {
     QF_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->identity), 16 * 16));
     double id[32] = {};
@@ -249,10 +250,11 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
     QF_HIP(ctx, hipEventCreate(&e1));
     // Two rounds over the candidates (warm-up launch, then 4 timed launches);
     // each candidate keeps its better round.
-    float t_best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    float t_best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
     for (int round = 0; round < 2; ++round)
       for (int c = 0; c < nc; ++c) {
         if (cands[c] > N) continue;
+        if (cands[c] == kPassMicro && (cls == 0 || n < 9)) continue;  // class-1 gates at n >= 9 only
         const PassGeom geo = make_pass_geom(n, q0, q1, cands[c]);
         hipError_t err = launch_pass(ctx->stream, precision, X, S, geo, I, I);
         if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
@@ -945,7 +947,8 @@ int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile
   if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
   if (n < 2 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [2, 16]", n);
   if (gate_class != 0 && gate_class != 1) return fail(ctx, QF_EINVAL, "gate_class must be 0 or 1");
-  const bool ok = tile == 0 || tile == kPassDirect || tile == 256 || tile == 512 || (tile == 1024 && precision == QF_C64);
+  const bool ok = tile == 0 || tile == kPassDirect || tile == 256 || tile == 512 ||
+                  ((tile == 1024 || tile == kPassMicro) && precision == QF_C64);
   if (!ok) return fail(ctx, QF_EINVAL, "tile %d not supported", tile);
   ctx->tuned_tcols[precision == QF_C64][gate_class][n] = tile;
   return QF_OK;

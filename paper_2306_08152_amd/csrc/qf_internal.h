@@ -27,9 +27,12 @@ struct PassGeom {
   uint32_t col_tiles;        // column tiles per row quad
   uint32_t tiles_per_start;  // (N/4) * col_tiles
   uint32_t direct;           // 1: register-direct pass (no LDS tile), n >= 6 only
+  uint32_t micro;            // 1: micro-tile register pass (complex64, both bits <= 2, n >= 9)
 };
-// Tile-width value that selects the register-direct pass.
+// Tile-width values that select the register-direct pass and the micro-tile
+// register pass.
 constexpr int kPassDirect = -1;
+constexpr int kPassMicro = -2;
 
 PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols);
 

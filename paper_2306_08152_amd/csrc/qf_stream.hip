@@ -56,9 +56,14 @@ __device__ __forceinline__ uint32_t ilog2u(uint32_t v) { return 31u - __builtin_
 PassGeom make_pass_geom(int n, int q0, int q1, int max_tcols) {
   PassGeom g{};
   g.direct = 0;
+  g.micro = 0;
   if (max_tcols == kPassDirect) {
     if (n >= 6) g.direct = 1u;
     max_tcols = pass_max_tcols(QF_C128);  // the LDS tile serves n < 6
+  } else if (max_tcols == kPassMicro) {
+    const int hb = (n - 1 - q0) > (n - 1 - q1) ? (n - 1 - q0) : (n - 1 - q1);
+    if (n >= 9 && hb <= 2) g.micro = 1u;
+    max_tcols = pass_max_tcols(QF_C128);  // the LDS tile serves other gates
   }
   g.n = (uint32_t)n;
   g.N = 1u << n;
@@ -324,6 +329,174 @@ __global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassG
     for (uint32_t j = 0; j < 4; ++j) base[(rb + off[i]) * N + cb + off[j]] = x[4 * i + j];
 }
 
+// ------------------------------------------------------------ k_pass_micro
+//
+// Register form of the pass for complex64 gates whose two column bits are
+// both among the three lowest (the class where the block-per-thread form's
+// loads stride by 2..8 elements): n >= 9.  The 8 columns that share the
+// high column bits form a micro-tile holding two 4x4 blocks of the gate (the
+// third low bit picks the block).  A wavefront covers 512 consecutive
+// columns (4 KiB) of each of a block row-group's four rows with 16 B loads:
+// load k of a row puts columns 128k + 2l, 128k + 2l + 1 in lane l, so every
+// load instruction reads 1 KiB contiguously and the four lanes of a quad hold
+// one micro-tile's row.  The left product (rows) is lane-local; each entry of
+// the right product (columns) takes its four operands from the quad by DPP
+// quad_perm moves, whose patterns follow from the gate's bits at compile
+// time.  Each output is the block-per-thread form's sum, term by term, so
+// all forms give bitwise the same builder.
+
+// Column (0..7) of the micro-tile holding gate-local index l in the block of
+// column c; the gate's column bits are B0 (high local bit) and B1.
+__host__ __device__ constexpr int mt_col(int B0, int B1, int c, int l) {
+  return (((l >> 1) & 1) << B0) | ((l & 1) << B1) | (c & (1 << (3 - B0 - B1)));
+}
+// quad_perm selector: lane q reads the lane holding operand l of its column 2q + h.
+__host__ __device__ constexpr int mt_pat(int B0, int B1, int h, int l) {
+  return (mt_col(B0, B1, h, l) >> 1) | ((mt_col(B0, B1, 2 + h, l) >> 1) << 2) |
+         ((mt_col(B0, B1, 4 + h, l) >> 1) << 4) | ((mt_col(B0, B1, 6 + h, l) >> 1) << 6);
+}
+// Which of the source lane's two columns it is (the same for every lane).
+__host__ __device__ constexpr int mt_slot(int B0, int B1, int h, int l) { return mt_col(B0, B1, h, l) & 1; }
+__host__ __device__ constexpr bool mt_slot_uniform(int B0, int B1) {
+  for (int h = 0; h < 2; ++h)
+    for (int l = 0; l < 4; ++l)
+      for (int q = 0; q < 4; ++q)
+        if ((mt_col(B0, B1, 2 * q + h, l) & 1) != mt_slot(B0, B1, h, l)) return false;
+  return true;
+}
+
+template <int CTRL>
+__device__ __forceinline__ cf dpp_cf(cf v) {
+  return cf{__int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.re), CTRL, 0xF, 0xF, false)),
+            __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.im), CTRL, 0xF, 0xF, false))};
+}
+template <int B0, int B1, int H, int L>
+__device__ __forceinline__ cf mt_operand(const cf x[2]) {
+  constexpr int P = mt_pat(B0, B1, H, L);
+  constexpr int SL = mt_slot(B0, B1, H, L);
+  if constexpr (P == 0xE4) return x[SL];  // [0,1,2,3]: the lane's own column
+  else return dpp_cf<P>(x[SL]);
+}
+// Right product of one micro-tile row: z[h] = sum_l x(column of l) b[l][j_h].
+template <int B0, int B1>
+__device__ __forceinline__ void mt_right(const cf x[2], const cf bc[2][4], cf z[2]) {
+  const cf o00 = mt_operand<B0, B1, 0, 0>(x), o01 = mt_operand<B0, B1, 0, 1>(x);
+  const cf o02 = mt_operand<B0, B1, 0, 2>(x), o03 = mt_operand<B0, B1, 0, 3>(x);
+  const cf o10 = mt_operand<B0, B1, 1, 0>(x), o11 = mt_operand<B0, B1, 1, 1>(x);
+  const cf o12 = mt_operand<B0, B1, 1, 2>(x), o13 = mt_operand<B0, B1, 1, 3>(x);
+  cf a0 = mk(0.f, 0.f), a1 = mk(0.f, 0.f);
+  cmac(a0, o00, bc[0][0]);
+  cmac(a0, o01, bc[0][1]);
+  cmac(a0, o02, bc[0][2]);
+  cmac(a0, o03, bc[0][3]);
+  cmac(a1, o10, bc[1][0]);
+  cmac(a1, o11, bc[1][1]);
+  cmac(a1, o12, bc[1][2]);
+  cmac(a1, o13, bc[1][3]);
+  z[0] = a0;
+  z[1] = a1;
+}
+
+template <int B0, int B1, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t n, uint32_t wg_per_start,
+                                                    Operand A, Operand B) {
+  static_assert(B0 != B1 && B0 >= 0 && B0 <= 2 && B1 >= 0 && B1 <= 2, "both gate bits among the three lowest");
+  static_assert(mt_slot_uniform(B0, B1), "operand slots must not depend on the lane");
+  constexpr uint32_t LO = B0 < B1 ? B0 : B1, HI = B0 < B1 ? B1 : B0;
+  const uint32_t N = 1u << n;
+  const uint32_t s = blockIdx.x / wg_per_start;
+  const uint32_t w = (blockIdx.x - s * wg_per_start) * 4u + (threadIdx.x >> 6);  // wavefront within the start
+  const uint32_t W = N >> 9;                                                      // 512-column spans per row
+  const uint32_t rgi = w / W, span = w - rgi * W;
+  const uint32_t rb = insert00(rgi, LO, HI);
+  const uint32_t lane = threadIdx.x & 63u, q = lane & 3u;
+  cf* base = X + (size_t)s * N * N + (size_t)span * 512u + 2u * lane;
+  cf a[16], b[16];
+  if (HA) load_operand_uniform<float>(a, A, s);
+  if (HB) load_operand_uniform<float>(b, B, s);
+  // x[i][k][h]: row rb + off(i), column 128k + 2 lane + h of the span
+  cf x[4][4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t row = rb + (uint32_t)mt_col(B0, B1, 0, i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 v = *reinterpret_cast<const float4*>(base + row * N + 128u * k);
+      x[i][k][0] = mk(v.x, v.y);
+      x[i][k][1] = mk(v.z, v.w);
+    }
+  }
+  if (HA) {  // x <- A x, lane-local
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        cf r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          cf acc = mk(0.f, 0.f);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cmac(acc, a[4 * i + j], x[j][k][h]);
+          r[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i][k][h] = r[i];
+      }
+  }
+  if (HB) {  // x <- x B, operands from the quad
+    // bc[h][l] = B[l][j] for the gate-local index j of this lane's column 2q + h
+    cf bc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t c = 2u * q + (uint32_t)h;
+      const uint32_t j = (((c >> B0) & 1u) << 1) | ((c >> B1) & 1u);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        cf v = b[4 * l];
+#pragma unroll
+        for (int jj = 1; jj < 4; ++jj) v = sel(j == (uint32_t)jj, b[4 * l + jj], v);
+        bc[h][l] = v;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        cf z[2];
+        mt_right<B0, B1>(x[i][k], bc, z);
+        x[i][k][0] = z[0];
+        x[i][k][1] = z[1];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t row = rb + (uint32_t)mt_col(B0, B1, 0, i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<float4*>(base + row * N + 128u * k) =
+          make_float4(x[i][k][0].re, x[i][k][0].im, x[i][k][1].re, x[i][k][1].im);
+  }
+}
+
+template <int B0, int B1, bool HA, bool HB>
+static hipError_t launch_pass_micro_t(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B) {
+  const uint32_t wgps = g.N * g.N / 8192u;  // (N/4 row groups) x (N/512 spans) wavefronts, 4 per workgroup
+  hipLaunchKernelGGL((k_pass_micro<B0, B1, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), 0, st, x, g.n, wgps, A, B);
+  return hipGetLastError();
+}
+template <bool HA, bool HB>
+static hipError_t launch_pass_micro(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B) {
+  switch (g.b0 * 3 + g.b1) {
+    case 0 * 3 + 1: return launch_pass_micro_t<0, 1, HA, HB>(st, x, S, g, A, B);
+    case 0 * 3 + 2: return launch_pass_micro_t<0, 2, HA, HB>(st, x, S, g, A, B);
+    case 1 * 3 + 0: return launch_pass_micro_t<1, 0, HA, HB>(st, x, S, g, A, B);
+    case 1 * 3 + 2: return launch_pass_micro_t<1, 2, HA, HB>(st, x, S, g, A, B);
+    case 2 * 3 + 0: return launch_pass_micro_t<2, 0, HA, HB>(st, x, S, g, A, B);
+    case 2 * 3 + 1: return launch_pass_micro_t<2, 1, HA, HB>(st, x, S, g, A, B);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename R, bool HA, bool HB>
 static hipError_t launch_pass_direct(hipStream_t st, cx<R>* x, int S, const PassGeom& g, Operand A, Operand B) {
   const uint32_t wgps = g.N * g.N / 4096u;  // N^2/16 blocks, 256 per workgroup
@@ -354,6 +527,16 @@ static hipError_t launch_pass_t(hipStream_t st, void* X, int S, const PassGeom& 
                                 Operand B) {
   const uint32_t total = (uint32_t)S * g.tiles_per_start;
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
+  if (g.micro && (reinterpret_cast<uintptr_t>(X) & 15u) == 0) {  // 16 B loads; else the LDS tile below
+    if constexpr (sizeof(R) == 4) {
+      if (A.ptr && B.ptr) return launch_pass_micro<true, true>(st, x, S, g, A, B);
+      if (A.ptr) return launch_pass_micro<true, false>(st, x, S, g, A, B);
+      if (B.ptr) return launch_pass_micro<false, true>(st, x, S, g, A, B);
+      return hipSuccess;
+    } else {
+      return hipErrorInvalidValue;  // complex64 only
+    }
+  }
   if (g.direct) {
     if (A.ptr && B.ptr) return launch_pass_direct<R, true, true>(st, x, S, g, A, B);
     if (A.ptr) return launch_pass_direct<R, true, false>(st, x, S, g, A, B);

@@ -208,22 +208,25 @@ def test_update_gate_steps(qf, n, dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_pass_forms_bitwise_equal(qf, dtype):
-    """Every form of the fused pass (register-direct, LDS tiles of every
-    width) gives bitwise the same builder for one-sided
-    products of both sides and for the two-sided update, at every qubit pair
-    of n = 6 and a spread of pairs (lowest bits included) of n = 10; the
-    one-sided products also match the oracle."""
+    """Every form of the fused pass (register-direct, micro-tile for
+    complex64, LDS tiles of every width) gives bitwise the same builder for
+    one-sided products of both sides and for the two-sided update, at every
+    qubit pair of n = 6 and a spread of pairs (all six ordered pairs of the
+    three lowest bits included) of n = 9 and 10; the one-sided products also
+    match the oracle."""
     prec = 0 if dtype == "c128" else 1
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
-    forms = [-1, 256, 512] + ([1024] if dtype == "c64" else [])
+    forms = [-1, 256, 512] + ([1024, -2] if dtype == "c64" else [])
     S = 2
     try:
-        for n in (6, 7, 10):
+        for n in (6, 7, 9, 10):
             rng = np.random.default_rng(4000 + n)
             X0 = I.random_builder(rng, S, n)
             if dtype == "c64":
                 X0 = X0.astype(np.complex64).astype(np.complex128)
             prs = pairs(n)
+            if n == 9:
+                prs = prs[::9] + [(7, 8), (8, 7), (6, 7), (7, 6), (6, 8), (8, 6)]
             if n == 10:
                 prs = prs[::5] + [(8, 9), (9, 8), (7, 8), (8, 7), (7, 9), (9, 7), (0, 9), (9, 0)]
             for k, loc in enumerate(prs):
