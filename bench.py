@@ -327,8 +327,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "fused remove + re-apply pass, complex64, 16 builders per launch (register-direct "
-                               "k_pass_block or LDS-tiled k_pass, as tuned per gate class); one read + one write of "
-                               "every builder entry",
+                               "k_pass_block, micro-tile k_pass_micro or LDS-tiled k_pass, as tuned per gate class); "
+                               "one read + one write of every builder entry",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
                      "launches_timed": tm["pass_launches"], "pass_form_mid_gate": tm.get("pass_tcols"),
                      "traffic_source": "profiles/k_pass_n10_s16_c64_traffic.json (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
