@@ -56,7 +56,11 @@ definition mode; for the gradient: brute-force central differences, torch's
 own autograd on an independent dense construction, the flat gate-phase
 direction, the vanishing Riemannian gradient at the global minimum, the
 closed form exp(i t P) = cos t I + i sin t P of the parameterised gates, and
-finite differences of the parameter chain rule.
+finite differences of the parameter chain rule.  Gates may act on any number
+k of qubits (2^k x 2^k unitaries; the paper states the method for any gate
+size); the three-qubit forms are pinned against Kronecker embeddings after
+qubit swaps, brute-force derivatives, the nuclear-norm bound of Eq. opt_u,
+builder against definition mode and the fixed point of a target's own gates.
 """
 from __future__ import annotations
 
@@ -123,12 +127,13 @@ def _swap_qubits_perm(n: int, q1: int, q2: int) -> np.ndarray:
 
 
 def embed_kron(u: np.ndarray, loc, n: int) -> np.ndarray:
-    """Textbook construction of the same operator for a two-qubit gate: bring
-    loc to the adjacent pair (0, 1) with qubit swaps, use I kron-free form
-    u (x) I_{2^(n-2)}, and swap back.  Independent of `embed`; used as a pin."""
-    a, b = int(loc[0]), int(loc[1])
+    """Textbook construction of the same operator for a gate on k = len(loc)
+    qubits: bring loc to the leading positions 0..k-1 with qubit swaps, use
+    the Kronecker form u (x) I_{2^(n-k)}, and swap back.  Independent of
+    `embed`; used as a pin."""
+    k = len(loc)
     N = 1 << n
-    # permutation P maps qubit a -> 0 and qubit b -> 1
+    # permutation P maps qubit loc[t] -> position t
     P = np.eye(N, dtype=np.complex128)
     order = list(range(n))  # order[pos] = original qubit currently at position pos
 
@@ -138,13 +143,11 @@ def embed_kron(u: np.ndarray, loc, n: int) -> np.ndarray:
         P = S @ P
         order[pos1], order[pos2] = order[pos2], order[pos1]
 
-    pa = order.index(a)
-    if pa != 0:
-        swap(0, pa)
-    pb = order.index(b)
-    if pb != 1:
-        swap(1, pb)
-    core = np.kron(u, np.eye(N >> 2, dtype=np.complex128))
+    for t, q in enumerate(loc):
+        pq = order.index(int(q))
+        if pq != t:
+            swap(t, pq)
+    core = np.kron(u, np.eye(N >> k, dtype=np.complex128))
     return P.conj().T @ core @ P
 
 
@@ -153,43 +156,50 @@ def embed_kron(u: np.ndarray, loc, n: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def apply_left(X: np.ndarray, u: np.ndarray, loc, n: int) -> np.ndarray:
-    """G X for G = u on loc.  X is (N, M) (any number M of columns) or carries
-    one leading batch axis (S, N, M); u may then be (S, 4, 4) (one gate per
-    batch entry) or (4, 4)."""
+    """G X for G = u on loc (a gate on k = len(loc) qubits, u of side 2^k).
+    X is (N, M) (any number M of columns) or carries one leading batch axis
+    (S, N, M); u may then be (S, 2^k, 2^k) (one gate per batch entry) or
+    (2^k, 2^k)."""
     M = X.shape[-1]
-    a, b = int(loc[0]), int(loc[1])
+    k = len(loc)
+    d = 1 << k
     batch = X.shape[:-2]
     if u.ndim == 2:
-        u = np.broadcast_to(u, batch + (4, 4))
+        u = np.broadcast_to(u, batch + (d, d))
     lt = [chr(ord('a') + i) for i in range(n)]
+    new = [chr(ord('A') + t) for t in range(k)]  # output legs of the gate
     z = 'Z' if batch else ''
     xin = z + ''.join(lt) + 'Y'
     out_l = list(lt)
-    out_l[a], out_l[b] = 'O', 'P'
-    uin = z + 'OP' + lt[a] + lt[b]
+    for t, q in enumerate(loc):
+        out_l[int(q)] = new[t]
+    uin = z + ''.join(new) + ''.join(lt[int(q)] for q in loc)
     xo = z + ''.join(out_l) + 'Y'
     Xr = X.reshape(batch + (2,) * n + (M,))
-    ur = u.reshape(batch + (2, 2, 2, 2))
+    ur = u.reshape(batch + (2,) * (2 * k))
     out = np.einsum(f"{uin},{xin}->{xo}", ur, Xr, optimize=True)
     return out.reshape(X.shape)
 
 
 def apply_right(X: np.ndarray, u: np.ndarray, loc, n: int) -> np.ndarray:
-    """X G for G = u on loc (batch rules as apply_left)."""
+    """X G for G = u on loc (gate size and batch rules as apply_left)."""
     N = 1 << n
-    a, b = int(loc[0]), int(loc[1])
+    k = len(loc)
+    d = 1 << k
     batch = X.shape[:-2]
     if u.ndim == 2:
-        u = np.broadcast_to(u, batch + (4, 4))
+        u = np.broadcast_to(u, batch + (d, d))
     lt = [chr(ord('a') + i) for i in range(n)]
+    new = [chr(ord('A') + t) for t in range(k)]  # input legs after the product
     z = 'Z' if batch else ''
     xin = z + 'Y' + ''.join(lt)
     out_l = list(lt)
-    out_l[a], out_l[b] = 'O', 'P'
-    uin = z + lt[a] + lt[b] + 'OP'
+    for t, q in enumerate(loc):
+        out_l[int(q)] = new[t]
+    uin = z + ''.join(lt[int(q)] for q in loc) + ''.join(new)
     xo = z + 'Y' + ''.join(out_l)
     Xr = X.reshape(batch + (N,) + (2,) * n)
-    ur = u.reshape(batch + (2, 2, 2, 2))
+    ur = u.reshape(batch + (2,) * (2 * k))
     out = np.einsum(f"{xin},{uin}->{xo}", Xr, ur, optimize=True)
     return out.reshape(X.shape)
 
@@ -255,18 +265,21 @@ def partial_trace_loops(X: np.ndarray, loc, n: int) -> np.ndarray:
 
 
 def partial_trace(X: np.ndarray, loc, n: int) -> np.ndarray:
-    """Same partial trace by index contraction; X may carry one batch axis."""
+    """Same partial trace by index contraction (gate on k = len(loc)
+    qubits); X may carry one batch axis."""
     batch = X.shape[:-2]
-    a, b = int(loc[0]), int(loc[1])
+    k = len(loc)
     lt = [chr(ord('a') + i) for i in range(n)]
+    new = [chr(ord('A') + t) for t in range(k)]
     col = list(lt)
-    col[a], col[b] = 'O', 'P'
+    for t, q in enumerate(loc):
+        col[int(q)] = new[t]
     z = 'Z' if batch else ''
     sub = z + ''.join(lt) + ''.join(col)
-    outs = z + lt[a] + lt[b] + 'OP'
+    outs = z + ''.join(lt[int(q)] for q in loc) + ''.join(new)
     Xr = X.reshape(batch + (2,) * (2 * n))
     E = np.einsum(f"{sub}->{outs}", Xr, optimize=True)
-    return E.reshape(batch + (4, 4))
+    return E.reshape(batch + (1 << k, 1 << k))
 
 
 def environment(V: np.ndarray, gates, locs, n: int, g: int) -> np.ndarray:
@@ -403,7 +416,7 @@ def optimize_gate_batched(E: np.ndarray, u_old: np.ndarray, beta: float = 0.0) -
     finite = np.all(np.isfinite(M), axis=(-2, -1))
     scale = np.max(np.abs(np.where(finite[:, None, None], M, 0.0)), axis=(-2, -1))
     zero = scale < 1e-300
-    Ms = np.where((finite & ~zero)[:, None, None], M / np.where(zero, 1.0, scale)[:, None, None], np.eye(4))
+    Ms = np.where((finite & ~zero)[:, None, None], M / np.where(zero, 1.0, scale)[:, None, None], np.eye(M.shape[-1]))
     Xs, _, Yh = np.linalg.svd(Ms)
     out = np.conj(np.swapaxes(Yh, -1, -2)) @ np.conj(np.swapaxes(Xs, -1, -2))
     out = np.where(zero[:, None, None], u_old, out)
@@ -448,7 +461,7 @@ class BuilderOracle:
         self.n = n
         self.N = 1 << n
         self.locs = [tuple(int(q) for q in l) for l in locs]
-        self.gates = np.array(gates, dtype=np.complex128)  # (S, p, 4, 4)
+        self.gates = np.array(gates, dtype=np.complex128)  # (S, p, 2^k, 2^k)
         if self.gates.ndim == 3:
             self.gates = self.gates[None]
         self.S = self.gates.shape[0]
@@ -520,8 +533,8 @@ class Options:
 
 @dataclass
 class Result:
-    gates: np.ndarray          # (p, 4, 4) best start
-    all_gates: np.ndarray      # (S, p, 4, 4)
+    gates: np.ndarray          # (p, 2^k, 2^k) best start
+    all_gates: np.ndarray      # (S, p, 2^k, 2^k)
     costs: np.ndarray          # (S,) final costs recomputed from scratch
     best_start: int
     sweeps: int

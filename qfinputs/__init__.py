@@ -73,20 +73,34 @@ def random_nn_locations(rng: np.random.Generator, n: int, count: int) -> np.ndar
 
 
 def circuit_unitary(gates: np.ndarray, locs: np.ndarray, n: int) -> np.ndarray:
-    """Target construction: C = G_p ... G_1 for two-qubit gates in time order.
+    """Target construction: C = G_p ... G_1 for gates in time order, each on
+    k = len(loc) qubits (k = 2 or 3 here).
 
     Each gate is applied to the running matrix by viewing its row index as n
-    binary legs (qubit 0 first) and contracting the gate with the two legs it
+    binary legs (qubit 0 first) and contracting the gate with the k legs it
     acts on.  Used only to synthesise targets from seeded gates."""
     N = 1 << n
     c = np.eye(N, dtype=np.complex128)
-    for u, (a, b) in zip(gates, locs):
+    for u, loc in zip(gates, locs):
+        k = len(loc)
+        legs = [int(q) for q in loc]
         t = c.reshape((2,) * n + (N,))
-        u4 = np.asarray(u, np.complex128).reshape(2, 2, 2, 2)
-        t = np.tensordot(u4, t, axes=([2, 3], [int(a), int(b)]))
-        t = np.moveaxis(t, [0, 1], [int(a), int(b)])
+        uk = np.asarray(u, np.complex128).reshape((2,) * (2 * k))
+        t = np.tensordot(uk, t, axes=(list(range(k, 2 * k)), legs))
+        t = np.moveaxis(t, list(range(k)), legs)
         c = np.ascontiguousarray(t.reshape(N, N))
     return c
+
+
+def brickwall3_locations(n: int, layers: int) -> np.ndarray:
+    """Open-chain brick-wall of three-qubit gates: layer l acts on
+    (s, s+1, s+2), (s+3, s+4, s+5), ... with s = l mod 3.  Returns a (p, 3)
+    int32 array in time order."""
+    locs = []
+    for layer in range(layers):
+        for q in range(layer % 3, n - 2, 3):
+            locs.append((q, q + 1, q + 2))
+    return np.asarray(locs, dtype=np.int32).reshape(-1, 3)
 
 
 @dataclass
@@ -95,10 +109,10 @@ class Problem:
 
     name: str
     n: int
-    locs: np.ndarray            # (p, 2) int32
-    target_gates: np.ndarray    # (p, 4, 4) complex128, the gates V was built from
+    locs: np.ndarray            # (p, k) int32, k = 2 (3 for the three-qubit problems)
+    target_gates: np.ndarray    # (p, 2^k, 2^k) complex128, the gates V was built from
     target: np.ndarray          # (N, N) complex128 (may be None for huge n until built)
-    init_gates: np.ndarray      # (S, p, 4, 4) complex128
+    init_gates: np.ndarray      # (S, p, 2^k, 2^k) complex128
     meta: dict = field(default_factory=dict)
 
     @property
@@ -113,11 +127,14 @@ class Problem:
 def make_problem(config_id: int, name: str, n: int, locs: np.ndarray, n_starts: int,
                  build_target: bool = True, block: int = 0) -> Problem:
     """Target from Haar gates (role 0, index=block) on `locs`; init gates for each
-    start s from stream (role 1, index=block*65536+s)."""
+    start s from stream (role 1, index=block*65536+s).  Gates act on
+    locs.shape[1] qubits (2^k x 2^k Haar unitaries)."""
+    locs = np.asarray(locs, np.int32)
     p = int(locs.shape[0])
-    tg = haar_gates(rng_for(config_id, ROLE_TARGET, block), p)
-    init = np.stack([haar_gates(rng_for(config_id, ROLE_INIT, block * 65536 + s), p)
-                     for s in range(n_starts)]) if n_starts else np.zeros((0, p, 4, 4), np.complex128)
+    d = 1 << int(locs.shape[1])
+    tg = haar_gates(rng_for(config_id, ROLE_TARGET, block), p, d)
+    init = np.stack([haar_gates(rng_for(config_id, ROLE_INIT, block * 65536 + s), p, d)
+                     for s in range(n_starts)]) if n_starts else np.zeros((0, p, d, d), np.complex128)
     target = circuit_unitary(tg, locs, n) if build_target else None
     return Problem(name, n, np.asarray(locs, np.int32), tg, target, init)
 
@@ -190,6 +207,13 @@ def deletion_problem(config_id: int, n: int, p: int, p_target: int, n_starts: in
 
 
 CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], np.complex128)
+
+
+def k3_problem(config_id: int, n: int, layers: int, n_starts: int, build_target: bool = True) -> Problem:
+    """Three-qubit-gate brick-wall (brickwall3_locations) with Haar U(8) target
+    gates and Haar initial gates (make_problem's streams)."""
+    return make_problem(config_id, f"k3_n{n}_l{layers}", n, brickwall3_locations(n, layers), n_starts,
+                        build_target=build_target)
 
 
 def u3cx_problem(config_id: int, n: int, layers: int, n_starts: int, build_target: bool = True):

@@ -704,3 +704,122 @@ def test_ms_definition_and_update():
                 + np.real(-1j * E[2, 1] / ed - 1j * E[1, 2] * ed)) / np.sqrt(2.0)
         assert best >= grid.max() - 1e-12 and best - grid.max() < 1e-4
         assert np.abs(u.conj().T @ u - np.eye(4)).max() < 1e-14
+
+
+# ---------------------------------------------------------------- three-qubit gates
+# The method is stated for gates of any size (Sec. III: the environment of a
+# gate is the tensor network with that gate removed; Eq. opt_u holds for any
+# unitary size).  These pins tie the oracle's k = 3 forms to independent
+# constructions.
+
+def triples(n):
+    return [(a, b, c) for a in range(n) for b in range(n) for c in range(n) if len({a, b, c}) == 3]
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_k3_embedding_apply_and_trace(n):
+    """apply_left / apply_right / embed / partial_trace of a three-qubit gate
+    against the Kronecker construction u (x) I after qubit swaps, and the
+    orientation identity Tr((u (x) I) X) = Tr(E u)."""
+    rng = np.random.default_rng(3000 + n)
+    X = I.random_builder(rng, 1, n)[0]
+    locs = triples(n)
+    if n == 5:
+        locs = locs[::4] + [(4, 3, 2), (0, 4, 2)]
+    for loc in locs:
+        u = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+        K = O.embed_kron(u, loc, n)
+        np.testing.assert_allclose(O.embed(u, loc, n), K, atol=1e-13)
+        np.testing.assert_allclose(O.apply_left(X, u, loc, n), K @ X, atol=1e-12)
+        np.testing.assert_allclose(O.apply_right(X, u, loc, n), X @ K, atol=1e-12)
+        E = O.partial_trace(X, loc, n)
+        np.testing.assert_allclose(E, O.partial_trace_loops(X, loc, n), atol=1e-13)
+        assert abs(np.trace(K @ X) - np.trace(E @ u)) < 1e-12
+
+
+def test_k3_embed_kron_of_adjacent_leading_qubits():
+    """For loc = (0, 1, 2) no swap is needed: the operator is u (x) I."""
+    rng = np.random.default_rng(3010)
+    u = I.haar_unitary(rng, 8)
+    np.testing.assert_allclose(O.embed(u, (0, 1, 2), 4), np.kron(u, np.eye(2)), atol=1e-15)
+    # a two-qubit gate embedded as a three-qubit one with an identity factor
+    v = I.haar_unitary(rng, 4)
+    np.testing.assert_allclose(O.embed(np.kron(v, np.eye(2)), (1, 3, 0), 4), O.embed(v, (1, 3), 4), atol=1e-14)
+
+
+@pytest.mark.parametrize("n,layers", [(4, 3), (5, 4)])
+def test_k3_trace_invariant_and_derivative(n, layers):
+    """Tr(E_g u_g) = Tr(V^dagger C) for every three-qubit gate, and E_g is
+    the exact derivative: T(u_g := e_ji) = E_g[i, j] (dense products)."""
+    pr = I.k3_problem(31, n, layers, 1)
+    rng = np.random.default_rng(3020 + n)
+    V = I.haar_unitary(rng, 1 << n)
+    gates = pr.init_gates[0]
+    T = O.overlap(V, O.circuit_unitary(gates, pr.locs, n, dense=True))
+    for g in range(pr.n_gates):
+        E = O.environment(V, gates, pr.locs, n, g)
+        assert abs(np.trace(E @ gates[g]) - T) < 1e-12 * (1 << n)
+    g = pr.n_gates // 2
+    E = O.environment(V, gates, pr.locs, n, g)
+    for (i, j) in [(0, 0), (3, 5), (7, 2)]:
+        G = gates.copy()
+        G[g] = 0.0
+        G[g][j, i] = 1.0
+        Tij = O.overlap(V, O.circuit_unitary(G, pr.locs, n, dense=True))
+        assert abs(Tij - E[i, j]) < 1e-12 * (1 << n)
+
+
+def test_k3_update_maximises_and_is_unitary():
+    """Eq. opt_u for 8 x 8: the result is unitary, attains the nuclear norm
+    (von Neumann's trace inequality bound) and beats random unitaries."""
+    rng = np.random.default_rng(3030)
+    for k in range(6):
+        E = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+        if k == 1:
+            E[:, 3] = 0.5 * E[:, 0] - 2j * E[:, 6]  # rank 7
+        if k == 2:
+            E[2, :] = 0.0                           # zero row
+        u = O.optimize_gate(E, np.eye(8, dtype=np.complex128))
+        assert np.abs(u.conj().T @ u - np.eye(8)).max() < 1e-12
+        nn = O.nuclear_norm(E)
+        assert abs(np.real(np.trace(E @ u)) - nn) < 1e-12 * nn
+        for _ in range(20):
+            w = I.haar_unitary(rng, 8)
+            assert np.real(np.trace(E @ w)) <= nn + 1e-12
+
+
+def test_k3_sweep_monotone_and_builder_equals_definition():
+    """Per-update monotonicity at beta = 0 (Sec. III-A) and Alg. 1's circuit
+    tensor against the from-scratch definition, update by update, for a
+    three-qubit-gate circuit with two starts."""
+    n = 5
+    pr = I.k3_problem(32, n, 4, 2)
+    rng = np.random.default_rng(3040)
+    V = I.haar_unitary(rng, 1 << n)
+    b = O.BuilderOracle(V, pr.init_gates, pr.locs, n)
+    recb = []
+    b.sweep(record=recb)
+    for s in range(2):
+        recd = []
+        O.sweep_definition(V, pr.init_gates[s], pr.locs, n, record=recd)
+        prev = abs(O.overlap(V, O.circuit_unitary(pr.init_gates[s], pr.locs, n)))
+        for (gd, hd, Ed, ud, Td), (gb, hb, Eb, ub, Tb) in zip(recd, recb):
+            assert (gd, hd) == (gb, hb)
+            np.testing.assert_allclose(Eb[s], Ed, atol=1e-12 * (1 << n))
+            np.testing.assert_allclose(ub[s], ud, atol=1e-11)
+            assert abs(Td) >= prev - 1e-13 * (1 << n)
+            prev = abs(Td)
+
+
+def test_k3_fixed_point_and_convergence():
+    """A target built from three-qubit gates: its own gates are a fixed point
+    (cost 0, E_g = 2^(n-3) u_g^dagger), and instantiation from Haar starts
+    reaches it."""
+    n = 4
+    pr = I.k3_problem(33, n, 2, 2)
+    assert O.cost(pr.target, pr.target_gates, pr.locs, n) < 1e-14
+    for g in range(pr.n_gates):
+        E = O.environment(pr.target, pr.target_gates, pr.locs, n, g)
+        np.testing.assert_allclose(E, (1 << (n - 3)) * pr.target_gates[g].conj().T, atol=1e-12)
+    r = O.instantiate(pr.target, pr.init_gates, pr.locs, n, tol=1e-10, opt=O.Options(max_iter=2000))
+    assert r.status == O.STATUS_CONVERGED and r.costs[r.best_start] < 1e-10
