@@ -278,6 +278,36 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
  * Returns QF_EINVAL for other values. */
 int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile);
 
+/* Three-qubit gates (Sec. III: the environment and the update of Eq. opt_u
+ * hold for gates of any size; the k = 3 gate-set variant of Sec. III-A-3).
+ * qf_instantiate for a circuit whose every gate is an 8 x 8 unitary on three
+ * qubits:
+ *   locations:  host, n_gates x 3 int32, three distinct qubits in [0, n)
+ *               (loc[0] the gate's most significant local bit, Q1)
+ *   init_gates: device, n_starts x n_gates x 8 x 8 c128 (row-major)
+ *   out_gates:  device, n_gates x 8 x 8 c128, the best start's gates
+ *   out_all_gates: optional device, n_starts x n_gates x 8 x 8 c128
+ *   target, out_costs, tol, stats: as for qf_instantiate.
+ * The same sweep order, termination tests, multistart rule, complex64
+ * recheck and final FP64 costs as qf_instantiate; all starts run on the
+ * context stream (stream_groups and stats->timing are ignored).  Needs
+ * 3 <= n <= 14, opt->gate_kinds == NULL and mode AUTO or STREAMING (RESIDENT
+ * gives QF_EUNSUPPORTED).  The caller owns the workspace
+ * (qf_workspace_size3 bytes, 0 for invalid sizes).  Errors as
+ * qf_instantiate. */
+size_t qf_workspace_size3(int n, int n_gates, int n_starts, const qf_options* opt);
+int qf_instantiate3(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                    const void* init_gates, int n_starts, double tol, const qf_options* opt, void* workspace,
+                    size_t ws_bytes, void* out_gates, void* out_all_gates, double* out_costs, qf_stats* stats);
+
+/* The 8 x 8 gate update of Eq. opt_u (beta of Sec. III-A-2) for `count`
+ * environments: u_new[k] = argmax over unitary u of Re Tr(M u),
+ * M = (1 - beta) env[k] + beta u_old[k]^dagger.  env, u_old, u_new: device,
+ * count x 8 x 8 c128 (u_new must not alias env or u_old).  A zero M (largest
+ * entry below 1e-300) keeps u_old; a non-finite M gives NaN.  QF_EINVAL for
+ * count < 1, NULL pointers or beta outside [0, 1]. */
+int qf_optimize_gate3(qf_ctx* ctx, int count, const void* env, const void* u_old, double beta, void* u_new);
+
 /* Batched instantiation of many small independent problems (the partitions
  * of hierarchical synthesis, Sec. II "Partitioning and Resynthesis"), each
  * run as QFactor with its own multistarts in lockstep (Sec. IV-A), all in

@@ -243,6 +243,54 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
                   st.n_rechecks, st.mode_used, st.elapsed_ms, h, tm)
 
 
+def optimize_gate3(env: torch.Tensor, u_old: torch.Tensor, beta: float = 0.0) -> torch.Tensor:
+    """The 8 x 8 gate update (qf_optimize_gate3) for (count, 8, 8) c128 environments."""
+    count = env.shape[0]
+    _c128(env, (count, 8, 8))
+    _c128(u_old, (count, 8, 8))
+    out = torch.empty_like(u_old)
+    ctx = _ctx(env.device)
+    nat.check(nat.load().qf_optimize_gate3(ctx, count, _ptr(env), _ptr(u_old), float(beta), _ptr(out)), ctx)
+    return out
+
+
+def instantiate3(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float = 1e-10,
+                 options: nat.QfOptions | None = None, history_rows: int = 0, **kw) -> Result:
+    """QFactor multistart instantiation of a circuit of three-qubit gates
+    (qf_instantiate3): locs (p, 3), init_gates (S, p, 8, 8) c128."""
+    opt = options if options is not None else default_options()
+    _kinds_keep = _apply_kw(opt, kw)  # noqa: F841
+    N = target.shape[0]
+    n = _n_of(N)
+    locs = np.asarray(locs, np.int32).reshape(-1, 3)
+    S, p = init_gates.shape[0], init_gates.shape[1]
+    _c128(target, (N, N))
+    _c128(init_gates, (S, p, 8, 8))
+    lib = nat.load()
+    need = int(lib.qf_workspace_size3(n, p, S, ctypes.byref(opt)))
+    if need == 0:
+        need = 1  # invalid sizes or options: the library rejects them with its message
+    workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
+    out = torch.empty((p, 8, 8), dtype=torch.complex128, device=target.device)
+    out_all = torch.empty((S, p, 8, 8), dtype=torch.complex128, device=target.device)
+    costs = (ctypes.c_double * S)()
+    st = nat.QfStats()
+    hist = None
+    if history_rows > 0:
+        hist = np.full((history_rows, S), np.nan, dtype=np.float64)
+        st.cost_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st.cost_history_rows = history_rows
+    ctx = _ctx(target.device)
+    rc = lib.qf_instantiate3(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
+                             ctypes.byref(opt), _ptr(workspace), need, _ptr(out), _ptr(out_all), costs,
+                             ctypes.byref(st))
+    if rc not in (nat.QF_OK, nat.QF_ENUMERIC):
+        nat.check(rc, ctx)
+    h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
+    return Result(out, out_all, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.n_resets,
+                  st.n_rechecks, st.mode_used, st.elapsed_ms, h, dict(pass_tcols=st.pass_tcols))
+
+
 @dataclass
 class BatchResult:
     gates: torch.Tensor          # flat: per block, n_starts x p_b x 4 x 4 (every start's final gates)

@@ -1175,6 +1175,283 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
   return QF_OK;
 }
 
+// ------------------------------------------------------- three-qubit gates
+
+struct Layout3 {
+  size_t X = 0, R = 0, gates = 0, uold = 0, costs = 0, trace = 0, frozen = 0, total = 0;
+};
+
+Layout3 make_layout3(int n, int p, int S, int precision) {
+  Layout3 L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t N = (size_t)1 << n;
+  L.X = take((size_t)S * N * N * elem_bytes(precision));
+  if (precision == QF_C64) L.R = take((size_t)S * N * N * 16);
+  L.gates = take((size_t)S * p * 64 * 16);
+  L.uold = take((size_t)S * 64 * 16);
+  L.costs = take((size_t)S * 8);
+  L.trace = take((size_t)S * 16);
+  L.frozen = take((size_t)S * 4);
+  L.total = off;
+  return L;
+}
+
+int validate_problem3(qf_ctx* ctx, int n, int p, const int32_t* locs, int S, const qf_options& o) {
+  if (n < 3 || n > 14) return fail(ctx, QF_EINVAL, "n=%d outside [3, 14] for three-qubit gates", n);
+  if (p < 1) return fail(ctx, QF_EINVAL, "n_gates must be >= 1");
+  if (!locs) return fail(ctx, QF_EINVAL, "locations is NULL");
+  for (int g = 0; g < p; ++g) {
+    const int32_t* l = locs + 3 * g;
+    const bool ok = l[0] >= 0 && l[0] < n && l[1] >= 0 && l[1] < n && l[2] >= 0 && l[2] < n && l[0] != l[1] &&
+                    l[0] != l[2] && l[1] != l[2];
+    if (!ok) return fail(ctx, QF_EINVAL, "gate %d: location (%d, %d, %d) invalid for n=%d", g, l[0], l[1], l[2], n);
+  }
+  if (S < 1) return fail(ctx, QF_EINVAL, "n_starts must be >= 1");
+  if (o.gate_kinds) return fail(ctx, QF_EINVAL, "gate_kinds must be NULL for three-qubit gates");
+  if (o.mode == QF_MODE_RESIDENT) return fail(ctx, QF_EUNSUPPORTED, "three-qubit gates run in streaming mode only");
+  return QF_OK;
+}
+
+// Alg. 1 on 8 x 8 gates, all starts on the context stream (same termination,
+// multistart rule, complex64 recheck and final FP64 costs as run_streaming).
+int run_streaming3(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, int S, double tol,
+                   const qf_options& o, unsigned char* ws, const Layout3& L, qf_stats* stats, RunOut& out) {
+  hipStream_t st = ctx->stream;
+  const int prec = o.precision;
+  void* X = ws + L.X;
+  void* R = prec == QF_C64 ? (void*)(ws + L.R) : nullptr;
+  double* gates = reinterpret_cast<double*>(ws + L.gates);
+  double* uold = reinterpret_cast<double*>(ws + L.uold);
+  double* costs = reinterpret_cast<double*>(ws + L.costs);
+  double* trace = reinterpret_cast<double*>(ws + L.trace);
+  int32_t* frozen = reinterpret_cast<int32_t*>(ws + L.frozen);
+  const int64_t gstride = (int64_t)p * 64;
+  const size_t N = (size_t)1 << n;
+  std::vector<Pass8Geom> geo(p);
+  for (int g = 0; g < p; ++g) geo[g] = make_pass8_geom(n, locs + 3 * g);
+  QF_HIP(ctx, launch_fill_i32(st, frozen, 0, (uint32_t)S));
+
+  auto build = [&](int pr, void* dst) -> int {
+    QF_HIP(ctx, launch_build_init(st, pr, V, dst, n, S));
+    for (int g = 0; g < p; ++g)
+      QF_HIP(ctx, launch_pass8(st, pr, dst, S, geo[g], Operand{gates + 2 * 64 * (int64_t)g, gstride, 0},
+                               Operand{nullptr, 0, 0}));
+    return QF_OK;
+  };
+  auto fp64_costs = [&](std::vector<double>& c) -> int {
+    void* dst = prec == QF_C64 ? R : X;
+    int rc = build(QF_C128, dst);
+    if (rc) return rc;
+    QF_HIP(ctx, launch_cost(st, QF_C128, dst, n, S, costs, trace));
+    return read_costs(ctx, costs, S, c);
+  };
+  Env8Args ea{};
+  ea.S = S;
+  ea.do_update = 1;
+  ea.beta = o.beta;
+  ea.gates = gates;
+  ea.gstride = gstride;
+  ea.uold = uold;
+  ea.frozen = frozen;
+  auto update = [&](int g, int half) -> int {
+    ea.half = half;
+    ea.gidx = g;
+    QF_HIP(ctx, launch_env8(st, prec, X, geo[g], ea));
+    const Operand gnew{gates + 2 * 64 * (int64_t)g, gstride, 0};
+    const Operand gold{uold, 64, 1};
+    if (half == 0)
+      QF_HIP(ctx, launch_pass8(st, prec, X, S, geo[g], gold, gnew));
+    else
+      QF_HIP(ctx, launch_pass8(st, prec, X, S, geo[g], gnew, gold));
+    return QF_OK;
+  };
+
+  int rc = build(prec, X);
+  if (rc) return rc;
+  QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
+  std::vector<double> c;
+  if ((rc = read_costs(ctx, costs, S, c))) return rc;
+  if (prec == QF_C64) {
+    bool any = false;
+    for (int s = 0; s < S; ++s) any = any || (c[s] < o.recheck_below);
+    if (any) {
+      std::vector<double> c64v = c;
+      if ((rc = fp64_costs(c))) return rc;
+      ++out.rechecks;
+      for (int s = 0; s < S; ++s)
+        if (!(c64v[s] < o.recheck_below)) c[s] = c64v[s];
+    }
+  }
+  out.flags.assign(S, 0);
+  for (int s = 0; s < S; ++s)
+    if (!std::isfinite(c[s])) {
+      c[s] = INFINITY;
+      out.flags[s] = kFlagNumeric | kFlagPlateau;
+    }
+  std::vector<std::vector<double>> hist;
+  hist.push_back(c);
+  auto record = [&](int i, const std::vector<double>& cv) {
+    if (stats && stats->cost_history && i < stats->cost_history_rows)
+      for (int s = 0; s < S; ++s) stats->cost_history[(size_t)i * S + s] = cv[s];
+  };
+  record(0, c);
+  std::vector<int32_t> frozen_host(S, 0);
+  auto sync_frozen = [&]() -> int {
+    bool changed = false;
+    for (int s = 0; s < S; ++s) {
+      const int32_t fz = (out.flags[s] & kFlagNumeric) ? 1 : 0;
+      changed = changed || (fz != frozen_host[s]);
+      frozen_host[s] = fz;
+    }
+    if (changed)
+      QF_HIP(ctx, hipMemcpyAsync(frozen, frozen_host.data(), (size_t)S * 4, hipMemcpyHostToDevice, st));
+    return QF_OK;
+  };
+  if ((rc = sync_frozen())) return rc;
+
+  int32_t i = 0;
+  int32_t decision = o.max_iter <= 0 ? kStopMaxIter : kContinue;
+  while (decision == kContinue) {
+    ++i;
+    for (int g = p - 1; g >= 0; --g)
+      if ((rc = update(g, 0))) return rc;
+    for (int g = 0; g < p; ++g)
+      if ((rc = update(g, 1))) return rc;
+    if (o.reset_iter > 0 && i % o.reset_iter == 0) {
+      if ((rc = build(prec, X))) return rc;
+      ++out.resets;
+    }
+    QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
+    if ((rc = read_costs(ctx, costs, S, c))) return rc;
+    if (prec == QF_C64) {
+      bool need = false;
+      for (int s = 0; s < S; ++s) need = need || (!(out.flags[s] & kFlagNumeric) && c[s] < o.recheck_below);
+      if (need) {
+        std::vector<double> c64v = c, c64d;
+        if ((rc = fp64_costs(c64d))) return rc;
+        ++out.rechecks;
+        for (int s = 0; s < S; ++s)
+          if (c64v[s] < o.recheck_below) c[s] = c64d[s];
+        if ((rc = cast_to_c64(ctx, R, X, (size_t)S * N * N))) return rc;  // refresh the builder
+      }
+    }
+    const int32_t Lh = o.long_diff_count;
+    for (int s = 0; s < S; ++s) {
+      const double ci = std::isfinite(c[s]) ? c[s] : INFINITY;
+      if (out.flags[s] & kFlagNumeric) {
+        c[s] = INFINITY;
+        continue;
+      }
+      const double cprev = hist[i - 1][s];
+      const double cback = (Lh > 0 && i >= Lh) ? hist[i - Lh][s] : 0.0;
+      out.flags[s] = start_flags_after_sweep(o, tol, i, out.flags[s], ci, cprev, cback);
+      c[s] = (out.flags[s] & kFlagNumeric) ? INFINITY : ci;
+    }
+    hist.push_back(c);
+    record(i, c);
+    if ((rc = sync_frozen())) return rc;
+    decision = job_decision(o, i, out.flags.data(), S);
+  }
+  out.sweeps = i;
+  out.decision = decision;
+  return fp64_costs(out.final_costs);
+}
+
+size_t qf_workspace_size3(int n, int n_gates, int n_starts, const qf_options* opt) {
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (n < 3 || n > 14 || n_gates < 1 || n_starts < 1) return 0;
+  if (validate_options(nullptr, o) != QF_OK) return 0;
+  return make_layout3(n, n_gates, n_starts, o.precision).total;
+}
+
+int qf_instantiate3(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                    const void* init_gates, int n_starts, double tol, const qf_options* opt, void* workspace,
+                    size_t ws_bytes, void* out_gates, void* out_all_gates, double* out_costs, qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  qf_options o;
+  if (opt)
+    o = *opt;
+  else
+    qf_options_default(&o);
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, QF_EINVAL, "tol must be finite and > 0");
+  o.dist_tol = tol;
+  int rc = validate_options(ctx, o);
+  if (rc) return rc;
+  if ((rc = validate_problem3(ctx, n, n_gates, locations, n_starts, o))) return rc;
+  if (!target || !init_gates || !out_gates || !out_costs) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (stats && stats->cost_history && stats->cost_history_rows < 0)
+    return fail(ctx, QF_EINVAL, "cost_history_rows must be >= 0");
+  const Layout3 L = make_layout3(n, n_gates, n_starts, o.precision);
+  if (!workspace || ws_bytes < L.total)
+    return fail(ctx, QF_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  DeviceGuard dg(ctx->device);
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  hipStream_t st = ctx->stream;
+  const size_t gate_bytes = (size_t)n_starts * n_gates * 1024;
+  QF_HIP(ctx, hipMemcpyAsync(ws + L.gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  if (stats) {
+    stats->pass_launches = stats->env_launches = 0;
+    stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
+  }
+  RunOut out;
+  if ((rc = run_streaming3(ctx, n, target, n_gates, locations, n_starts, tol, o, ws, L, stats, out))) return rc;
+  int best = 0;
+  bool all_numeric = true;
+  for (int s = 0; s < n_starts; ++s) {
+    double cs = out.final_costs[s];
+    if (!std::isfinite(cs) || (out.flags[s] & kFlagNumeric)) cs = INFINITY;
+    out.final_costs[s] = cs;
+    out_costs[s] = cs;
+    all_numeric = all_numeric && !std::isfinite(cs);
+    if (cs < out.final_costs[best]) best = s;
+  }
+  QF_HIP(ctx, hipMemcpyAsync(out_gates, ws + L.gates + (size_t)best * n_gates * 1024, (size_t)n_gates * 1024,
+                             hipMemcpyDeviceToDevice, st));
+  if (out_all_gates) QF_HIP(ctx, hipMemcpyAsync(out_all_gates, ws + L.gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  QF_HIP(ctx, hipStreamSynchronize(st));
+  int status = QF_MAX_ITER;
+  if (all_numeric)
+    status = QF_NUMERIC;
+  else if (out.final_costs[best] < tol)
+    status = QF_CONVERGED;
+  else if (out.decision == kStopPlateau)
+    status = QF_PLATEAU;
+  if (stats) {
+    stats->sweeps = out.sweeps;
+    stats->best_start = best;
+    stats->status = status;
+    stats->n_resets = out.resets;
+    stats->n_rechecks = out.rechecks;
+    stats->mode_used = QF_MODE_STREAMING;
+    stats->pass_tcols = 0;
+    stats->best_cost = out.final_costs[best];
+    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (all_numeric) return fail(ctx, QF_ENUMERIC, "every start produced non-finite values");
+  return QF_OK;
+}
+
+int qf_optimize_gate3(qf_ctx* ctx, int count, const void* env, const void* u_old, double beta, void* u_new) {
+  if (!ctx) return QF_EINVAL;
+  if (count < 1) return fail(ctx, QF_EINVAL, "count must be >= 1");
+  if (!env || !u_old || !u_new) return fail(ctx, QF_EINVAL, "NULL pointer argument");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
+  DeviceGuard dg(ctx->device);
+  QF_HIP(ctx, launch_optimize8(ctx->stream, count, reinterpret_cast<const double*>(env),
+                               reinterpret_cast<const double*>(u_old), beta, reinterpret_cast<double*>(u_new)));
+  return QF_OK;
+}
+
 size_t qf_batch_workspace_size(int n_blocks, const int32_t* block_n, const int32_t* gate_offsets, int n_starts,
                                const qf_options* opt) {
   qf_options o;

@@ -47,6 +47,30 @@ struct Operand {
 hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
                        Operand B);
 
+// Three-qubit gates (qf_k3.hip).  Operands are 8 x 8 c128 per start.
+struct Pass8Geom {
+  uint32_t n, N;
+  uint32_t b[3];             // bit positions of the gate's local bits, most significant first
+  uint32_t s[3];             // the same positions in ascending order
+  uint32_t W, wlog;          // column groups per tile (a power of two <= 32) and its log2
+  uint32_t col_tiles, tiles_per_start;
+};
+Pass8Geom make_pass8_geom(int n, const int32_t loc[3]);
+hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B);
+struct Env8Args {
+  int S, half, do_update;
+  double beta;
+  double* gates;             // per start: gstride complex entries, gate g at 64 g
+  int64_t gstride;
+  int gidx;
+  double* uold;              // S x 64 complex: u_old as used (for the pass)
+  const int32_t* frozen;     // per start, nullptr = none
+  double* env_out;           // S x 64 complex partial traces when do_update == 0
+};
+hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8Geom& g, const Env8Args& a);
+hipError_t launch_optimize8(hipStream_t st, int count, const double* env, const double* uold, double beta,
+                            double* unew);
+
 hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void* X, int n, int S);
 
 // Partial trace over every qubit but (q0, q1), FP64.  Optionally followed by

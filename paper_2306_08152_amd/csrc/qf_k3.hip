@@ -1,0 +1,368 @@
+// Three-qubit gates: the instantiation sweep for circuits whose gates are
+// 8 x 8 unitaries on three qubits (the method is stated for gates of any
+// size, Sec. III; the k = 3 gate-set variant of Sec. III-A-3).
+//
+//   k_pass8      X <- (A (x) I) X (B (x) I) for an 8 x 8 gate: LDS tile of the
+//                eight rows that differ in the gate's bits times the eight
+//                column variants of up to 32 column groups; the left product
+//                runs one column per thread, the right product one row per
+//                thread, both on the tile.
+//   k_env8       P = Tr_rest X (8 x 8, FP64 sums, one workgroup per start),
+//                E = u_old^dagger P or P u_old^dagger, and the FP64 update of
+//                Eq. opt_u on one wavefront (lane 8r + c = entry (r, c)).
+//   k_optimize8  the same update for a batch of given environments.
+#include <hip/hip_runtime.h>
+
+#include "qf_device.h"
+#include "qf_internal.h"
+
+namespace qf {
+
+// Offset of local index i (0..7) for a gate whose local bits, most
+// significant first, sit at bit positions b[0], b[1], b[2] (Q1).
+__device__ __forceinline__ uint32_t local_off8(uint32_t i, const uint32_t b[3]) {
+  return (((i >> 2) & 1u) << b[0]) | (((i >> 1) & 1u) << b[1]) | ((i & 1u) << b[2]);
+}
+// Insert zero bits at the ascending positions s[0] < s[1] < s[2].
+__device__ __forceinline__ uint32_t insert000(uint32_t v, const uint32_t s[3]) {
+  return insert0(insert0(insert0(v, s[0]), s[1]), s[2]);
+}
+
+Pass8Geom make_pass8_geom(int n, const int32_t loc[3]) {
+  Pass8Geom g{};
+  g.n = (uint32_t)n;
+  g.N = 1u << n;
+  for (int t = 0; t < 3; ++t) g.b[t] = (uint32_t)(n - 1 - loc[t]);
+  uint32_t s0 = g.b[0], s1 = g.b[1], s2 = g.b[2], tmp;
+  if (s0 > s1) { tmp = s0; s0 = s1; s1 = tmp; }
+  if (s1 > s2) { tmp = s1; s1 = s2; s2 = tmp; }
+  if (s0 > s1) { tmp = s0; s0 = s1; s1 = tmp; }
+  g.s[0] = s0;
+  g.s[1] = s1;
+  g.s[2] = s2;
+  const uint32_t groups = g.N >> 3;  // column groups (base columns with the gate's bits zero)
+  g.W = groups < 32u ? groups : 32u;
+  g.wlog = 0;
+  while ((1u << g.wlog) < g.W) ++g.wlog;
+  g.col_tiles = groups >> g.wlog;
+  g.tiles_per_start = groups * g.col_tiles;
+  return g;
+}
+
+// ------------------------------------------------------------------ k_pass8
+
+// Grid: S x tiles_per_start workgroups of 256 threads.  Tile entry
+// ((i * 8 + j) * W + w) holds row rb + off(i), column cb_w + off(j); the
+// loads and stores run w fastest, so a wavefront touches W consecutive
+// column groups of one (row, column variant).
+template <typename R, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom g, Operand A, Operand B) {
+  __shared__ cx<R> tile[64 * 32];
+  __shared__ cx<R> As[64], Bs[64];
+  const uint32_t t = threadIdx.x;
+  const uint32_t s = blockIdx.x / g.tiles_per_start;
+  const uint32_t rem = blockIdx.x - s * g.tiles_per_start;
+  const uint32_t rgi = rem / g.col_tiles, cti = rem - rgi * g.col_tiles;
+  const uint32_t rb = insert000(rgi, g.s);
+  const uint32_t W = g.W, wlog = g.wlog, nel = 64u << wlog;
+  cx<R>* Xs = X + (size_t)s * g.N * g.N;
+  if (HA && t < 64) {
+    const cd* src = reinterpret_cast<const cd*>(A.ptr) + (int64_t)s * A.stride;
+    const uint32_t r = t >> 3, c = t & 7u;
+    const cd v = A.dagger ? conj(src[8 * c + r]) : src[8 * r + c];
+    As[t] = cx<R>{(R)v.re, (R)v.im};
+  }
+  if (HB && t >= 64 && t < 128) {
+    const cd* src = reinterpret_cast<const cd*>(B.ptr) + (int64_t)s * B.stride;
+    const uint32_t r = (t - 64) >> 3, c = (t - 64) & 7u;
+    const cd v = B.dagger ? conj(src[8 * c + r]) : src[8 * r + c];
+    Bs[t - 64] = cx<R>{(R)v.re, (R)v.im};
+  }
+  for (uint32_t e = t; e < nel; e += 256u) {
+    const uint32_t w = e & (W - 1u), ij = e >> wlog, i = ij >> 3, j = ij & 7u;
+    const uint32_t cb = insert000((cti << wlog) + w, g.s);
+    tile[e] = Xs[(size_t)(rb + local_off8(i, g.b)) * g.N + cb + local_off8(j, g.b)];
+  }
+  __syncthreads();
+  if (HA && t < (8u << wlog)) {  // one column (variant j of group w): x <- A x
+    const uint32_t j = t >> wlog, w = t & (W - 1u);
+    cx<R> x[8], y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = tile[(((uint32_t)i * 8u + j) << wlog) + w];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cmac(acc, As[8 * i + k], x[k]);
+      y[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tile[(((uint32_t)i * 8u + j) << wlog) + w] = y[i];
+  }
+  __syncthreads();
+  if (HB && t < (8u << wlog)) {  // one row (i of group w): x <- x B
+    const uint32_t i = t >> wlog, w = t & (W - 1u);
+    cx<R> x[8], y[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = tile[((i * 8u + (uint32_t)j) << wlog) + w];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+      for (int l = 0; l < 8; ++l) cmac(acc, x[l], Bs[8 * l + j]);
+      y[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) tile[((i * 8u + (uint32_t)j) << wlog) + w] = y[j];
+  }
+  __syncthreads();
+  for (uint32_t e = t; e < nel; e += 256u) {
+    const uint32_t w = e & (W - 1u), ij = e >> wlog, i = ij >> 3, j = ij & 7u;
+    const uint32_t cb = insert000((cti << wlog) + w, g.s);
+    Xs[(size_t)(rb + local_off8(i, g.b)) * g.N + cb + local_off8(j, g.b)] = tile[e];
+  }
+}
+
+template <typename R>
+static hipError_t launch_pass8_t(hipStream_t st, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
+  const dim3 grid((uint32_t)S * g.tiles_per_start), block(256);
+  cx<R>* x = reinterpret_cast<cx<R>*>(X);
+  if (A.ptr && B.ptr)
+    hipLaunchKernelGGL((k_pass8<R, true, true>), grid, block, 0, st, x, g, A, B);
+  else if (A.ptr)
+    hipLaunchKernelGGL((k_pass8<R, true, false>), grid, block, 0, st, x, g, A, B);
+  else if (B.ptr)
+    hipLaunchKernelGGL((k_pass8<R, false, true>), grid, block, 0, st, x, g, A, B);
+  else
+    return hipSuccess;
+  return hipGetLastError();
+}
+
+hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
+  if (precision == QF_C64) return launch_pass8_t<float>(st, X, S, g, A, B);
+  return launch_pass8_t<double>(st, X, S, g, A, B);
+}
+
+// ------------------------------------------------- FP64 update, 8 x 8 (oct form)
+//
+// The one-sided Jacobi step of the 4 x 4 forms (jacobi_params / jacobi_apply,
+// rank tolerance kRankTol2) on 64 lanes of a wavefront: lane 8r + c holds
+// entry (r, c) of M and of the accumulated rotation Y.  A sweep is seven
+// rounds; in round K column c pairs with c ^ K (every pair once per sweep,
+// four disjoint pairs per round, all at once on different lanes).  Column sums
+// are a butterfly over the three row bits of the lane index, so every lane of
+// a column gets bitwise the same sum.
+
+__device__ __forceinline__ cd shfl_xor_cd(cd v, int m) {
+  return mk(__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64));
+}
+__device__ __forceinline__ cd shfl_cd(cd v, int src) { return mk(__shfl(v.re, src, 64), __shfl(v.im, src, 64)); }
+__device__ __forceinline__ double oct_colsum(double v) {
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 16, 64);
+  return v + __shfl_xor(v, 32, 64);
+}
+__device__ __forceinline__ double oct_rowmax(double v) {
+  v = fmax(v, __shfl_xor(v, 1, 64));
+  v = fmax(v, __shfl_xor(v, 2, 64));
+  return fmax(v, __shfl_xor(v, 4, 64));
+}
+__device__ __forceinline__ double oct_wavemax(double v) {
+  v = oct_rowmax(v);
+  v = fmax(v, __shfl_xor(v, 8, 64));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  return fmax(v, __shfl_xor(v, 32, 64));
+}
+
+__device__ __forceinline__ double oct_round(cd& m, cd& y, int c, int K) {
+  const bool pside = c < (c ^ K);
+  const cd mo = shfl_xor_cd(m, K);
+  const cd yo = shfl_xor_cd(y, K);
+  const cd mP = sel(pside, m, mo), mQ = sel(pside, mo, m);
+  const double na = oct_colsum(nrm2x(m));
+  const cd gl = cjmulx(mP, mQ);
+  const cd g = mk(oct_colsum(gl.re), oct_colsum(gl.im));
+  const double nb = __shfl_xor(na, K, 64);
+  JacobiRot j;
+  if (!jacobi_params(pside ? na : nb, pside ? nb : na, g, j)) return 0.0;
+  cd np, nq;
+  jacobi_apply(j, mP, mQ, np, nq);
+  m = sel(pside, np, nq);
+  jacobi_apply(j, sel(pside, y, yo), sel(pside, yo, y), np, nq);
+  y = sel(pside, np, nq);
+  return j.large;
+}
+
+// m: entry (r, c) of M (overwritten); keep: entry (r, c) of the result for a
+// zero M.  Result entry (r, c) of the maximiser of Re Tr(M u); codes as the
+// 4 x 4 forms (0 computed, 1 zero M, 2 non-finite M).  All 64 lanes active.
+__device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew) {
+  double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
+  const double bad = oct_wavemax((finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0);
+  if (bad != 0.0) {
+    const double nan = __builtin_nan("");
+    unew = mk(nan, nan);
+    return 2;
+  }
+  if (!(amax >= 1e-300)) {
+    unew = keep;
+    return 1;
+  }
+  m = scale(m, rcp_nr(amax));
+  cd y = mk(c == r ? 1.0 : 0.0, 0.0);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double rel = 0.0;
+    for (int K = 1; K < 8; ++K) rel = fmax(rel, oct_round(m, y, c, K));
+    if (!(oct_rowmax(rel) > 0.0)) break;
+  }
+  const double sig2 = oct_colsum(nrm2x(m));
+  const double smax2 = oct_rowmax(sig2);
+  const bool acc = sig2 > smax2 * kRankTol2;
+  const int row0 = (int)(__lane_id() & ~7u);  // lane of (r, 0)
+  double accv[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) accv[j] = __shfl(acc ? 1.0 : 0.0, row0 + j, 64);
+  cd x = sel(acc, scale(m, rsqrt_nr(acc ? sig2 : 1.0)), mk(0.0, 0.0));  // X[r][c]
+  bool singular = false;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) singular = singular || accv[j] == 0.0;
+  if (singular) {
+    // Gram-Schmidt of e_0..e_7 against the accepted columns; lane (r, c)
+    // computes component r, alike for every c.  A complement of dimension
+    // >= 1 leaves some e_k with squared norm >= 1/8 after projection.
+    for (int j = 0; j < 8; ++j) {
+      if (accv[j] == 0.0) {
+        bool found = false;
+        cd xj = mk(0.0, 0.0);
+        for (int k = 0; k < 8; ++k) {
+          cd v = mk(r == k ? 1.0 : 0.0, 0.0);
+          for (int jj = 0; jj < 8; ++jj) {
+            if (accv[jj] != 0.0) {
+              const cd xjj = shfl_cd(x, row0 + jj);
+              const cd pr = cjmulx(xjj, v);
+              const cd d = mk(oct_colsum(pr.re), oct_colsum(pr.im));
+              v = v - mulx(xjj, d);
+            }
+          }
+          const double nv = oct_colsum(nrm2x(v));
+          const bool take = !found && nv >= 0.125;
+          if (take) xj = scale(v, rsqrt_nr(nv));
+          found = found || take;
+        }
+        if (c == j) x = xj;
+        accv[j] = 1.0;
+      }
+    }
+  }
+  // u_new[r][c] = sum_j Y[r][j] conj(X[c][j])
+  const int base = (int)(__lane_id() & ~63u);
+  cd a = mk(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const cd yrj = shfl_cd(y, row0 + j);
+    const cd xcj = shfl_cd(x, base + 8 * c + j);
+    cmac(a, yrj, conj(xcj));
+  }
+  unew = a;
+  return 0;
+}
+
+// Lane (r, c) passes E[r][c], u_old[c][r], u_old[r][c]; receives u_new[r][c]
+// for M = (1 - beta) E + beta u_old^dagger (Eq. opt_u; beta of Sec. III-A-2).
+__device__ inline void optimize_gate_f64_oct(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew) {
+  cd m = axpbyx(e, 1.0 - beta, conj(uold_cr), beta);
+  nearest_unitary_f64_oct(m, uold_rc, r, c, unew);
+}
+
+// ------------------------------------------------------------------ k_env8
+
+// Grid: one 256-thread workgroup per start (n <= 14).  Thread t sums entry
+// (i, j) = t % 64 over the rests congruent to t / 64 mod 4 (eight loads in
+// flight); the four partial sums of an entry are added in a fixed order.
+template <typename R>
+__global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8Geom g, Env8Args a) {
+  __shared__ cd red[256];
+  __shared__ cd P[64], U[64];
+  __shared__ int frz;
+  const uint32_t t = threadIdx.x;
+  const uint32_t s = blockIdx.x;
+  const cd* gsrc = reinterpret_cast<const cd*>(a.gates) + (int64_t)s * a.gstride + 64 * (int64_t)a.gidx;
+  if (a.do_update && t < 64) U[t] = gsrc[t];
+  if (t == 64) frz = (a.do_update && a.frozen && a.frozen[s]) ? 1 : 0;
+  const uint32_t ij = t & 63u, i = ij >> 3, j = ij & 7u, rl = t >> 6;
+  const uint32_t ro = local_off8(i, g.b), co = local_off8(j, g.b);
+  const uint32_t nrest = g.N >> 3;
+  const cx<R>* Xs = X + (size_t)s * g.N * g.N;
+  cd acc = mk(0.0, 0.0);
+  for (uint32_t r0 = rl; r0 < nrest; r0 += 32u) {
+    cx<R> v[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint32_t rest = r0 + 4u * k;
+      v[k] = mk<R>(0, 0);
+      if (rest < nrest) {
+        const uint32_t base = insert000(rest, g.s);
+        v[k] = Xs[(size_t)(base + ro) * g.N + base + co];
+      }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) acc = acc + mk((double)v[k].re, (double)v[k].im);
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < 64) P[t] = (red[t] + red[t + 64]) + (red[t + 128] + red[t + 192]);
+  __syncthreads();
+  if (t >= 64) return;
+  const int r = (int)(t >> 3), c = (int)(t & 7u);
+  if (!a.do_update) {
+    reinterpret_cast<cd*>(a.env_out)[64 * (size_t)s + t] = P[t];
+    return;
+  }
+  // E = u_old^dagger P (first half) or P u_old^dagger (second half)
+  cd e = mk(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (a.half == 0)
+      cmac(e, conj(U[8 * k + r]), P[8 * k + c]);
+    else
+      cmac(e, P[8 * r + k], conj(U[8 * c + k]));
+  }
+  const cd urc = U[8 * r + c];
+  cd un = urc;
+  if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un);
+  reinterpret_cast<cd*>(a.uold)[64 * (size_t)s + t] = urc;
+  reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 64 * (int64_t)a.gidx + t] = un;
+}
+
+hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8Geom& g, const Env8Args& a) {
+  if (g.n > 14) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)a.S), block(256);
+  if (precision == QF_C64)
+    hipLaunchKernelGGL(k_env8<float>, grid, block, 0, st, reinterpret_cast<const cf*>(X), g, a);
+  else
+    hipLaunchKernelGGL(k_env8<double>, grid, block, 0, st, reinterpret_cast<const cd*>(X), g, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_optimize8
+
+// One wavefront per environment, lane 8r + c = entry (r, c).
+__global__ __launch_bounds__(64) void k_optimize8(const cd* __restrict__ env, const cd* __restrict__ uold, double beta,
+                                                  cd* __restrict__ unew) {
+  const size_t s = blockIdx.x;
+  const int t = (int)threadIdx.x, r = t >> 3, c = t & 7;
+  const cd* u = uold + 64 * s;
+  cd un;
+  optimize_gate_f64_oct(env[64 * s + t], u[8 * c + r], u[8 * r + c], r, c, beta, un);
+  unew[64 * s + t] = un;
+}
+
+hipError_t launch_optimize8(hipStream_t st, int count, const double* env, const double* uold, double beta,
+                            double* unew) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_optimize8, dim3((uint32_t)count), dim3(64), 0, st, reinterpret_cast<const cd*>(env),
+                     reinterpret_cast<const cd*>(uold), beta, reinterpret_cast<cd*>(unew));
+  return hipGetLastError();
+}
+
+}  // namespace qf
