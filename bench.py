@@ -66,11 +66,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion", "u3cx"], default=None,
+    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion", "u3cx", "k3"], default=None,
                     help="copy: only a plain device copy of known size (traffic-counter calibration); "
                          "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
                          "and L-BFGS workload; deletion: only the gate-deletion sweep; u3cx: only the U3 + CNOT "
-                         "instantiations")
+                         "instantiations; k3: only the three-qubit-gate workloads")
     return ap.parse_args()
 
 
@@ -225,6 +225,40 @@ def u3cx_workload(qf, torch) -> dict:
     return out
 
 
+def k3_workload(qf, torch) -> dict:
+    """Three-qubit gates: n = 10 brick-wall of 8 x 8 gates (6 layers, 16
+    gates), 8 starts, 5 sweeps with the plateau tests off, both precisions
+    (start-sweeps/s and the time of one gate update: environment + pass);
+    then a reachable n = 6 target (6 gates, 4 starts) to tol 1e-8."""
+    import qfinputs as I
+    n, S, K = 10, 8, 5
+    pr = I.k3_problem(38, n, 6, S, build_target=False)
+    rng = np.random.default_rng(3800)
+    V = torch.from_numpy(I.haar_unitary(rng, 1 << n)).to("cuda")
+    g = torch.from_numpy(pr.init_gates).to("cuda")
+    kw = dict(tol=1e-300, diff_tol_r=0.0, long_diff_count=0)
+    out = {}
+    for prec, tag in ((1, "c64"), (0, "c128")):
+        qf.instantiate3(V, pr.locs, g, max_iter=1, precision=prec, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qf.instantiate3(V, pr.locs, g, max_iter=K, precision=prec, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"k3_n10_p{pr.n_gates}_s{S}_{tag}_start_sweeps_per_s"] = round(S * K / dt, 2)
+        out[f"k3_n10_p{pr.n_gates}_s{S}_{tag}_us_per_gate_update"] = round(1e6 * dt / (K * 2 * pr.n_gates), 1)
+    small = I.k3_problem(39, 6, 4, 4)
+    Vs, gs = torch.from_numpy(small.target).to("cuda"), torch.from_numpy(small.init_gates).to("cuda")
+    qf.instantiate3(Vs, small.locs, gs, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = qf.instantiate3(Vs, small.locs, gs, tol=1e-8)
+    torch.cuda.synchronize()
+    out["k3_n6_p6_s4_c128"] = {"seconds": round(time.perf_counter() - t0, 4), "sweeps": r.sweeps,
+                               "status": r.status, "cost": float(r.costs[r.best_start])}
+    return out
+
+
 def deletion_workload(qf, torch) -> dict:
     """Gate-deletion sweep (re-synthesis workflow): n = 5, a 24-gate chain
     whose first 10 gates are identities, 4 starts per attempt, complex64."""
@@ -287,6 +321,9 @@ def main():
         return
     if args.probe == "u3cx":
         print(json.dumps(u3cx_workload(qf, torch)), flush=True)
+        return
+    if args.probe == "k3":
+        print(json.dumps(k3_workload(qf, torch)), flush=True)
         return
     if args.probe == "deletion":
         print(json.dumps(deletion_workload(qf, torch)), flush=True)
@@ -391,6 +428,7 @@ def main():
         extra.update(gradient_workload(qf, torch))
         extra.update(deletion_workload(qf, torch))
         extra.update(u3cx_workload(qf, torch))
+        extra.update(k3_workload(qf, torch))
         out["extra"] = extra
 
     if not args.no_cpu:
