@@ -130,14 +130,17 @@ typedef struct {
   int32_t precision;  /* qf_precision */
   int32_t mode;       /* qf_mode */
   double recheck_below;
-  int32_t stream_groups; /* streaming mode: starts are split into this many
-                            groups whose sweeps run on separate streams,
-                            staggered so one group's environment + SVD step
-                            runs under another's pass; group 0 runs on the
-                            caller's stream (qf_set_stream), the others on
-                            the library's own (0 = automatic: 4, the
-                            device's 4 hardware queues; at most 4 and at most
-                            n_starts) */
+  int32_t stream_groups; /* streaming mode: how the environment + SVD step
+                            of some starts runs under the pass of others.
+                            0 = automatic: four groups in two pairs, each
+                            pair on one stream (the caller's, qf_set_stream,
+                            and one of the library's), every launch carrying
+                            one group's environment step beside the other
+                            group's pass (two groups on the caller's stream
+                            for 2-3 starts; one group for one start or n >=
+                            15).  1..4 = that many groups on separate
+                            streams (group 0 on the caller's), staggered;
+                            at most n_starts groups */
   const int32_t* gate_kinds; /* host, one qf_gate_kind per gate (for
                                 qf_instantiate_batch: per gate of the whole
                                 batch); NULL = every gate QF_KIND_U4 */

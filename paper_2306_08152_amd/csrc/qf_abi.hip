@@ -432,7 +432,14 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   int G = o.stream_groups > 0 ? o.stream_groups : kMaxGroups;
   G = std::min(std::min(G, kMaxGroups), S);
   if (stats && stats->timing) G = 1;
-  if (G > 1) {
+  // Default schedule: two groups on the caller's stream, each launch carrying
+  // one group's environment step beside the other group's pass (k_fused).
+  const bool fused = o.stream_groups == 0 && !(stats && stats->timing) && S >= 2 && env_workgroups(n) == 1;
+  constexpr int kFusedPairs = 2;  // pairs of groups, one stream each
+  static_assert(kFusedPairs >= 1 && kFusedPairs <= kMaxGroups, "one stream per pair: the caller's and kMaxGroups - 1 own");
+  const int pairs = fused ? std::min(kFusedPairs, S / 2) : 0;
+  if (fused) G = 2 * pairs;
+  if ((G > 1 && !fused) || pairs > 1) {
     int rc0 = ensure_aux_streams(ctx);
     if (rc0) return rc0;
   }
@@ -442,13 +449,13 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     void* X = nullptr;
     EnvArgs ea{};
   };
-  Group grp[kMaxGroups];
+  Group grp[2 * kMaxGroups];
   const uint32_t nwg = env_workgroups(n);
   for (int gi = 0; gi < G; ++gi) {
     Group& q = grp[gi];
     q.s0 = gi * S / G;
     q.ns = (gi + 1) * S / G - q.s0;
-    q.st = gi == 0 ? st : ctx->aux[gi - 1];
+    q.st = fused ? (gi < 2 ? st : ctx->aux[gi / 2 - 1]) : (gi == 0 ? st : ctx->aux[gi - 1]);
     q.X = reinterpret_cast<unsigned char*>(X) + (size_t)q.s0 * N * N * elem_bytes(prec);
     EnvArgs& ea = q.ea;
     ea.n = n;
@@ -531,7 +538,114 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     }
     return QF_OK;
   };
-  auto sweep = [&]() -> int { return sweep_on(st); };
+  // Fused schedule: both groups run the same sequence of steps (an
+  // environment step unless the gate is fixed, then a pass); group 1 trails
+  // group 0 by one step, so each launch pairs one group's environment with
+  // the other's pass.  Steps that do not pair (two passes, a pass form
+  // without a fused kernel) are launched alone, in order.
+  struct Step {
+    int g, half, env;
+  };
+  std::vector<Step> steps;
+  if (fused) {
+    for (int g = p - 1; g >= 0; --g) {
+      const bool fx = o.gate_kinds && o.gate_kinds[g] == QF_KIND_FIXED;
+      if (!fx) steps.push_back({g, 0, 1});
+      steps.push_back({g, 0, 0});
+    }
+    for (int g = 0; g < p; ++g) {
+      const bool fx = o.gate_kinds && o.gate_kinds[g] == QF_KIND_FIXED;
+      if (!fx) steps.push_back({g, 1, 1});
+      steps.push_back({g, 1, 0});
+    }
+  }
+  auto prep_env = [&](Group& q, const Step& k) -> EnvArgs& {
+    EnvArgs& ea = q.ea;
+    ea.kind = o.gate_kinds ? o.gate_kinds[k.g] : QF_KIND_U4;
+    ea.q0 = locs[2 * k.g];
+    ea.q1 = locs[2 * k.g + 1];
+    ea.half = k.half;
+    ea.gidx = k.g;
+    return ea;
+  };
+  auto pass_ops = [&](Group& q, const Step& k, Operand& A, Operand& B) {
+    const bool fx = o.gate_kinds && o.gate_kinds[k.g] == QF_KIND_FIXED;
+    const Operand gnew{q.ea.gates + 2 * 16 * (int64_t)k.g, gstride, 0};
+    const Operand gold = fx ? Operand{q.ea.gates + 2 * 16 * (int64_t)k.g, gstride, 1} : Operand{q.ea.uold, 16, 1};
+    A = k.half == 0 ? gold : gnew;
+    B = k.half == 0 ? gnew : gold;
+  };
+  auto run_alone = [&](Group& q, const Step& k) -> int {
+    if (k.env) {
+      QF_HIP(ctx, launch_env(q.st, prec, q.X, prep_env(q, k)));
+    } else {
+      Operand A, B;
+      pass_ops(q, k, A, B);
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[k.g], A, B));
+    }
+    return QF_OK;
+  };
+  // One pair of groups (q0 leading, q1 trailing by a step) on q0's stream;
+  // advance() enqueues one launch of the pair and returns 1 when done.
+  struct PairState {
+    size_t i0 = 0, i1 = 0;
+  };
+  auto advance = [&](Group& q0, Group& q1, PairState& ps, int& rc1) -> bool {
+    const size_t ns = steps.size();
+    if (ps.i0 >= ns && ps.i1 >= ns) return true;
+    const Step* a = ps.i0 < ns ? &steps[ps.i0] : nullptr;
+    const Step* b = (ps.i1 < ns && ps.i1 < ps.i0) ? &steps[ps.i1] : nullptr;
+    if (a && b && a->env != b->env) {
+      Group& qe = a->env ? q0 : q1;
+      Group& qp = a->env ? q1 : q0;
+      const Step& ke = a->env ? *a : *b;
+      const Step& kp = a->env ? *b : *a;
+      if (fused_supported(prec, n, geo[kp.g])) {
+        Operand A, B;
+        pass_ops(qp, kp, A, B);
+        const hipError_t e = launch_fused(q0.st, prec, qe.X, prep_env(qe, ke), qp.X, qp.ns, geo[kp.g], A, B);
+        if (e != hipSuccess) {
+          rc1 = fail(ctx, QF_EHIP, "fused launch: %s", hipGetErrorString(e));
+          return true;
+        }
+        ++ps.i0;
+        ++ps.i1;
+        return false;
+      }
+    }
+    if (b && (!a || ps.i1 + 1 < ps.i0 || a->env == b->env)) {
+      rc1 = run_alone(q1, *b);
+      ++ps.i1;
+    } else {
+      rc1 = run_alone(q0, *a);
+      ++ps.i0;
+    }
+    return rc1 != QF_OK;
+  };
+  auto sweep_fused = [&]() -> int {
+    int rc1 = QF_OK;
+    if (pairs > 1) {
+      QF_HIP(ctx, hipEventRecord(ctx->fork, st));
+      for (int k = 1; k < pairs; ++k) QF_HIP(ctx, hipStreamWaitEvent(ctx->aux[k - 1], ctx->fork, 0));
+    }
+    PairState ps[kFusedPairs];
+    bool done[kFusedPairs] = {};
+    for (int k = pairs; k < kFusedPairs; ++k) done[k] = true;
+    for (bool all = false; !all;) {  // the pairs' launches are enqueued in turn
+      all = true;
+      for (int k = 0; k < pairs; ++k) {
+        if (!done[k]) done[k] = advance(grp[2 * k], grp[2 * k + 1], ps[k], rc1);
+        if (rc1) return rc1;
+        all = all && done[k];
+      }
+    }
+    for (int k = 1; k < pairs; ++k) {
+      QF_HIP(ctx, hipEventRecord(ctx->join[k], ctx->aux[k - 1]));
+      QF_HIP(ctx, hipStreamWaitEvent(st, ctx->join[k], 0));
+    }
+    return QF_OK;
+  };
+  auto sweep = [&]() -> int { return fused ? sweep_fused() : sweep_on(st); };
   // FP64 costs of the current gates from a fresh complex128 builder (into
   // R for complex64, into X itself for complex128).
   auto fp64_costs = [&](std::vector<double>& c) -> int {

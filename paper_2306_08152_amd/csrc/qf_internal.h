@@ -99,6 +99,11 @@ uint32_t env_workgroups(int n);
 hipError_t launch_fill_i32(hipStream_t st, int32_t* p, int32_t v, uint32_t count);
 int pass_max_tcols(int precision);
 hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a);
+// One launch: the environment step `ea` (update mode) on builders Xe and the
+// two-sided pass of gate geometry g on the Sp builders at Xp (disjoint data).
+bool fused_supported(int precision, int n, const PassGeom& g);
+hipError_t launch_fused(hipStream_t st, int precision, const void* Xe, const EnvArgs& ea, void* Xp, int Sp,
+                        const PassGeom& g, Operand A, Operand B);
 
 hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int S, double* cost,
                        double* trace);

@@ -274,11 +274,11 @@ __device__ __forceinline__ void load_operand_uniform(cx<R> m[16], const Operand&
 }
 
 template <typename R, bool HA, bool HB>
-__global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassGeom g, uint32_t wg_per_start,
-                                                    Operand A, Operand B) {
+__device__ __forceinline__ void pass_block_body(cx<R>* __restrict__ X, const PassGeom& g, uint32_t wg_per_start,
+                                                const Operand& A, const Operand& B, uint32_t wg) {
   const uint32_t N = g.N;
-  const uint32_t s = blockIdx.x / wg_per_start;
-  const uint32_t blk = (blockIdx.x - s * wg_per_start) * 256u + threadIdx.x;
+  const uint32_t s = wg / wg_per_start;
+  const uint32_t blk = (wg - s * wg_per_start) * 256u + threadIdx.x;
   const uint32_t rq = blk >> (g.n - 2), cq = blk & ((N >> 2) - 1u);
   const uint32_t rb = insert00(rq, g.rlo, g.rhi), cb = insert00(cq, g.rlo, g.rhi);
   uint32_t off[4];
@@ -327,6 +327,12 @@ __global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassG
   for (uint32_t i = 0; i < 4; ++i)
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) base[(rb + off[i]) * N + cb + off[j]] = x[4 * i + j];
+}
+
+template <typename R, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass_block(cx<R>* __restrict__ X, PassGeom g, uint32_t wg_per_start,
+                                                    Operand A, Operand B) {
+  pass_block_body<R, HA, HB>(X, g, wg_per_start, A, B, blockIdx.x);
 }
 
 // ------------------------------------------------------------ k_pass_micro
@@ -398,14 +404,14 @@ __device__ __forceinline__ void mt_right(const cf x[2], const cf bc[2][4], cf z[
 }
 
 template <int B0, int B1, bool HA, bool HB>
-__global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t n, uint32_t wg_per_start,
-                                                    Operand A, Operand B) {
+__device__ __forceinline__ void pass_micro_body(cf* __restrict__ X, uint32_t n, uint32_t wg_per_start,
+                                                const Operand& A, const Operand& B, uint32_t wg) {
   static_assert(B0 != B1 && B0 >= 0 && B0 <= 2 && B1 >= 0 && B1 <= 2, "both gate bits among the three lowest");
   static_assert(mt_slot_uniform(B0, B1), "operand slots must not depend on the lane");
   constexpr uint32_t LO = B0 < B1 ? B0 : B1, HI = B0 < B1 ? B1 : B0;
   const uint32_t N = 1u << n;
-  const uint32_t s = blockIdx.x / wg_per_start;
-  const uint32_t w = (blockIdx.x - s * wg_per_start) * 4u + (threadIdx.x >> 6);  // wavefront within the start
+  const uint32_t s = wg / wg_per_start;
+  const uint32_t w = (wg - s * wg_per_start) * 4u + (threadIdx.x >> 6);  // wavefront within the start
   const uint32_t W = N >> 9;                                                      // 512-column spans per row
   const uint32_t rgi = w / W, span = w - rgi * W;
   const uint32_t rb = insert00(rgi, LO, HI);
@@ -476,6 +482,12 @@ __global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t
       *reinterpret_cast<float4*>(base + row * N + 128u * k) =
           make_float4(x[i][k][0].re, x[i][k][0].im, x[i][k][1].re, x[i][k][1].im);
   }
+}
+
+template <int B0, int B1, bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t n, uint32_t wg_per_start,
+                                                    Operand A, Operand B) {
+  pass_micro_body<B0, B1, HA, HB>(X, n, wg_per_start, A, B, blockIdx.x);
 }
 
 template <int B0, int B1, bool HA, bool HB>
@@ -698,13 +710,13 @@ __device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, const cd
 // its 16 partials and the last one to arrive (device-scope counter) adds them
 // in workgroup order.
 template <typename R>
-__global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
+__device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvDev& d, uint32_t wg) {
   __shared__ cd red[kEnvThreads];
   __shared__ cd u_sh[16];
   __shared__ int last, frz;
   const uint32_t t = threadIdx.x;
-  const uint32_t s = blockIdx.x / d.nwg;
-  const uint32_t w = blockIdx.x - s * d.nwg;
+  const uint32_t s = wg / d.nwg;
+  const uint32_t w = wg - s * d.nwg;
   // Gate update: fetch the old gate and the frozen flag now, so their latency
   // hides under the partial trace (the reduction's barriers publish them).
   if (d.a.do_update && t < 16)
@@ -771,12 +783,17 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
   env_finish(d, s, red, u_sh, frz != 0, t);
 }
 
+template <typename R>
+__global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
+  env_body<R>(X, d, blockIdx.x);
+}
+
 uint32_t env_workgroups(int n) {
   const uint32_t nrest = (1u << n) >> 2;
   return (nrest + kEnvRestsPerWG - 1) / kEnvRestsPerWG;
 }
 
-hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a) {
+static EnvDev make_env_dev(const EnvArgs& a) {
   EnvDev d{};
   d.a = a;
   d.N = 1u << a.n;
@@ -786,6 +803,11 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
   d.rlo = d.b0 < d.b1 ? d.b0 : d.b1;
   d.rhi = d.b0 < d.b1 ? d.b1 : d.b0;
   d.nwg = env_workgroups(a.n);
+  return d;
+}
+
+hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a) {
+  const EnvDev d = make_env_dev(a);
   if (d.nwg > 1 && (!a.partials || !a.counters)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)a.S * d.nwg), block(kEnvThreads);
   if (precision == QF_C64)
@@ -793,6 +815,68 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
   else
     hipLaunchKernelGGL(k_env<double>, grid, block, 0, st, reinterpret_cast<const cd*>(X), d);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_fused
+//
+// One launch carrying the environment step (partial trace + FP64 update) of
+// one group of starts and the two-sided pass of another group.  The two touch
+// disjoint builders and gates, so their workgroups run side by side: the
+// latency-bound environment workgroups (first in the grid, so dispatched
+// first) sit under the HBM-bound pass, on one stream and without a
+// cross-stream event.  The pass is the register-direct or the micro-tile
+// form; the environment needs one workgroup per start (n <= 14).
+template <typename R, int FORM, int B0, int B1>
+__global__ __launch_bounds__(256) void k_fused(const cx<R>* Xe, EnvDev ed, uint32_t n_env, cx<R>* Xp, PassGeom g,
+                                               uint32_t wgps, Operand A, Operand B) {
+  if (blockIdx.x < n_env) {
+    env_body<R>(Xe, ed, blockIdx.x);
+    return;
+  }
+  const uint32_t wg = blockIdx.x - n_env;
+  if constexpr (FORM == 1 && sizeof(R) == 4)
+    pass_micro_body<B0, B1, true, true>(Xp, g.n, wgps, A, B, wg);
+  else
+    pass_block_body<R, true, true>(Xp, g, wgps, A, B, wg);
+}
+
+bool fused_supported(int precision, int n, const PassGeom& g) {
+  if (env_workgroups(n) != 1) return false;
+  if (g.micro) return precision == QF_C64;
+  return g.direct != 0;
+}
+
+template <typename R, int FORM, int B0, int B1>
+static hipError_t launch_fused_t(hipStream_t st, const void* Xe, const EnvDev& d, uint32_t n_env, void* Xp, int Sp,
+                                 const PassGeom& g, uint32_t wgps, Operand A, Operand B) {
+  const dim3 grid(n_env + (uint32_t)Sp * wgps), block(256);
+  hipLaunchKernelGGL((k_fused<R, FORM, B0, B1>), grid, block, 0, st, reinterpret_cast<const cx<R>*>(Xe), d, n_env,
+                     reinterpret_cast<cx<R>*>(Xp), g, wgps, A, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(hipStream_t st, int precision, const void* Xe, const EnvArgs& ea, void* Xp, int Sp,
+                        const PassGeom& g, Operand A, Operand B) {
+  const EnvDev d = make_env_dev(ea);
+  if (d.nwg != 1 || !ea.do_update || !A.ptr || !B.ptr) return hipErrorInvalidValue;
+  const uint32_t n_env = (uint32_t)ea.S;
+  if (g.micro) {
+    if (precision != QF_C64 || (reinterpret_cast<uintptr_t>(Xp) & 15u) != 0) return hipErrorInvalidValue;
+    const uint32_t wgps = g.N * g.N / 8192u;
+    switch (g.b0 * 3 + g.b1) {
+      case 0 * 3 + 1: return launch_fused_t<float, 1, 0, 1>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      case 0 * 3 + 2: return launch_fused_t<float, 1, 0, 2>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      case 1 * 3 + 0: return launch_fused_t<float, 1, 1, 0>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      case 1 * 3 + 2: return launch_fused_t<float, 1, 1, 2>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      case 2 * 3 + 0: return launch_fused_t<float, 1, 2, 0>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      case 2 * 3 + 1: return launch_fused_t<float, 1, 2, 1>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (!g.direct) return hipErrorInvalidValue;
+  const uint32_t wgps = g.N * g.N / 4096u;
+  if (precision == QF_C64) return launch_fused_t<float, 0, 0, 0>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
+  return launch_fused_t<double, 0, 0, 0>(st, Xe, d, n_env, Xp, Sp, g, wgps, A, B);
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, uint32_t count) {
