@@ -369,6 +369,33 @@ def test_n12_one_sweep_properties(qf):
     assert np.abs(host(X[0, rows]) - ref).max() < C128_TOL
 
 
+@pytest.mark.parametrize("S", [1, 3, 16])
+def test_stream_schedules_bitwise_equal(qf, S):
+    """The default schedule (group pairs, each launch one group's environment
+    step beside another group's pass) and 1, 2 and 4 staggered groups on
+    separate streams give bitwise the same gates and costs: every start sees
+    the same kernels in the same order (n = 10, complex64, two sweeps)."""
+    pr = I.config3(n_starts=S)
+    kw = dict(tol=1e-300, max_iter=2, precision=1, diff_tol_r=0.0, long_diff_count=0)
+    V, g = dev(pr.target), dev(pr.init_gates)
+    a = qf.instantiate(V, pr.locs, g, **kw)
+    for groups in (1, 2, 4):
+        b = qf.instantiate(V, pr.locs, g, stream_groups=groups, **kw)
+        assert np.array_equal(host(a.all_gates), host(b.all_gates)), groups
+        assert np.array_equal(a.costs, b.costs), groups
+
+
+def test_stream_schedules_with_fixed_gates(qf):
+    """U3 + CNOT at n = 9 (fixed CNOT steps have no environment, so the
+    default schedule launches some passes alone): bitwise equal to one group."""
+    locs, kinds, _, V, init = I.u3cx_problem(9, 9, 3, 6)
+    kw = dict(tol=1e-300, max_iter=2, precision=1, diff_tol_r=0.0, long_diff_count=0, gate_kinds=kinds)
+    a = qf.instantiate(dev(V), locs, dev(init), **kw)
+    b = qf.instantiate(dev(V), locs, dev(init), stream_groups=1, **kw)
+    assert np.array_equal(host(a.all_gates), host(b.all_gates))
+    assert np.array_equal(a.costs, b.costs)
+
+
 def test_determinism(qf):
     pr = I.config2(n_starts=8)
     a = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, max_iter=30)
