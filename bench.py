@@ -71,6 +71,10 @@ def parse():
                          "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
                          "and L-BFGS workload; deletion: only the gate-deletion sweep; u3cx: only the U3 + CNOT "
                          "instantiations; k3: only the three-qubit-gate workloads")
+    ap.add_argument("--pass-forms", default=None,
+                    help="A,B: fix the complex64 pass form at n = 10 for gate class 0 (A) and 1 (B) instead of "
+                         "tuning it (-1 register-direct, -2 micro-tile, 256/512/1024 LDS tile); for counter runs, "
+                         "whose serialised dispatches distort the tuner's timings")
     return ap.parse_args()
 
 
@@ -330,6 +334,10 @@ def main():
         return
 
     K, W = max(1, args.steps), max(0, args.warmup)
+    if args.pass_forms:
+        fa, fb = (int(x) for x in args.pass_forms.split(","))
+        qf.set_pass_tile("cuda", 1, 10, 0, fa)
+        qf.set_pass_tile("cuda", 1, 10, 1, fb)
     n, layers, S = 10, 10, 16
     pr, V, init = brickwall_problem(qf, torch, 3, n, layers, S, build_on_gpu=False)
     N = 1 << n

@@ -78,7 +78,8 @@ def _c128(t: torch.Tensor, shape) -> torch.Tensor:
 
 def set_pass_tile(device, precision: int, n: int, gate_class: int, tile: int) -> None:
     """Fix the pass form for (precision, n, gate class): -1 register-direct,
-    256/512/1024 LDS tile columns, 0 = tune again (qf_set_pass_tile)."""
+    -2 micro-tile (complex64), 256/512/1024 LDS tile columns, 0 = tune again
+    (qf_set_pass_tile)."""
     ctx = _ctx(device)
     nat.check(nat.load().qf_set_pass_tile(ctx, precision, n, gate_class, tile), ctx)
 
