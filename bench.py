@@ -304,7 +304,7 @@ def cpu_baseline(n_sweeps=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the multistart and block dimensions shard "
+        print(json.dumps({"error": "this benchmark runs on one GPU: the multistart and block dimensions shard "
                                    "across GPUs only by running independent processes, which this benchmark "
                                    "does not do; run with --gpus 1"}), flush=True)
         sys.exit(2)

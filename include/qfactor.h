@@ -47,7 +47,7 @@ typedef struct qf_ctx qf_ctx;
 typedef enum {
   QF_OK = 0,
   QF_EINVAL = -1,        /* invalid argument (checked on the host) */
-  QF_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+  QF_EUNSUPPORTED = -2,  /* valid request that this library does not implement */
   QF_EHIP = -3,          /* HIP runtime error */
   QF_EWORKSPACE = -4,    /* workspace missing or smaller than qf_workspace_size */
   QF_ENUMERIC = -5,      /* every start produced non-finite values */
