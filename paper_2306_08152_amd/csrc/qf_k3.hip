@@ -9,7 +9,7 @@
 //                thread, both on the tile.
 //   k_env8       P = Tr_rest X (8 x 8, FP64 sums, one workgroup per start),
 //                E = u_old^dagger P or P u_old^dagger, and the FP64 update of
-//                Eq. opt_u on one wavefront (lane 8r + c = entry (r, c)).
+//                Eq. opt_u on one wavefront (lane r + 8c = entry (r, c)).
 //   k_optimize8  the same update for a batch of given environments.
 #include <hip/hip_runtime.h>
 
@@ -146,43 +146,66 @@ hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pas
 // ------------------------------------------------- FP64 update, 8 x 8 (oct form)
 //
 // The one-sided Jacobi step of the 4 x 4 forms (jacobi_params / jacobi_apply,
-// rank tolerance kRankTol2) on 64 lanes of a wavefront: lane 8r + c holds
+// rank tolerance kRankTol2) on the 64 lanes of a wavefront: lane r + 8c holds
 // entry (r, c) of M and of the accumulated rotation Y.  A sweep is seven
 // rounds; in round K column c pairs with c ^ K (every pair once per sweep,
-// four disjoint pairs per round, all at once on different lanes).  Column sums
-// are a butterfly over the three row bits of the lane index, so every lane of
-// a column gets bitwise the same sum.
+// four disjoint pairs per round, all at once on different lanes).  A column
+// sum is a butterfly over the three low lane bits (rows), by DPP moves within
+// each group of eight lanes, so every lane of a column gets bitwise the same
+// sum; the partner column is lane ^ 8K: a DPP row rotation for K = 1, a
+// swizzle within 32 lanes for K = 2, 3, a permute across the halves for K >= 4.
 
-__device__ __forceinline__ cd shfl_xor_cd(cd v, int m) {
-  return mk(__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64));
+// lane ^ 4 within each group of eight: mirror the eight (lane ^ 7), then
+// quad_perm [3,2,1,0] (lane ^ 3).
+__device__ __forceinline__ double dpp_xor4(double v) { return dpp_quad<kQuadXor3>(dpp_quad<0x141>(v)); }
+// lane ^ XM within each half of the wavefront (ds_swizzle bit-mask mode).
+template <int XM>
+__device__ __forceinline__ double swz_xor(double v) {
+  constexpr int pat = 0x1F | (XM << 10);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, pat);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), pat);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+// lane ^ 8K (partner column of round K)
+template <int K>
+__device__ __forceinline__ double col_xor(double v) {
+  if constexpr (K == 1) return dpp_quad<kRowRor8>(v);
+  else if constexpr (K < 4) return swz_xor<8 * K>(v);
+  else return __shfl_xor(v, 8 * K, 64);
+}
+template <int K>
+__device__ __forceinline__ cd col_xor_cd(cd v) {
+  return mk(col_xor<K>(v.re), col_xor<K>(v.im));
 }
 __device__ __forceinline__ cd shfl_cd(cd v, int src) { return mk(__shfl(v.re, src, 64), __shfl(v.im, src, 64)); }
-__device__ __forceinline__ double oct_colsum(double v) {
-  v += __shfl_xor(v, 8, 64);
-  v += __shfl_xor(v, 16, 64);
-  return v + __shfl_xor(v, 32, 64);
+__device__ __forceinline__ double oct_colsum(double v) {  // over the 8 rows of this lane's column
+  v += dpp_quad<kQuadXor1>(v);
+  v += dpp_quad<kQuadXor2>(v);
+  return v + dpp_xor4(v);
 }
-__device__ __forceinline__ double oct_rowmax(double v) {
-  v = fmax(v, __shfl_xor(v, 1, 64));
-  v = fmax(v, __shfl_xor(v, 2, 64));
-  return fmax(v, __shfl_xor(v, 4, 64));
-}
-__device__ __forceinline__ double oct_wavemax(double v) {
-  v = oct_rowmax(v);
-  v = fmax(v, __shfl_xor(v, 8, 64));
-  v = fmax(v, __shfl_xor(v, 16, 64));
+__device__ __forceinline__ double oct_rowmax(double v) {  // over the 8 columns of this lane's row
+  v = fmax(v, dpp_quad<kRowRor8>(v));
+  v = fmax(v, swz_xor<16>(v));
   return fmax(v, __shfl_xor(v, 32, 64));
 }
+__device__ __forceinline__ double oct_wavemax(double v) {
+  v = fmax(v, dpp_quad<kQuadXor1>(v));
+  v = fmax(v, dpp_quad<kQuadXor2>(v));
+  v = fmax(v, dpp_xor4(v));
+  return oct_rowmax(v);
+}
 
-__device__ __forceinline__ double oct_round(cd& m, cd& y, int c, int K) {
+template <int K>
+__device__ __forceinline__ double oct_round(cd& m, cd& y, int c) {
   const bool pside = c < (c ^ K);
-  const cd mo = shfl_xor_cd(m, K);
-  const cd yo = shfl_xor_cd(y, K);
+  const cd mo = col_xor_cd<K>(m);
+  const cd yo = col_xor_cd<K>(y);
   const cd mP = sel(pside, m, mo), mQ = sel(pside, mo, m);
   const double na = oct_colsum(nrm2x(m));
   const cd gl = cjmulx(mP, mQ);
   const cd g = mk(oct_colsum(gl.re), oct_colsum(gl.im));
-  const double nb = __shfl_xor(na, K, 64);
+  const double nb = col_xor<K>(na);
   JacobiRot j;
   if (!jacobi_params(pside ? na : nb, pside ? nb : na, g, j)) return 0.0;
   cd np, nq;
@@ -195,9 +218,10 @@ __device__ __forceinline__ double oct_round(cd& m, cd& y, int c, int K) {
 
 // m: entry (r, c) of M (overwritten); keep: entry (r, c) of the result for a
 // zero M.  Result entry (r, c) of the maximiser of Re Tr(M u); codes as the
-// 4 x 4 forms (0 computed, 1 zero M, 2 non-finite M).  All 64 lanes active.
+// 4 x 4 forms (0 computed, 1 zero M, 2 non-finite M).  All 64 lanes active,
+// lane = r + 8c.
 __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew) {
-  double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
+  const double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
   const double bad = oct_wavemax((finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0);
   if (bad != 0.0) {
     const double nan = __builtin_nan("");
@@ -211,17 +235,21 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
   m = scale(m, rcp_nr(amax));
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
   for (int sweep = 0; sweep < 30; ++sweep) {
-    double rel = 0.0;
-    for (int K = 1; K < 8; ++K) rel = fmax(rel, oct_round(m, y, c, K));
+    double rel = oct_round<1>(m, y, c);
+    rel = fmax(rel, oct_round<2>(m, y, c));
+    rel = fmax(rel, oct_round<3>(m, y, c));
+    rel = fmax(rel, oct_round<4>(m, y, c));
+    rel = fmax(rel, oct_round<5>(m, y, c));
+    rel = fmax(rel, oct_round<6>(m, y, c));
+    rel = fmax(rel, oct_round<7>(m, y, c));
     if (!(oct_rowmax(rel) > 0.0)) break;
   }
   const double sig2 = oct_colsum(nrm2x(m));
   const double smax2 = oct_rowmax(sig2);
   const bool acc = sig2 > smax2 * kRankTol2;
-  const int row0 = (int)(__lane_id() & ~7u);  // lane of (r, 0)
   double accv[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) accv[j] = __shfl(acc ? 1.0 : 0.0, row0 + j, 64);
+  for (int j = 0; j < 8; ++j) accv[j] = __shfl(acc ? 1.0 : 0.0, r + 8 * j, 64);
   cd x = sel(acc, scale(m, rsqrt_nr(acc ? sig2 : 1.0)), mk(0.0, 0.0));  // X[r][c]
   bool singular = false;
 #pragma unroll
@@ -238,7 +266,7 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
           cd v = mk(r == k ? 1.0 : 0.0, 0.0);
           for (int jj = 0; jj < 8; ++jj) {
             if (accv[jj] != 0.0) {
-              const cd xjj = shfl_cd(x, row0 + jj);
+              const cd xjj = shfl_cd(x, r + 8 * jj);
               const cd pr = cjmulx(xjj, v);
               const cd d = mk(oct_colsum(pr.re), oct_colsum(pr.im));
               v = v - mulx(xjj, d);
@@ -255,12 +283,11 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
     }
   }
   // u_new[r][c] = sum_j Y[r][j] conj(X[c][j])
-  const int base = (int)(__lane_id() & ~63u);
   cd a = mk(0.0, 0.0);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const cd yrj = shfl_cd(y, row0 + j);
-    const cd xcj = shfl_cd(x, base + 8 * c + j);
+    const cd yrj = shfl_cd(y, r + 8 * j);
+    const cd xcj = shfl_cd(x, c + 8 * j);
     cmac(a, yrj, conj(xcj));
   }
   unew = a;
@@ -313,7 +340,8 @@ __global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8
   if (t < 64) P[t] = (red[t] + red[t + 64]) + (red[t + 128] + red[t + 192]);
   __syncthreads();
   if (t >= 64) return;
-  const int r = (int)(t >> 3), c = (int)(t & 7u);
+  const int r = (int)(t & 7u), c = (int)(t >> 3);  // lane r + 8c
+  const int rc = 8 * r + c;                          // row-major entry of this lane
   if (!a.do_update) {
     reinterpret_cast<cd*>(a.env_out)[64 * (size_t)s + t] = P[t];
     return;
@@ -330,8 +358,8 @@ __global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8
   const cd urc = U[8 * r + c];
   cd un = urc;
   if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un);
-  reinterpret_cast<cd*>(a.uold)[64 * (size_t)s + t] = urc;
-  reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 64 * (int64_t)a.gidx + t] = un;
+  reinterpret_cast<cd*>(a.uold)[64 * (size_t)s + rc] = urc;
+  reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 64 * (int64_t)a.gidx + rc] = un;
 }
 
 hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8Geom& g, const Env8Args& a) {
@@ -346,15 +374,15 @@ hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8
 
 // ------------------------------------------------------------------ k_optimize8
 
-// One wavefront per environment, lane 8r + c = entry (r, c).
+// One wavefront per environment, lane r + 8c = entry (r, c).
 __global__ __launch_bounds__(64) void k_optimize8(const cd* __restrict__ env, const cd* __restrict__ uold, double beta,
                                                   cd* __restrict__ unew) {
   const size_t s = blockIdx.x;
-  const int t = (int)threadIdx.x, r = t >> 3, c = t & 7;
+  const int t = (int)threadIdx.x, r = t & 7, c = t >> 3;
   const cd* u = uold + 64 * s;
   cd un;
-  optimize_gate_f64_oct(env[64 * s + t], u[8 * c + r], u[8 * r + c], r, c, beta, un);
-  unew[64 * s + t] = un;
+  optimize_gate_f64_oct(env[64 * s + 8 * r + c], u[8 * c + r], u[8 * r + c], r, c, beta, un);
+  unew[64 * s + 8 * r + c] = un;
 }
 
 hipError_t launch_optimize8(hipStream_t st, int count, const double* env, const double* uold, double beta,
