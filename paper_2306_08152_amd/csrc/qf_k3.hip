@@ -303,12 +303,15 @@ __device__ inline void optimize_gate_f64_oct(cd e, cd uold_cr, cd uold_rc, int r
 
 // ------------------------------------------------------------------ k_env8
 
-// Grid: one 256-thread workgroup per start (n <= 14).  Thread t sums entry
-// (i, j) = t % 64 over the rests congruent to t / 64 mod 4 (eight loads in
-// flight); the four partial sums of an entry are added in a fixed order.
+// Grid: one workgroup of kEnv8Threads per start (n <= 14).  Thread t sums
+// entry (i, j) = t % 64 over the rests congruent to t / 64 mod 16 (eight
+// loads in flight: at n = 10 every thread's loads are one round); the 16
+// partial sums of an entry are added in a fixed tree.
+constexpr uint32_t kEnv8Threads = 1024;
+constexpr uint32_t kEnv8Lanes = kEnv8Threads / 64;  // rest lanes per entry
 template <typename R>
-__global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8Geom g, Env8Args a) {
-  __shared__ cd red[256];
+__global__ __launch_bounds__(kEnv8Threads) void k_env8(const cx<R>* __restrict__ X, Pass8Geom g, Env8Args a) {
+  __shared__ cd red[kEnv8Threads];
   __shared__ cd P[64], U[64];
   __shared__ int frz;
   const uint32_t t = threadIdx.x;
@@ -321,11 +324,11 @@ __global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8
   const uint32_t nrest = g.N >> 3;
   const cx<R>* Xs = X + (size_t)s * g.N * g.N;
   cd acc = mk(0.0, 0.0);
-  for (uint32_t r0 = rl; r0 < nrest; r0 += 32u) {
+  for (uint32_t r0 = rl; r0 < nrest; r0 += 8u * kEnv8Lanes) {
     cx<R> v[8];
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
-      const uint32_t rest = r0 + 4u * k;
+      const uint32_t rest = r0 + kEnv8Lanes * k;
       v[k] = mk<R>(0, 0);
       if (rest < nrest) {
         const uint32_t base = insert000(rest, g.s);
@@ -337,7 +340,11 @@ __global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8
   }
   red[t] = acc;
   __syncthreads();
-  if (t < 64) P[t] = (red[t] + red[t + 64]) + (red[t + 128] + red[t + 192]);
+  for (uint32_t stride = kEnv8Threads / 2; stride >= 64; stride >>= 1) {
+    if (t < stride) red[t] = red[t] + red[t + stride];
+    __syncthreads();
+  }
+  if (t < 64) P[t] = red[t];
   __syncthreads();
   if (t >= 64) return;
   const int r = (int)(t & 7u), c = (int)(t >> 3);  // lane r + 8c
@@ -364,7 +371,7 @@ __global__ __launch_bounds__(256) void k_env8(const cx<R>* __restrict__ X, Pass8
 
 hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8Geom& g, const Env8Args& a) {
   if (g.n > 14) return hipErrorInvalidValue;
-  const dim3 grid((uint32_t)a.S), block(256);
+  const dim3 grid((uint32_t)a.S), block(kEnv8Threads);
   if (precision == QF_C64)
     hipLaunchKernelGGL(k_env8<float>, grid, block, 0, st, reinterpret_cast<const cf*>(X), g, a);
   else

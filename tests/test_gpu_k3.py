@@ -119,7 +119,10 @@ def test_instantiate3_converges_on_reachable_target(qf, precision):
     assert res.status == 0
     assert O.cost(pr.target, host(res.gates), pr.locs, n) < tol
     if precision == 0:
-        assert res.sweeps == ref.sweeps and res.best_start == ref.best_start
+        # starts that all reach round-off tie, so the best start is not unique:
+        # compare the sweep count and the best cost
+        assert res.sweeps == ref.sweeps
+        assert res.costs[res.best_start] <= ref.costs.min() + 1e-12
 
 
 def test_instantiate3_rejects_invalid(qf):
