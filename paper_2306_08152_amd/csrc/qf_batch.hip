@@ -168,8 +168,13 @@ __global__ __launch_bounds__(kBThreads) void k_batch(BatchDev d) {
   const int r = hex_row(i), c = i & 3;
   const qf_options& o = d.opt;
   cx<R>* X = Xs[h];
-  cd* Y = d.scratch + ((size_t)blockIdx.x * kBSlots + h) * (kBNmax * kBNmax);
+  // FP64 builder of each hex (complex64 rechecks, final costs): in LDS for
+  // complex64 (the workgroup holds one workgroup per CU anyway), in global
+  // scratch for complex128.
+  __shared__ cd Ys[sizeof(R) == 4 ? kBSlots * kBNmax * kBNmax : 1];
   const bool c64 = sizeof(R) == 4;
+  cd* Y = c64 ? Ys + (size_t)h * (kBNmax * kBNmax)
+              : d.scratch + ((size_t)blockIdx.x * kBSlots + h) * (kBNmax * kBNmax);
   // Largest per-hex value over the workgroup (v uniform within each hex).
   auto wg_max = [&](int v) -> int {
     __syncthreads();
