@@ -825,11 +825,15 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
 // latency-bound environment workgroups (first in the grid, so dispatched
 // first) sit under the HBM-bound pass, on one stream and without a
 // cross-stream event.  The pass is the register-direct or the micro-tile
-// form; the environment needs one workgroup per start (n <= 14).
+// form; the environment needs one workgroup per start (n <= 14).  The
+// environment's waves raise their issue priority: they share SIMDs with pass
+// waves that mostly wait on memory, and the launch lasts as long as its
+// slower part.
 template <typename R, int FORM, int B0, int B1>
 __global__ __launch_bounds__(256) void k_fused(const cx<R>* Xe, EnvDev ed, uint32_t n_env, cx<R>* Xp, PassGeom g,
                                                uint32_t wgps, Operand A, Operand B) {
   if (blockIdx.x < n_env) {
+    __builtin_amdgcn_s_setprio(3);
     env_body<R>(Xe, ed, blockIdx.x);
     return;
   }
