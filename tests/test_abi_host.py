@@ -86,7 +86,9 @@ def test_workspace_size_layout(lib):
 
 def test_batch_workspace_size(lib):
     """Batched layout: descriptors, history ring per (block, start), and an
-    FP64 scratch builder (16 x 16) per quad of each launched workgroup."""
+    FP64 scratch builder (16 x 16) per hex (16 lanes, one instantiation) of
+    each launched workgroup, which the complex128 kernel's fresh FP64
+    re-evaluations use."""
     I32 = ctypes.c_int32
     bn = (I32 * 3)(3, 4, 2)
     go = (I32 * 4)(0, 5, 17, 18)
@@ -112,6 +114,27 @@ def test_batch_workspace_size(lib):
     assert lib.qf_batch_workspace_size(3, bn, empty, 8, ctypes.byref(o)) == 0
 
 
+def test_workspace_size3_layout(lib):
+    """Three-qubit gates: S builders of N^2 entries (plus an FP64 rebuild
+    copy each for complex64), S x p gates of 8 x 8 complex128, and small
+    per-start state; sizes outside n in [3, 14] are refused."""
+    n, p, S = 10, 16, 8
+    N = 1 << n
+    gates = S * p * 64 * 16
+    o = _opts(lib, precision=nat.QF_C128)
+    ws = lib.qf_workspace_size3(n, p, S, ctypes.byref(o))
+    assert S * N * N * 16 + gates <= ws <= S * N * N * 16 + gates + (1 << 16)
+    o = _opts(lib, precision=nat.QF_C64)
+    ws64 = lib.qf_workspace_size3(n, p, S, ctypes.byref(o))
+    assert S * N * N * (8 + 16) + gates <= ws64 <= S * N * N * (8 + 16) + gates + (1 << 16)
+    assert lib.qf_workspace_size3(3, 1, 1, None) > 0
+    assert lib.qf_workspace_size3(2, 1, 1, None) == 0
+    assert lib.qf_workspace_size3(15, 1, 1, None) == 0
+    assert lib.qf_workspace_size3(5, 0, 1, None) == 0
+    assert lib.qf_workspace_size3(5, 2, 0, None) == 0
+    assert lib.qf_workspace_size3(5, 2, 1, ctypes.byref(_opts(lib, beta=1.5))) == 0
+
+
 def test_null_context_is_rejected_before_device_work(lib):
     locs = (ctypes.c_int32 * 2)(0, 1)
     assert lib.qf_instantiate(None, 2, None, 1, locs, None, 1, 1e-8, None, None, 0, None, None, None,
@@ -121,6 +144,11 @@ def test_null_context_is_rejected_before_device_work(lib):
                                     0, None, None, None, None, None, None) == nat.QF_EINVAL
     assert lib.qf_apply_gate(None, 2, 1, None, 0, locs, None, 0, 0) == nat.QF_EINVAL
     assert lib.qf_environment(None, 2, 1, None, 0, locs, None) == nat.QF_EINVAL
+    locs3 = (ctypes.c_int32 * 3)(0, 1, 2)
+    assert lib.qf_instantiate3(None, 3, None, 1, locs3, None, 1, 1e-8, None, None, 0, None, None, None,
+                               None) == nat.QF_EINVAL
+    assert lib.qf_optimize_gate3(None, 1, None, None, 0.0, None) == nat.QF_EINVAL
+    assert lib.qf_optimize_gate(None, 1, None, None, 0.0, None) == nat.QF_EINVAL
     assert lib.qf_destroy(None) == nat.QF_EINVAL
     ctx = ctypes.c_void_p()
     assert lib.qf_create(None, 0, None) == nat.QF_EINVAL
