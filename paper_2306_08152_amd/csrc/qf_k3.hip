@@ -51,11 +51,64 @@ Pass8Geom make_pass8_geom(int n, const int32_t loc[3]) {
 
 // ------------------------------------------------------------------ k_pass8
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Entry (r, k) of the real 16 x 16 form [[Mr, -Mi], [Mi, Mr]] of an 8 x 8
+// complex matrix M (rows and columns 0..7 real parts, 8..15 imaginary), with
+// M(a, b) = src[8 a + b], or src[8 b + a] when T.
+template <bool T>
+__device__ __forceinline__ float real16(const cf* src, uint32_t r, uint32_t k) {
+  const uint32_t a = r & 7u, b = k & 7u;
+  const cf m = src[T ? 8u * b + a : 8u * a + b];
+  if (r < 8u) return k < 8u ? m.re : -m.im;
+  return k < 8u ? m.im : m.re;
+}
+
+// Matrix-core form of one product over a complex64 tile of W = 32 column
+// groups: y = M x for the tile's 256 vectors x, in place.  LEFT: the vectors
+// are the columns (j, w) and M = A (entry i of a vector is tile entry
+// (i, j, w)); otherwise the rows (i, w) and M = B^T (entry j is (i, j, w)).
+// Each product is the real contraction [Re y; Im y] = M16 [Re x; Im x] on
+// v_mfma_f32_16x16x4f32 (A operand 16 x 4: lane l holds row l % 16, column
+// l / 16; B operand 4 x 16: lane l holds row l / 16, column l % 16; result:
+// lane l holds rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16), four
+// k-steps of four.  Wavefront v takes vectors 64 v .. 64 v + 63, sixteen per
+// MFMA tile; a vector's entries are read and written by its own wavefront
+// only, so the update in place needs no barrier.  Sums run in the matrix
+// core's order, so the result differs from the vector form's in rounding only.
+template <bool LEFT>
+__device__ __forceinline__ void tile_products_mfma(cf* tile, const cf* M, uint32_t t) {
+  const uint32_t l = t & 63u, wv = t >> 6, g = l >> 4, cl = l & 15u;
+  float am[4];
+#pragma unroll
+  for (uint32_t ks = 0; ks < 4; ++ks) am[ks] = real16<!LEFT>(M, cl, 4u * ks + g);
+  float* tf = reinterpret_cast<float*>(tile);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t vec = (wv * 4u + q) * 16u + cl;  // 0..255
+    const uint32_t hi = vec >> 5, w = vec & 31u;     // LEFT: column variant j; else row i
+    auto at = [&](uint32_t c) -> uint32_t { return (LEFT ? ((c * 8u + hi) << 5) : ((hi * 8u + c) << 5)) + w; };
+    // k-row 4 ks + g of the vector: Re x_g, Re x_{4+g}, Im x_g, Im x_{4+g}
+    const cf x0 = tile[at(g)], x1 = tile[at(4u + g)];
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[0], x0.re, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[1], x1.re, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[2], x0.im, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[3], x1.im, acc, 0, 0, 0);
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) {
+      const uint32_t r = 4u * g + v;  // < 8: Re y_r, else Im y_{r-8}
+      tf[2u * at(r & 7u) + (r >> 3)] = acc[v];
+    }
+  }
+}
+
 // Grid: S x tiles_per_start workgroups of 256 threads.  Tile entry
 // ((i * 8 + j) * W + w) holds row rb + off(i), column cb_w + off(j); the
 // loads and stores run w fastest, so a wavefront touches W consecutive
-// column groups of one (row, column variant).
-template <typename R, bool HA, bool HB>
+// column groups of one (row, column variant).  MF (complex64, W = 32): the
+// two products on the matrix cores.
+template <typename R, bool HA, bool HB, bool MF>
 __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom g, Operand A, Operand B) {
   __shared__ cx<R> tile[64 * 32];
   __shared__ cx<R> As[64], Bs[64];
@@ -84,7 +137,9 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
     tile[e] = Xs[(size_t)(rb + local_off8(i, g.b)) * g.N + cb + local_off8(j, g.b)];
   }
   __syncthreads();
-  if (HA && t < (8u << wlog)) {  // one column (variant j of group w): x <- A x
+  if constexpr (MF) {
+    if (HA) tile_products_mfma<true>(tile, As, t);
+  } else if (HA && t < (8u << wlog)) {  // one column (variant j of group w): x <- A x
     const uint32_t j = t >> wlog, w = t & (W - 1u);
     cx<R> x[8], y[8];
 #pragma unroll
@@ -100,7 +155,9 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
     for (int i = 0; i < 8; ++i) tile[(((uint32_t)i * 8u + j) << wlog) + w] = y[i];
   }
   __syncthreads();
-  if (HB && t < (8u << wlog)) {  // one row (i of group w): x <- x B
+  if constexpr (MF) {
+    if (HB) tile_products_mfma<false>(tile, Bs, t);
+  } else if (HB && t < (8u << wlog)) {  // one row (i of group w): x <- x B
     const uint32_t i = t >> wlog, w = t & (W - 1u);
     cx<R> x[8], y[8];
 #pragma unroll
@@ -123,24 +180,27 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
   }
 }
 
-template <typename R>
+template <typename R, bool MF>
 static hipError_t launch_pass8_t(hipStream_t st, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
   const dim3 grid((uint32_t)S * g.tiles_per_start), block(256);
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
   if (A.ptr && B.ptr)
-    hipLaunchKernelGGL((k_pass8<R, true, true>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, true, true, MF>), grid, block, 0, st, x, g, A, B);
   else if (A.ptr)
-    hipLaunchKernelGGL((k_pass8<R, true, false>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, true, false, MF>), grid, block, 0, st, x, g, A, B);
   else if (B.ptr)
-    hipLaunchKernelGGL((k_pass8<R, false, true>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, false, true, MF>), grid, block, 0, st, x, g, A, B);
   else
     return hipSuccess;
   return hipGetLastError();
 }
 
 hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
-  if (precision == QF_C64) return launch_pass8_t<float>(st, X, S, g, A, B);
-  return launch_pass8_t<double>(st, X, S, g, A, B);
+  if (precision == QF_C64) {
+    if (g.W == 32u && g.wlog == 5u) return launch_pass8_t<float, true>(st, X, S, g, A, B);
+    return launch_pass8_t<float, false>(st, X, S, g, A, B);
+  }
+  return launch_pass8_t<double, false>(st, X, S, g, A, B);
 }
 
 // ------------------------------------------------- FP64 update, 8 x 8 (oct form)

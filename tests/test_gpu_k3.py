@@ -4,7 +4,8 @@ whose k-qubit forms are pinned in test_oracle_pins.py.
 
 Tolerances: complex128 sweeps follow the oracle's trajectory update by update
 (gates to 1e-9 after a few sweeps, costs to 1e-10); complex64 builders to
-1e-5 relative; the 8 x 8 update is unitary to 1e-12 and attains the nuclear
+1e-5 in the costs (1e-4 in the gates after three sweeps), with the 8 x 8
+products on the matrix cores for n >= 8; the 8 x 8 update is unitary to 1e-12 and attains the nuclear
 norm to 1e-12 relative."""
 import numpy as np
 import pytest
@@ -103,6 +104,28 @@ def test_instantiate3_n10_one_sweep_both_precisions(qf):
     assert np.abs(r64.costs - ref.costs).max() <= 1e-5
     for s in range(2):
         assert abs(O.cost(V, host(r64.all_gates)[s], pr.locs, n) - r64.costs[s]) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [8, 9])
+def test_instantiate3_c64_matrix_core_pass_follows_oracle(qf, n):
+    """n >= 8: the complex64 pass runs its 8 x 8 products on the matrix
+    cores (32-group tiles).  Three sweeps from three Haar starts: the
+    complex64 sweep costs stay within 1e-5 of the oracle's, the gates within
+    1e-4, and the FP64 final costs equal the oracle cost of the returned
+    gates."""
+    pr = I.k3_problem(38, n, 3, 3)
+    rng = np.random.default_rng(3400 + n)
+    V = I.haar_unitary(rng, 1 << n)
+    sweeps = 3
+    ref = O.instantiate(V, pr.init_gates, pr.locs, n, tol=1e-300, opt=O.Options(max_iter=sweeps, **NOPLATEAU))
+    r64 = qf.instantiate3(dev(V), pr.locs, dev(pr.init_gates), tol=1e-300, max_iter=sweeps, precision=1,
+                          history_rows=sweeps + 1, **NOPLATEAU)
+    assert r64.sweeps == ref.sweeps == sweeps
+    assert np.abs(r64.history - ref.history[: r64.history.shape[0]]).max() <= 1e-5
+    got = host(r64.all_gates)
+    assert np.abs(got - ref.all_gates).max() <= 1e-4
+    for s in range(3):
+        assert abs(O.cost(V, got[s], pr.locs, n) - r64.costs[s]) <= 1e-12
 
 
 @pytest.mark.parametrize("precision", [0, 1])
