@@ -160,8 +160,10 @@ typedef struct {
                             row i receives the costs after sweep i (row 0 =
                             initial gates) for i < cost_history_rows */
   int32_t cost_history_rows;
-  int32_t timing;        /* in: nonzero records HIP events around every
-                            kernel of the streaming sweep loop; the starts
+  int32_t timing;        /* in: nonzero times every pass and environment
+                            kernel of the streaming sweep loop with a HIP
+                            start / stop event pair that its dispatch
+                            stamps (the kernel's execution); the starts
                             then run as one group (no overlap of two
                             groups' kernels), so each duration is the
                             kernel's own */

@@ -337,9 +337,10 @@ int read_costs(qf_ctx* ctx, const double* dev, int S, std::vector<double>& out) 
   return QF_OK;
 }
 
-// Optional per-kernel timing of the streaming sweeps with HIP events on the
-// context stream (pairs recorded around each launch, summed after the
-// per-sweep synchronisation).
+// Optional per-kernel timing of the streaming sweeps with HIP events: each
+// timed launch carries a start / stop pair that the dispatch itself stamps
+// (the kernel's execution, without the stream's dispatch gap around it);
+// the pairs are summed after the per-sweep synchronisation.
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> ev;  // pairs
@@ -365,14 +366,13 @@ struct KernelTimer {
     if (r != hipSuccess) return r;
     return hipEventCreate(&s1);
   }
-  hipError_t begin(hipStream_t st, int k) {
-    if (!on || used >= kind.size()) return hipSuccess;
+  // the event pair for the next launch of kind k (0 = pass, 1 = env), or none
+  KernelEvents next(int k) {
+    if (!on || used >= kind.size()) return {};
     kind[used] = k;
-    return hipEventRecord(ev[2 * used], st);
-  }
-  hipError_t end(hipStream_t st) {
-    if (!on || used >= kind.size()) return hipSuccess;
-    return hipEventRecord(ev[2 * used++ + 1], st);
+    const KernelEvents e{ev[2 * used], ev[2 * used + 1]};
+    ++used;
+    return e;
   }
   // after a stream synchronisation: fold the recorded pairs into the sums
   hipError_t collect() {
@@ -481,12 +481,11 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
       Operand ud{ea.gates + 2 * 16 * (int64_t)g, gstride, 1};
       Operand u{ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
       if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
-      QF_HIP(ctx, timer.begin(q.st, 0));
+      const KernelEvents te = timer.next(0);
       if (half == 0)
-        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], ud, u));
+        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], ud, u, te));
       else
-        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], u, ud));
-      QF_HIP(ctx, timer.end(q.st));
+        QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], u, ud, te));
       return QF_OK;
     }
     ea.kind = kind;
@@ -494,18 +493,15 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     ea.q1 = locs[2 * g + 1];
     ea.half = half;
     ea.gidx = g;
-    QF_HIP(ctx, timer.begin(q.st, 1));
-    QF_HIP(ctx, launch_env(q.st, prec, q.X, ea));
-    QF_HIP(ctx, timer.end(q.st));
+    QF_HIP(ctx, launch_env(q.st, prec, q.X, ea, timer.next(1)));
     if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
     Operand gnew{ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
     Operand gold{ea.uold, 16, 1};
-    QF_HIP(ctx, timer.begin(q.st, 0));
+    const KernelEvents te = timer.next(0);
     if (half == 0)
-      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gold, gnew));
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gold, gnew, te));
     else
-      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gnew, gold));
-    QF_HIP(ctx, timer.end(q.st));
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gnew, gold, te));
     return QF_OK;
   };
   // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved,

@@ -44,8 +44,15 @@ struct Operand {
   int dagger;
 };
 
+// Optional timestamps of one kernel's own execution (hipExtLaunchKernel's
+// start / stop events: the dispatch's begin and end, not the stream's
+// position around the launch).  Both null: a plain launch.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
-                       Operand B);
+                       Operand B, KernelEvents ev = {});
 
 // Three-qubit gates (qf_k3.hip).  Operands are 8 x 8 c128 per start.
 struct Pass8Geom {
@@ -98,7 +105,7 @@ uint32_t env_workgroups(int n);
 // be captured in a HIP graph).
 hipError_t launch_fill_i32(hipStream_t st, int32_t* p, int32_t v, uint32_t count);
 int pass_max_tcols(int precision);
-hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a);
+hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a, KernelEvents ev = {});
 // One launch: the environment step `ea` (update mode) on builders Xe and the
 // two-sided pass of gate geometry g on the Sp builders at Xp (disjoint data).
 bool fused_supported(int precision, int n, const PassGeom& g);

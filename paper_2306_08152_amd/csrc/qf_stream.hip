@@ -9,6 +9,7 @@
 //   k_cost         Tr X_s and 1 - |Tr X_s| / N in FP64
 //   k_optimize     batched FP64 gate update on given environments
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "qf_device.h"
 #include "qf_internal.h"
@@ -490,45 +491,57 @@ __global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t
   pass_micro_body<B0, B1, HA, HB>(X, n, wg_per_start, A, B, blockIdx.x);
 }
 
-template <int B0, int B1, bool HA, bool HB>
-static hipError_t launch_pass_micro_t(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B) {
-  const uint32_t wgps = g.N * g.N / 8192u;  // (N/4 row groups) x (N/512 spans) wavefronts, 4 per workgroup
-  hipLaunchKernelGGL((k_pass_micro<B0, B1, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), 0, st, x, g.n, wgps, A, B);
+// A launch, with the kernel's own start / stop timestamps when asked for.
+template <typename F, typename... Args>
+static hipError_t launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, KernelEvents ev,
+                           Args... args) {
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, st, ev.start, ev.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
   return hipGetLastError();
 }
+
+template <int B0, int B1, bool HA, bool HB>
+static hipError_t launch_pass_micro_t(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B,
+                                      KernelEvents ev) {
+  const uint32_t wgps = g.N * g.N / 8192u;  // (N/4 row groups) x (N/512 spans) wavefronts, 4 per workgroup
+  return launch_k(k_pass_micro<B0, B1, HA, HB>, dim3((uint32_t)S * wgps), dim3(256), 0u, st, ev, x, g.n, wgps, A,
+                  B);
+}
 template <bool HA, bool HB>
-static hipError_t launch_pass_micro(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B) {
+static hipError_t launch_pass_micro(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B,
+                                    KernelEvents ev) {
   switch (g.b0 * 3 + g.b1) {
-    case 0 * 3 + 1: return launch_pass_micro_t<0, 1, HA, HB>(st, x, S, g, A, B);
-    case 0 * 3 + 2: return launch_pass_micro_t<0, 2, HA, HB>(st, x, S, g, A, B);
-    case 1 * 3 + 0: return launch_pass_micro_t<1, 0, HA, HB>(st, x, S, g, A, B);
-    case 1 * 3 + 2: return launch_pass_micro_t<1, 2, HA, HB>(st, x, S, g, A, B);
-    case 2 * 3 + 0: return launch_pass_micro_t<2, 0, HA, HB>(st, x, S, g, A, B);
-    case 2 * 3 + 1: return launch_pass_micro_t<2, 1, HA, HB>(st, x, S, g, A, B);
+    case 0 * 3 + 1: return launch_pass_micro_t<0, 1, HA, HB>(st, x, S, g, A, B, ev);
+    case 0 * 3 + 2: return launch_pass_micro_t<0, 2, HA, HB>(st, x, S, g, A, B, ev);
+    case 1 * 3 + 0: return launch_pass_micro_t<1, 0, HA, HB>(st, x, S, g, A, B, ev);
+    case 1 * 3 + 2: return launch_pass_micro_t<1, 2, HA, HB>(st, x, S, g, A, B, ev);
+    case 2 * 3 + 0: return launch_pass_micro_t<2, 0, HA, HB>(st, x, S, g, A, B, ev);
+    case 2 * 3 + 1: return launch_pass_micro_t<2, 1, HA, HB>(st, x, S, g, A, B, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename R, bool HA, bool HB>
-static hipError_t launch_pass_direct(hipStream_t st, cx<R>* x, int S, const PassGeom& g, Operand A, Operand B) {
+static hipError_t launch_pass_direct(hipStream_t st, cx<R>* x, int S, const PassGeom& g, Operand A, Operand B,
+                                     KernelEvents ev) {
   const uint32_t wgps = g.N * g.N / 4096u;  // N^2/16 blocks, 256 per workgroup
   // The kernel uses no LDS; the 40 KiB it reserves caps it at 4 workgroups
   // (16 waves) per CU, which keeps its bandwidth and was measured to let the
   // concurrent stream groups' environment steps interleave with it better
   // (start-sweeps/s +7 to +10 % at n = 10 with 16 starts in 3-4 groups).
   constexpr size_t kPassBlockLds = 40 * 1024;
-  hipLaunchKernelGGL((k_pass_block<R, HA, HB>), dim3((uint32_t)S * wgps), dim3(256), kPassBlockLds, st, x, g, wgps,
-                     A, B);
-  return hipGetLastError();
+  return launch_k(k_pass_block<R, HA, HB>, dim3((uint32_t)S * wgps), dim3(256), (uint32_t)kPassBlockLds, st, ev, x,
+                  g, wgps, A, B);
 }
 
 template <typename R, bool HA, bool HB>
 static hipError_t launch_pass_v(hipStream_t st, cx<R>* x, uint32_t total, const PassGeom& g, Operand A,
-                                Operand B) {
+                                Operand B, KernelEvents ev) {
   const uint32_t TCOLS = 1u << g.tcols_log;
   const size_t lds = 4u * TCOLS * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_pass<R, HA, HB>), dim3(total), dim3(TCOLS >> 2), lds, st, x, g, A, B);
-  return hipGetLastError();
+  return launch_k(k_pass<R, HA, HB>, dim3(total), dim3(TCOLS >> 2), (uint32_t)lds, st, ev, x, g, A, B);
 }
 
 // Default tile width before (or without) tuning: 32 KiB of LDS per tile.
@@ -536,35 +549,35 @@ int pass_max_tcols(int precision) { return precision == QF_C64 ? 1024 : 512; }
 
 template <typename R>
 static hipError_t launch_pass_t(hipStream_t st, void* X, int S, const PassGeom& g, Operand A,
-                                Operand B) {
+                                Operand B, KernelEvents ev) {
   const uint32_t total = (uint32_t)S * g.tiles_per_start;
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
   if (g.micro && (reinterpret_cast<uintptr_t>(X) & 15u) == 0) {  // 16 B loads; else the LDS tile below
     if constexpr (sizeof(R) == 4) {
-      if (A.ptr && B.ptr) return launch_pass_micro<true, true>(st, x, S, g, A, B);
-      if (A.ptr) return launch_pass_micro<true, false>(st, x, S, g, A, B);
-      if (B.ptr) return launch_pass_micro<false, true>(st, x, S, g, A, B);
+      if (A.ptr && B.ptr) return launch_pass_micro<true, true>(st, x, S, g, A, B, ev);
+      if (A.ptr) return launch_pass_micro<true, false>(st, x, S, g, A, B, ev);
+      if (B.ptr) return launch_pass_micro<false, true>(st, x, S, g, A, B, ev);
       return hipSuccess;
     } else {
       return hipErrorInvalidValue;  // complex64 only
     }
   }
   if (g.direct) {
-    if (A.ptr && B.ptr) return launch_pass_direct<R, true, true>(st, x, S, g, A, B);
-    if (A.ptr) return launch_pass_direct<R, true, false>(st, x, S, g, A, B);
-    if (B.ptr) return launch_pass_direct<R, false, true>(st, x, S, g, A, B);
+    if (A.ptr && B.ptr) return launch_pass_direct<R, true, true>(st, x, S, g, A, B, ev);
+    if (A.ptr) return launch_pass_direct<R, true, false>(st, x, S, g, A, B, ev);
+    if (B.ptr) return launch_pass_direct<R, false, true>(st, x, S, g, A, B, ev);
     return hipSuccess;
   }
-  if (A.ptr && B.ptr) return launch_pass_v<R, true, true>(st, x, total, g, A, B);
-  if (A.ptr) return launch_pass_v<R, true, false>(st, x, total, g, A, B);
-  if (B.ptr) return launch_pass_v<R, false, true>(st, x, total, g, A, B);
+  if (A.ptr && B.ptr) return launch_pass_v<R, true, true>(st, x, total, g, A, B, ev);
+  if (A.ptr) return launch_pass_v<R, true, false>(st, x, total, g, A, B, ev);
+  if (B.ptr) return launch_pass_v<R, false, true>(st, x, total, g, A, B, ev);
   return hipSuccess;
 }
 
 hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const PassGeom& g, Operand A,
-                       Operand B) {
-  if (precision == QF_C64) return launch_pass_t<float>(st, X, S, g, A, B);
-  return launch_pass_t<double>(st, X, S, g, A, B);
+                       Operand B, KernelEvents ev) {
+  if (precision == QF_C64) return launch_pass_t<float>(st, X, S, g, A, B, ev);
+  return launch_pass_t<double>(st, X, S, g, A, B, ev);
 }
 
 // k_env: 256 threads = 16 (i,j) pairs x 16 rest lanes; one workgroup covers
@@ -806,15 +819,12 @@ static EnvDev make_env_dev(const EnvArgs& a) {
   return d;
 }
 
-hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a) {
+hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a, KernelEvents ev) {
   const EnvDev d = make_env_dev(a);
   if (d.nwg > 1 && (!a.partials || !a.counters)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)a.S * d.nwg), block(kEnvThreads);
-  if (precision == QF_C64)
-    hipLaunchKernelGGL(k_env<float>, grid, block, 0, st, reinterpret_cast<const cf*>(X), d);
-  else
-    hipLaunchKernelGGL(k_env<double>, grid, block, 0, st, reinterpret_cast<const cd*>(X), d);
-  return hipGetLastError();
+  if (precision == QF_C64) return launch_k(k_env<float>, grid, block, 0u, st, ev, reinterpret_cast<const cf*>(X), d);
+  return launch_k(k_env<double>, grid, block, 0u, st, ev, reinterpret_cast<const cd*>(X), d);
 }
 
 // ------------------------------------------------------------ k_fused
