@@ -385,6 +385,29 @@ def test_stream_schedules_bitwise_equal(qf, S):
         assert np.array_equal(a.costs, b.costs), groups
 
 
+def test_timing_run_same_results_and_consistent_durations(qf):
+    """The per-kernel timing run (starts as one group, every pass and
+    environment launch stamped by its own dispatch) gives bitwise the
+    default schedule's gates and costs, counts 2p passes and 2p environment
+    steps per sweep, and its kernels, which run one after another on one
+    stream, sum to no more than the sweep loop's device time."""
+    pr = I.config3(n_starts=4)
+    sweeps = 2
+    kw = dict(tol=1e-300, max_iter=sweeps, precision=1, diff_tol_r=0.0, long_diff_count=0)
+    V, g = dev(pr.target), dev(pr.init_gates)
+    a = qf.instantiate(V, pr.locs, g, **kw)
+    b = qf.instantiate(V, pr.locs, g, timing=True, **kw)
+    assert np.array_equal(host(a.all_gates), host(b.all_gates))
+    assert np.array_equal(a.costs, b.costs)
+    t = b.timing
+    p = len(pr.locs)
+    assert t["pass_launches"] == 2 * p * sweeps
+    assert t["env_launches"] == 2 * p * sweeps
+    per_pass_us = 1e3 * t["pass_ms"] / t["pass_launches"]
+    assert 1.0 < per_pass_us < 1e4
+    assert 0 < t["env_ms"] and t["pass_ms"] + t["env_ms"] <= t["sweep_ms"] * 1.001
+
+
 def test_stream_schedules_with_fixed_gates(qf):
     """U3 + CNOT at n = 9 (fixed CNOT steps have no environment, so the
     default schedule launches some passes alone): bitwise equal to one group."""
