@@ -106,9 +106,9 @@ __device__ __forceinline__ void tile_products_mfma(cf* tile, const cf* M, uint32
 // Grid: S x tiles_per_start workgroups of 256 threads.  Tile entry
 // ((i * 8 + j) * W + w) holds row rb + off(i), column cb_w + off(j); the
 // loads and stores run w fastest, so a wavefront touches W consecutive
-// column groups of one (row, column variant).  MF (complex64, W = 32): the
-// two products on the matrix cores.
-template <typename R, bool HA, bool HB, bool MF>
+// column groups of one (row, column variant).  complex64 at W = 32 (n >= 8)
+// takes the pipelined form below instead.
+template <typename R, bool HA, bool HB>
 __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom g, Operand A, Operand B) {
   __shared__ cx<R> tile[64 * 32];
   __shared__ cx<R> As[64], Bs[64];
@@ -137,9 +137,7 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
     tile[e] = Xs[(size_t)(rb + local_off8(i, g.b)) * g.N + cb + local_off8(j, g.b)];
   }
   __syncthreads();
-  if constexpr (MF) {
-    if (HA) tile_products_mfma<true>(tile, As, t);
-  } else if (HA && t < (8u << wlog)) {  // one column (variant j of group w): x <- A x
+  if (HA && t < (8u << wlog)) {  // one column (variant j of group w): x <- A x
     const uint32_t j = t >> wlog, w = t & (W - 1u);
     cx<R> x[8], y[8];
 #pragma unroll
@@ -155,9 +153,7 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
     for (int i = 0; i < 8; ++i) tile[(((uint32_t)i * 8u + j) << wlog) + w] = y[i];
   }
   __syncthreads();
-  if constexpr (MF) {
-    if (HB) tile_products_mfma<false>(tile, Bs, t);
-  } else if (HB && t < (8u << wlog)) {  // one row (i of group w): x <- x B
+  if (HB && t < (8u << wlog)) {  // one row (i of group w): x <- x B
     const uint32_t i = t >> wlog, w = t & (W - 1u);
     cx<R> x[8], y[8];
 #pragma unroll
@@ -180,27 +176,103 @@ __global__ __launch_bounds__(256) void k_pass8(cx<R>* __restrict__ X, Pass8Geom 
   }
 }
 
-template <typename R, bool MF>
+// Complex64, W = 32 (n >= 8), software-pipelined: a workgroup walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... and issues the loads of its next
+// tile (eight entries per thread, held in registers) before it multiplies
+// and stores the current one, so their latency runs under that work.  Tiles
+// are those of k_pass8; every entry is read and written once; the products
+// run on the matrix cores.
+constexpr uint32_t kPass8PipeGrid = 2048;
+template <bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_pass8_pipe(cf* __restrict__ X, Pass8Geom g, Operand A, Operand B,
+                                                    uint32_t total) {
+  __shared__ cf tile[64 * 32];
+  __shared__ cf As[64], Bs[64];
+  const uint32_t t = threadIdx.x;
+  auto entry = [&](uint32_t tl, uint32_t e) -> size_t {  // offset of tile entry e of tile tl
+    const uint32_t s = tl / g.tiles_per_start;
+    const uint32_t rem = tl - s * g.tiles_per_start;
+    const uint32_t rgi = rem / g.col_tiles, cti = rem - rgi * g.col_tiles;
+    const uint32_t w = e & 31u, ij = e >> 5, i = ij >> 3, j = ij & 7u;
+    const uint32_t rb = insert000(rgi, g.s), cb = insert000((cti << 5) + w, g.s);
+    return (size_t)s * g.N * g.N + (size_t)(rb + local_off8(i, g.b)) * g.N + cb + local_off8(j, g.b);
+  };
+  cf pre[8];
+  uint32_t tl = blockIdx.x;
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) pre[k] = X[entry(tl, t + 256u * k)];
+  for (; tl < total; tl += gridDim.x) {
+    const uint32_t s = tl / g.tiles_per_start;
+    __syncthreads();  // the previous tile's stores have read the LDS tile
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) tile[t + 256u * k] = pre[k];
+    if (HA && t < 64) {
+      const cd* src = reinterpret_cast<const cd*>(A.ptr) + (int64_t)s * A.stride;
+      const uint32_t r = t >> 3, c = t & 7u;
+      const cd v = A.dagger ? conj(src[8 * c + r]) : src[8 * r + c];
+      As[t] = cf{(float)v.re, (float)v.im};
+    }
+    if (HB && t >= 64 && t < 128) {
+      const cd* src = reinterpret_cast<const cd*>(B.ptr) + (int64_t)s * B.stride;
+      const uint32_t r = (t - 64) >> 3, c = (t - 64) & 7u;
+      const cd v = B.dagger ? conj(src[8 * c + r]) : src[8 * r + c];
+      Bs[t - 64] = cf{(float)v.re, (float)v.im};
+    }
+    const uint32_t nx = tl + gridDim.x;
+    if (nx < total) {
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) pre[k] = X[entry(nx, t + 256u * k)];
+    }
+    __syncthreads();
+    if (HA) tile_products_mfma<true>(tile, As, t);
+    __syncthreads();
+    if (HB) tile_products_mfma<false>(tile, Bs, t);
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) X[entry(tl, t + 256u * k)] = tile[t + 256u * k];
+  }
+}
+
+template <typename R>
 static hipError_t launch_pass8_t(hipStream_t st, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
   const dim3 grid((uint32_t)S * g.tiles_per_start), block(256);
   cx<R>* x = reinterpret_cast<cx<R>*>(X);
   if (A.ptr && B.ptr)
-    hipLaunchKernelGGL((k_pass8<R, true, true, MF>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, true, true>), grid, block, 0, st, x, g, A, B);
   else if (A.ptr)
-    hipLaunchKernelGGL((k_pass8<R, true, false, MF>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, true, false>), grid, block, 0, st, x, g, A, B);
   else if (B.ptr)
-    hipLaunchKernelGGL((k_pass8<R, false, true, MF>), grid, block, 0, st, x, g, A, B);
+    hipLaunchKernelGGL((k_pass8<R, false, true>), grid, block, 0, st, x, g, A, B);
+  else
+    return hipSuccess;
+  return hipGetLastError();
+}
+
+static hipError_t launch_pass8_pipe(hipStream_t st, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
+  const uint32_t total = (uint32_t)S * g.tiles_per_start;
+  const dim3 grid(total < kPass8PipeGrid ? total : kPass8PipeGrid), block(256);
+  cf* x = reinterpret_cast<cf*>(X);
+  if (A.ptr && B.ptr)
+    hipLaunchKernelGGL((k_pass8_pipe<true, true>), grid, block, 0, st, x, g, A, B, total);
+  else if (A.ptr)
+    hipLaunchKernelGGL((k_pass8_pipe<true, false>), grid, block, 0, st, x, g, A, B, total);
+  else if (B.ptr)
+    hipLaunchKernelGGL((k_pass8_pipe<false, true>), grid, block, 0, st, x, g, A, B, total);
   else
     return hipSuccess;
   return hipGetLastError();
 }
 
 hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
+  // complex128 keeps k_pass8 also at W = 32: a pipelined form with vector
+  // FP64 products (34 KiB of LDS, four workgroups per CU) was measured
+  // slower, 83 against 54 us at n = 10, 8 starts.
+  const bool w32 = g.W == 32u && g.wlog == 5u;  // n >= 8
   if (precision == QF_C64) {
-    if (g.W == 32u && g.wlog == 5u) return launch_pass8_t<float, true>(st, X, S, g, A, B);
-    return launch_pass8_t<float, false>(st, X, S, g, A, B);
+    if (w32) return launch_pass8_pipe(st, X, S, g, A, B);
+    return launch_pass8_t<float>(st, X, S, g, A, B);
   }
-  return launch_pass8_t<double, false>(st, X, S, g, A, B);
+  return launch_pass8_t<double>(st, X, S, g, A, B);
 }
 
 // ------------------------------------------------- FP64 update, 8 x 8 (oct form)
