@@ -128,6 +128,29 @@ def test_instantiate3_c64_matrix_core_pass_follows_oracle(qf, n):
         assert abs(O.cost(V, got[s], pr.locs, n) - r64.costs[s]) <= 1e-12
 
 
+def test_instantiate3_n10_eight_starts_pipelined_walk(qf):
+    """n = 10, 8 starts: the launch configuration the three-qubit timing
+    uses.  The complex64 pass then has 4096 tiles on a grid of 2048
+    workgroups, so every workgroup walks two tiles, four starts apart, and
+    prefetches the second while it finishes the first.  One sweep: complex64
+    costs within 1e-5 of the oracle's, gates within 1e-4, FP64 final costs
+    equal to the oracle cost of the returned gates; complex128 gates within
+    1e-9."""
+    n = 10
+    pr = I.k3_problem(39, n, 3, 8)
+    rng = np.random.default_rng(3500)
+    V = I.haar_unitary(rng, 1 << n)
+    ref = O.instantiate(V, pr.init_gates, pr.locs, n, tol=1e-300, opt=O.Options(max_iter=1, **NOPLATEAU))
+    r64 = qf.instantiate3(dev(V), pr.locs, dev(pr.init_gates), tol=1e-300, max_iter=1, precision=1, **NOPLATEAU)
+    assert np.abs(r64.costs - ref.costs).max() <= 1e-5
+    got = host(r64.all_gates)
+    assert np.abs(got - ref.all_gates).max() <= 1e-4
+    for s in (0, 7):
+        assert abs(O.cost(V, got[s], pr.locs, n) - r64.costs[s]) <= 1e-12
+    r128 = qf.instantiate3(dev(V), pr.locs, dev(pr.init_gates), tol=1e-300, max_iter=1, **NOPLATEAU)
+    assert np.abs(host(r128.all_gates) - ref.all_gates).max() <= 1e-9
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_instantiate3_converges_on_reachable_target(qf, precision):
     """A target built from three-qubit gates (n = 5, 3 gates), four Haar
