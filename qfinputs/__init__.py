@@ -245,6 +245,19 @@ def u3cx_problem(config_id: int, n: int, layers: int, n_starts: int, build_targe
     return locs, kinds, tg, target, init
 
 
+def unreachable_problem(config_id: int, n_starts: int):
+    """Three gates on (0,1),(1,2),(0,1) of 3 qubits against a Haar 8 x 8
+    target (role 0) that such a circuit cannot realise, with Haar initial
+    gates per start (role 1, index = start).  Every start ends on a plateau,
+    at a sweep that depends on its initial gates.  Returns n, locs, target,
+    init."""
+    n = 3
+    locs = np.asarray([(0, 1), (1, 2), (0, 1)], np.int32)
+    V = haar_unitary(rng_for(config_id, ROLE_TARGET, 0), 8)
+    init = np.stack([haar_gates(rng_for(config_id, ROLE_INIT, s), 3) for s in range(n_starts)])
+    return n, locs, V, init
+
+
 def random_builder(rng: np.random.Generator, n_starts: int, n: int) -> np.ndarray:
     """Generic complex test matrices (S, N, N) with entries ~ CN(0, 1/N)."""
     N = 1 << n

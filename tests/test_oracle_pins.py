@@ -376,6 +376,89 @@ def test_nan_start_is_frozen():
     assert res.best_start == 1 and res.status == O.STATUS_CONVERGED and not np.isfinite(res.costs[0])
 
 
+@pytest.mark.parametrize("cfg,n_starts", [(45, 3), (49, 4)])
+def test_multistart_waits_for_every_plateau_and_plateaued_starts_keep_sweeping(cfg, n_starts):
+    """Sec. IV-A: with parallel multistarts the plateau stop is taken only when
+    every start has hit a plateau.  Sec. V-A: a start whose plateau test has
+    fired keeps iterating with the others.  Starts are independent runs in
+    lockstep, so the job's length is the longest solo plateau sweep, and each
+    start's cost column equals its own run for that many sweeps with the
+    plateau tests switched off.  A start that has hit a plateau stays counted
+    as plateaued even when its test stops firing at a later sweep (config
+    49: counting only the starts whose test fires in the current sweep would
+    run to sweep 95).  Config 45's starts plateau at sweeps 35, 7 and 13;
+    config 49's at 13, 10, 12 and 22."""
+    n, locs, V, init = I.unreachable_problem(cfg, n_starts)
+    S = n_starts
+    solo = [O.instantiate(V, init[s], locs, n, tol=1e-10) for s in range(S)]
+    ks = [r.sweeps for r in solo]
+    assert all(r.status == O.STATUS_PLATEAU for r in solo)
+    assert min(ks) + 5 < max(ks)  # the case is staggered
+    K = max(ks)
+    fixed = [O.instantiate(V, init[s], locs, n, tol=1e-10,
+                           opt=O.Options(max_iter=K, diff_tol_r=0.0, long_diff_count=0)) for s in range(S)]
+    multi = O.instantiate(V, init, locs, n, tol=1e-10)
+    assert multi.status == O.STATUS_PLATEAU and multi.sweeps == K
+    for s in range(S):
+        np.testing.assert_allclose(multi.history[:, s], fixed[s].history[:, 0], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(multi.all_gates[s], fixed[s].all_gates[0], rtol=0, atol=1e-11)
+    # the earliest plateau's start went on improving after its test fired
+    s0 = int(np.argmin(ks))
+    assert multi.history[ks[s0], s0] - multi.history[K, s0] > 1e-9
+    assert np.abs(multi.all_gates[s0] - solo[s0].all_gates[0]).max() > 1e-9
+    assert multi.best_start == int(np.argmin(multi.costs))
+    # the same rule in definition mode (no circuit tensor) stops at the same sweep
+    dfn = O.instantiate(V, init, locs, n, tol=1e-10, mode="definition")
+    assert dfn.sweeps == K and dfn.status == O.STATUS_PLATEAU
+
+
+def test_reset_iter_rebuilds_the_circuit_tensor_before_the_cost(monkeypatch):
+    """Sec. III-A-2 (reset_iter): the circuit tensor accumulates error from the
+    apply / un-apply pairs, so every reset_iter sweeps it is recomputed from
+    the gates; the cost of that sweep is then read from the fresh tensor.  A
+    drift is planted after every sweep (the tensor scaled by 1 + 1e-7: the
+    SVD step is scale invariant, so the gates follow the undisturbed
+    trajectory and only the tensor's trace is off).  The costs read at
+    multiples of reset_iter are then the from-scratch costs; the others carry
+    the drift; with resets off every sweep carries it."""
+    pr = I.config1()
+    orig = O.BuilderOracle.sweep
+
+    def drifting_sweep(self, record=None, active=None):
+        orig(self, record, active)
+        self.X = self.X * (1.0 + 1e-7)
+
+    monkeypatch.setattr(O.BuilderOracle, "sweep", drifting_sweep)
+    kw = dict(max_iter=7, diff_tol_r=0.0, long_diff_count=0)
+    ref = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-300, mode="definition",
+                        opt=O.Options(**kw))
+    got = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-300, opt=O.Options(reset_iter=3, **kw))
+    off = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-300, opt=O.Options(reset_iter=0, **kw))
+    np.testing.assert_allclose(got.all_gates, ref.all_gates, rtol=0, atol=1e-12)
+    d = np.abs(got.history[:, 0] - ref.history[:, 0])
+    for i in range(1, 8):
+        if i % 3 == 0:
+            assert d[i] <= 1e-13, (i, d[i])
+        else:
+            assert d[i] > 1e-9, (i, d[i])
+    assert np.all(np.abs(off.history[1:, 0] - ref.history[1:, 0]) > 1e-9)
+    # drift grows sweep by sweep until a reset clears it
+    assert d[2] > d[1] and d[5] > d[4]
+
+
+def test_builder_with_default_resets_tracks_definition_mode_across_sweep_40():
+    """Sec. III-A-2 default reset_iter = 40: over 45 sweeps the circuit tensor
+    (reset after sweep 40) and from-scratch environments give the same cost
+    history and gates."""
+    pr = I.config1()
+    kw = dict(max_iter=45, diff_tol_r=0.0, long_diff_count=0)
+    b = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-300, opt=O.Options(**kw))
+    d = O.instantiate(pr.target, pr.init_gates, pr.locs, pr.n, tol=1e-300, mode="definition", opt=O.Options(**kw))
+    assert b.sweeps == 45 and d.sweeps == 45
+    np.testing.assert_allclose(b.history, d.history, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(b.all_gates, d.all_gates, rtol=0, atol=1e-10)
+
+
 def test_default_hyperparameters_match_paper():
     with open(os.path.join(GOLDEN, "default_hyperparameters.json")) as f:
         ref = json.load(f)
@@ -823,3 +906,32 @@ def test_k3_fixed_point_and_convergence():
         np.testing.assert_allclose(E, (1 << (n - 3)) * pr.target_gates[g].conj().T, atol=1e-12)
     r = O.instantiate(pr.target, pr.init_gates, pr.locs, n, tol=1e-10, opt=O.Options(max_iter=2000))
     assert r.status == O.STATUS_CONVERGED and r.costs[r.best_start] < 1e-10
+
+
+# ---------------------------------------------------------------- stored trajectories
+
+def test_stored_full_size_trajectories_satisfy_the_invariants():
+    """The full-size one-sweep trajectories under tests/golden/ (written by
+    make_sweep_trajectories.py from the oracle) obey what the paper fixes:
+    every new gate is unitary (Eq. opt_u), after each beta = 0 update the
+    trace is real, non-negative and never decreases in modulus (Sec. III-A-1),
+    the first update of the second half reproduces the gate just set
+    (turnaround of Alg. 1), the trace equals Tr(E u_new) of that update, and
+    the stored cost is 1 - |Tr| / N of the last update."""
+    gd = np.load(os.path.join(GOLDEN, "n12_brickwall8_sweep1.npz"), allow_pickle=False)
+    N, p = 1 << 12, 44
+    U, E, T = gd["gate"], gd["env"], gd["trace"]
+    assert U.shape == (2 * p, 4, 4) and [tuple(o) for o in gd["order"][:2]] == [(p - 1, 0), (p - 2, 0)]
+    eye = np.eye(4)
+    for j in range(2 * p):
+        assert np.abs(U[j].conj().T @ U[j] - eye).max() < 1e-12
+        assert abs(T[j].imag) <= 1e-12 * N and T[j].real >= 0
+        assert abs(np.trace(E[j] @ U[j]) - T[j]) <= 1e-11 * N
+        if j:
+            assert abs(T[j]) >= abs(T[j - 1]) - 1e-12 * N
+    np.testing.assert_allclose(U[p], U[p - 1], atol=1e-12)
+    assert abs(float(gd["cost1"]) - (1 - abs(T[-1]) / N)) < 1e-12
+    assert float(gd["cost1"]) < float(gd["cost0"])
+    g10 = np.load(os.path.join(GOLDEN, "n10_brickwall10_s16_sweep1.npz"), allow_pickle=False)
+    assert g10["history"].shape == (2, 3) and np.all(g10["history"][1] < g10["history"][0])
+    np.testing.assert_allclose(g10["history"][1], g10["costs"], atol=1e-12)
