@@ -333,6 +333,24 @@ def test_config2_c64(qf, mode):
     assert np.abs(res.history[1] - ref.history[1]).max() <= 1e-5
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("cfg,n_starts", [(45, 3), (49, 4)])
+def test_staggered_plateaus_match_oracle(qf, mode, cfg, n_starts):
+    """Starts on an unreachable target whose plateau tests fire at different
+    sweeps (config 45: 35, 7, 13; config 49: 13, 10, 12, 22, one of whose
+    tests fires and later stops firing): the job runs until every start has
+    hit a plateau, plateaued starts keep sweeping, and sweeps, status, best
+    start, the whole cost history and the final costs equal the oracle's."""
+    n, locs, V, init = I.unreachable_problem(cfg, n_starts)
+    res = qf.instantiate(dev(V), locs, dev(init), tol=1e-10, mode=mode, precision=0, history_rows=200)
+    ref = O.instantiate(V, init, locs, n, tol=1e-10)
+    assert ref.status == O.STATUS_PLATEAU
+    assert res.sweeps == ref.sweeps and res.status == ref.status and res.best_start == ref.best_start
+    assert np.abs(res.history - ref.history).max() <= C128_TOL
+    assert np.abs(res.costs - ref.costs).max() <= C128_TOL
+    assert np.abs(host(res.all_gates) - ref.all_gates).max() <= 1e-8
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_n10_streaming_two_sweeps(qf, precision):
     """Full-size n = 10 brick-wall (45 gates), two starts, two sweeps."""
@@ -367,6 +385,78 @@ def test_n12_one_sweep_properties(qf):
     rows = [5, 3000]
     ref = O.builder_rows(V, g, pr.locs, 12, rows)
     assert np.abs(host(X[0, rows]) - ref).max() < C128_TOL
+
+
+def _golden(name):
+    import os
+    return np.load(os.path.join(os.path.dirname(__file__), "golden", name), allow_pickle=False)
+
+
+def test_n12_sweep_matches_oracle_update_by_update(qf):
+    """Full-size n = 12 brick-wall (44 gates, 4096 x 4096 builder), complex128:
+    every one of the 88 updates of the first TwoSidedSweep (environment, new
+    gate, trace of the circuit tensor) against the oracle's builder mode
+    (values stored by tests/golden/make_sweep_trajectories.py)."""
+    gd = _golden("n12_brickwall8_sweep1.npz")
+    pr = I.config5(n_starts=1)
+    N = 1 << pr.n
+    X = qf.build(dev(pr.target), pr.locs, dev(pr.init_gates), torch.complex128)
+    c0, _ = qf.cost(X)
+    assert abs(host(c0)[0] - float(gd["cost0"])) <= C128_TOL
+    G = dev(pr.init_gates.copy())
+    for j, (g, half) in enumerate(gd["order"]):
+        gcol = G[:, g].contiguous()
+        _, env = qf.update_gate(X, tuple(pr.locs[g]), int(half), gcol, 0.0, want_env=True)
+        G[:, g] = gcol
+        E_ref = gd["env"][j]
+        assert np.abs(host(env)[0] - E_ref).max() <= C128_TOL * max(1.0, np.abs(E_ref).max()), (j, g, half)
+        assert np.abs(host(gcol)[0] - gd["gate"][j]).max() <= 1e-9, (j, g, half)
+        _, tr = qf.cost(X)
+        assert abs(host(tr)[0] - gd["trace"][j]) <= C128_TOL * N, (j, g, half)
+    assert np.abs(host(G)[0] - gd["gates1"]).max() <= 1e-9
+    del X
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_n12_instantiate_one_sweep_matches_oracle(qf, precision):
+    """qf_instantiate on the n = 12 workload for one sweep (streaming, one
+    start): complex128 cost history, FP64 final cost and gates to the
+    complex128 bar; complex64 cost after the sweep to 1e-5, its final cost an
+    FP64 re-evaluation of its own gates (unitary to 1e-12)."""
+    gd = _golden("n12_brickwall8_sweep1.npz")
+    pr = I.config5(n_starts=1)
+    res = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-8, mode=2, precision=precision,
+                         max_iter=1, diff_tol_r=0.0, long_diff_count=0, history_rows=2)
+    hist_ref = np.array([float(gd["cost0"]), float(gd["cost1"])])
+    g = host(res.all_gates)[0]
+    assert np.abs(np.conj(np.swapaxes(g, -1, -2)) @ g - np.eye(4)).max() < 1e-12
+    if precision == 0:
+        assert np.abs(res.history[:, 0] - hist_ref).max() <= C128_TOL
+        assert abs(res.costs[0] - float(gd["cost1"])) <= C128_TOL
+        assert np.abs(g - gd["gates1"]).max() <= 1e-9
+    else:
+        assert np.abs(res.history[:, 0] - hist_ref).max() <= C64_REL
+        assert abs(res.costs[0] - float(gd["cost1"])) <= C64_REL
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_n10_s16_default_schedule_matches_oracle(qf, precision):
+    """The headline launch configuration (n = 10, 45 gates, 16 starts, the
+    default streaming schedule with environment steps fused beside other
+    groups' passes on two streams) for one sweep: starts 0, 7 and 15 against
+    the oracle (values stored by tests/golden/make_sweep_trajectories.py)."""
+    gd = _golden("n10_brickwall10_s16_sweep1.npz")
+    pr = I.config3(n_starts=16)
+    res = qf.instantiate(dev(pr.target), pr.locs, dev(pr.init_gates), tol=1e-300, precision=precision,
+                         max_iter=1, diff_tol_r=0.0, long_diff_count=0, history_rows=2)
+    st = list(gd["starts"])
+    tol = C128_TOL if precision == 0 else C64_REL
+    assert np.abs(res.history[:, st] - gd["history"]).max() <= tol
+    assert np.abs(res.costs[st] - gd["costs"]).max() <= tol
+    if precision == 0:
+        assert np.abs(host(res.all_gates)[st] - gd["gates"]).max() <= 1e-8
 
 
 @pytest.mark.parametrize("S", [1, 3, 16])
