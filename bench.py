@@ -66,11 +66,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion", "u3cx", "k3"], default=None,
+    ap.add_argument("--probe", choices=["copy", "batch", "gradient", "deletion", "u3cx", "k3", "n12"], default=None,
                     help="copy: only a plain device copy of known size (traffic-counter calibration); "
                          "batch: only the 4096-block batched workload; gradient: only the n = 12 gradient "
                          "and L-BFGS workload; deletion: only the gate-deletion sweep; u3cx: only the U3 + CNOT "
-                         "instantiations; k3: only the three-qubit-gate workloads")
+                         "instantiations; k3: only the three-qubit-gate workloads; n12: only the n = 12 workloads "
+                         "(one start, and four starts beyond the MALL)")
     ap.add_argument("--pass-forms", default=None,
                     help="A,B: fix the complex64 pass form at n = 10 for gate class 0 (A) and 1 (B) instead of "
                          "tuning it (-1 register-direct, -2 micro-tile, 256/512/1024 LDS tile); for counter runs, "
@@ -106,17 +107,22 @@ def brickwall_problem(qf, torch, cfg_id, n, layers, starts, build_on_gpu):
     return pr, V, init
 
 
-def timed_sweeps(qf, torch, V, locs, init, precision, sweeps, warmup, timing=False):
-    """Wall time of one qf_instantiate call running exactly `sweeps` sweeps
-    (plateau tests off, tolerance unreachable)."""
+def timed_sweeps(qf, torch, V, locs, init, precision, sweeps, warmup, timing=False, reps=1, history_rows=0):
+    """Median wall time of `reps` qf_instantiate calls, each running exactly
+    `sweeps` sweeps (plateau tests off, tolerance unreachable), after one
+    untimed call of `warmup` sweeps.  Returns (median seconds, last result,
+    every call's seconds)."""
     kw = dict(tol=1e-300, precision=precision, mode=2, diff_tol_r=0.0, long_diff_count=0)
     if warmup > 0:
         qf.instantiate(V, locs, init, max_iter=warmup, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = qf.instantiate(V, locs, init, max_iter=sweeps, timing=timing, **kw)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, res
+    times, res = [], None
+    for _ in range(max(1, reps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = qf.instantiate(V, locs, init, max_iter=sweeps, timing=timing, history_rows=history_rows, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times)), res, times
 
 
 def copy_probe(torch):
@@ -134,6 +140,25 @@ def copy_probe(torch):
     dt = time.perf_counter() - t0
     print(json.dumps({"probe": "copy", "bytes_per_launch": n, "launches": 10,
                       "GBps_read_plus_write": 2 * n * 10 / dt / 1e9}), flush=True)
+
+
+def rmw_ceiling(torch, nbytes, reps=20) -> float:
+    """Measured in-place read-modify-write bandwidth (GB/s, read + write) of a
+    plain elementwise kernel over `nbytes` of float32: the device's practical
+    ceiling for a pass that reads and writes every byte once.  Median of
+    `reps` launches timed with events on the current stream."""
+    x = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        x.add_(1.0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        x.add_(1.0)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del x
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def batch_workload(qf, torch) -> dict:
@@ -280,25 +305,90 @@ def deletion_workload(qf, torch) -> dict:
 
 
 def cpu_baseline(n_sweeps=3):
-    """The FP64 oracle (builder mode) on the host: 3 sweeps of one start of the
-    n = 10 headline problem."""
+    """The FP64 oracle (builder mode) on the host: `n_sweeps` sweeps of start
+    0 of the n = 10 headline problem on all of the BLAS threads, then the same
+    sweeps on one thread.  Returns the rates and the oracle's cost after each
+    sweep (the reference the GPU's cost history is compared against)."""
     import oracle as O
     import qfinputs as I
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     pr = I.config3(n_starts=1)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     t0 = time.perf_counter()
     b = O.BuilderOracle(pr.target, pr.init_gates, pr.locs, pr.n)
     t_init = time.perf_counter() - t0
+    hist = [float(b.costs()[0])]
     t0 = time.perf_counter()
     for _ in range(n_sweeps):
         b.sweep()
+        hist.append(float(b.costs()[0]))
     dt = time.perf_counter() - t0
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        b1 = O.BuilderOracle(pr.target, pr.init_gates, pr.locs, pr.n)
+        t0 = time.perf_counter()
+        for _ in range(n_sweeps):
+            b1.sweep()
+        dt1 = time.perf_counter() - t0
     return {"value": n_sweeps / dt, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"n=10 brick-wall depth 10 (45 gates), 1 start, {n_sweeps} sweeps of the FP64 NumPy "
-                      f"builder-mode oracle ({dt:.1f} s; builder construction {t_init:.1f} s not counted); "
-                      f"CPU: {cpu_model()}",
-            "seconds": dt}
+            "sample": f"n=10 brick-wall depth 10 (45 gates), start 0, {n_sweeps} sweeps of the FP64 NumPy "
+                      f"builder-mode oracle ({dt:.1f} s on {threads} BLAS threads; builder construction "
+                      f"{t_init:.1f} s not counted); CPU: {cpu_model()}",
+            "one_thread": {"value": round(n_sweeps / dt1, 4), "unit": "start-sweeps/s", "cores": 1,
+                           "seconds": round(dt1, 2)},
+            "seconds": dt, "history": hist, "final_gates": b.gates[0].copy()}
+
+
+def n12_workload(qf, torch, K3) -> dict:
+    """n = 12 brick-wall of depth 8 (44 gates): one start in both precisions
+    (sweeps/s over the whole call, no per-kernel instrumentation; the pass's
+    GB/s from a separate timing call), then four starts in complex64, whose
+    512 MiB of builders do not fit in the 256 MB MALL: the clean HBM point."""
+    out = {}
+    pr12, V12, init12 = brickwall_problem(qf, torch, 5, 12, 8, 4, build_on_gpu=True)
+    N = 1 << 12
+    one = init12[:1].contiguous()
+    d12, _, _ = timed_sweeps(qf, torch, V12, pr12.locs, one, 1, K3, 1, reps=3)
+    _, r12, _ = timed_sweeps(qf, torch, V12, pr12.locs, one, 1, K3, 0, timing=True)
+    t12 = r12.timing
+    b12 = 2 * N * N * 8
+    a12 = b12 / (t12["pass_ms"] / max(1, t12["pass_launches"]) * 1e-3) / 1e9
+    out["n12_c64_sweeps_per_s"] = round(K3 / d12, 3)
+    out["n12_c64_pass_GBps"] = round(a12, 1)
+    out["n12_c64_env_us"] = round(1e3 * t12["env_ms"] / max(1, t12["env_launches"]), 2)
+    out["n12_c64_sweep_frac"] = round(2 * pr12.n_gates * b12 * K3 / d12 / 1e9 / HBM_PEAK_GBS, 4)
+    d12b, _, _ = timed_sweeps(qf, torch, V12, pr12.locs, one, 0, K3, 1, reps=3)
+    out["n12_c128_sweeps_per_s"] = round(K3 / d12b, 3)
+    out["n12_c64_over_c128_speedup"] = round(d12b / d12, 3)
+    S4 = 4
+    d4, _, _ = timed_sweeps(qf, torch, V12, pr12.locs, init12, 1, K3, 1, reps=3)
+    _, r4, _ = timed_sweeps(qf, torch, V12, pr12.locs, init12, 1, K3, 0, timing=True)
+    t4 = r4.timing
+    b4 = S4 * b12
+    a4 = b4 / (t4["pass_ms"] / max(1, t4["pass_launches"]) * 1e-3) / 1e9
+    rmw512 = rmw_ceiling(torch, b4 // 2)
+    out["n12_s4_c64_start_sweeps_per_s"] = round(S4 * K3 / d4, 3)
+    out["n12_s4_c64_pass_GBps"] = round(a4, 1)
+    out["n12_s4_c64_pass_frac"] = round(a4 / HBM_PEAK_GBS, 4)
+    out["n12_s4_c64_sweep_frac"] = round(2 * pr12.n_gates * b4 * K3 / d4 / 1e9 / HBM_PEAK_GBS, 4)
+    out["n12_s4_rmw_ceiling_GBps"] = round(rmw512, 1)
+    out["n12_s4_c64_pass_frac_of_rmw_ceiling"] = round(a4 / rmw512, 4)
+    return out
+
+
+def oracle_error(qf, torch, V, pr, init, cb) -> dict:
+    """The GPU's cost after each of the CPU leg's sweeps against the FP64
+    oracle's (start 0 of the headline problem): complex64 intermediates
+    (bar 1e-5) and complex128 (bar 1e-10), and the FP64 final cost of each."""
+    K = len(cb["history"]) - 1
+    ref = np.asarray(cb["history"])
+    out = {"sweeps": K, "start": 0}
+    for prec, tag in ((1, "c64"), (0, "c128")):
+        r = qf.instantiate(V, pr.locs, init[:1].contiguous(), tol=1e-300, precision=prec, mode=2,
+                           diff_tol_r=0.0, long_diff_count=0, max_iter=K, history_rows=K + 1)
+        out[f"{tag}_max_abs_cost_diff"] = float(np.abs(r.history[:, 0] - ref).max())
+        out[f"{tag}_final_cost_diff"] = float(abs(r.costs[0] - ref[-1]))
+        out[f"{tag}_max_abs_gate_diff"] = float(np.abs(r.all_gates[0].cpu().numpy() - cb["final_gates"]).max())
+    return out
 
 
 def main():
@@ -332,6 +422,9 @@ def main():
     if args.probe == "deletion":
         print(json.dumps(deletion_workload(qf, torch)), flush=True)
         return
+    if args.probe == "n12":
+        print(json.dumps(n12_workload(qf, torch, max(2, args.steps // 4))), flush=True)
+        return
 
     K, W = max(1, args.steps), max(0, args.warmup)
     if args.pass_forms:
@@ -342,17 +435,20 @@ def main():
     pr, V, init = brickwall_problem(qf, torch, 3, n, layers, S, build_on_gpu=False)
     N = 1 << n
 
-    # ---- headline: complex64 builder + FP64 SVD step / tests / final cost
-    dt, res = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, W)
+    # ---- headline: complex64 builder + FP64 SVD step / tests / final cost;
+    # median of 5 calls of exactly K sweeps each
+    dt, res, calls = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, W, reps=5)
     value = S * K / dt
+    sweep_bytes = 2 * pr.n_gates * 2 * S * N * N * 8   # 2p updates, each one read + one write of every builder
     # ---- dominant kernel (fused remove/re-apply pass), HIP events in the library
-    _, rt = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, 0, timing=True)
+    _, rt, _ = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, 0, timing=True)
     tm = rt.timing
     pass_bytes = 2 * S * N * N * 8          # read + write of every builder, complex64
     pass_avg_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
     achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
     env_avg_us = 1e3 * tm["env_ms"] / max(1, tm["env_launches"])
     sweep_loop_rate = S * K / (tm["sweep_ms"] * 1e-3) if tm["sweep_ms"] > 0 else None
+    rmw128 = rmw_ceiling(torch, pass_bytes // 2)
 
     out = {
         "metric": "sweeps/sec (n=10,12) + converged instantiations/sec; % of HBM roofline",
@@ -368,16 +464,25 @@ def main():
         "dtype": "c64 builder (fp32 complex) + f64 SVD step, tests and final cost",
         "data": "synthetic: seeded Haar-random U(4) brick-wall targets and Haar initial gates",
         "config": {"workload": "n10_brickwall10_p45_s16_c64", "n_qubits": n, "n_gates": pr.n_gates,
-                   "starts": S, "builder": "1024x1024 complex64 per start", "parallelism": "multistarts"},
+                   "starts": S, "builder": "1024x1024 complex64 per start", "parallelism": "multistarts",
+                   "timed_calls": 5, "call_seconds": [round(x, 5) for x in calls]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "fused remove + re-apply pass, complex64, 16 builders per launch (register-direct "
                                "k_pass_block, micro-tile k_pass_micro or LDS-tiled k_pass, as tuned per gate class); "
-                               "one read + one write of every builder entry",
+                               "one read + one write of every builder entry; timed alone (all starts in one "
+                               "group, kernel-stamped HIP events) in a second call of the same K sweeps",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
                      "launches_timed": tm["pass_launches"], "pass_form_mid_gate": tm.get("pass_tcols"),
                      "traffic_source": "profiles/k_pass_n10_s16_c64_traffic.json (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
-                                       "scaled by a 256 MiB copy)"},
+                                       "scaled by a 256 MiB copy)",
+                     "sweep_bytes": sweep_bytes,
+                     "sweep_achieved": round(sweep_bytes * value / S / 1e9, 1),
+                     "sweep_frac": round(sweep_bytes * value / S / 1e9 / HBM_PEAK_GBS, 4),
+                     "rmw_ceiling_GBps": round(rmw128, 1),
+                     "frac_of_rmw_ceiling": round(achieved / rmw128, 4),
+                     "mall_note": "the 128 MiB builder set fits in the 256 MB MALL (Infinity Cache), so this "
+                                  "working set can exceed HBM peak; extra.n12_s4_* is the 512 MiB point beyond it"},
         "breakdown": {"pass_avg_us": round(1e3 * pass_avg_ms, 2), "env_svd_avg_us": round(env_avg_us, 2),
                       "sweep_loop_start_sweeps_per_s": round(sweep_loop_rate, 2) if sweep_loop_rate else None,
                       "final_best_cost": float(np.min(res.costs))},
@@ -387,21 +492,12 @@ def main():
         extra = {}
         # complex128 form of the same problem
         K2 = max(2, K // 2)
-        dt128, _ = timed_sweeps(qf, torch, V, pr.locs, init, 0, K2, 1)
+        dt128, _, _ = timed_sweeps(qf, torch, V, pr.locs, init, 0, K2, 1, reps=3)
         extra["n10_c128_start_sweeps_per_s"] = round(S * K2 / dt128, 2)
         extra["n10_c64_over_c128_speedup"] = round(value / (S * K2 / dt128), 3)
-        # n = 12, one start
-        pr12, V12, init12 = brickwall_problem(qf, torch, 5, 12, 8, 1, build_on_gpu=True)
-        K3 = max(2, K // 4)
-        d12, r12 = timed_sweeps(qf, torch, V12, pr12.locs, init12, 1, K3, 1, timing=True)
-        t12 = r12.timing
-        b12 = 2 * (1 << 24) * 8
-        a12 = b12 / (t12["pass_ms"] / max(1, t12["pass_launches"]) * 1e-3) / 1e9
-        extra["n12_c64_sweeps_per_s"] = round(K3 / d12, 3)
-        extra["n12_c64_pass_GBps"] = round(a12, 1)
-        d12b, _ = timed_sweeps(qf, torch, V12, pr12.locs, init12, 0, K3, 1)
-        extra["n12_c128_sweeps_per_s"] = round(K3 / d12b, 3)
-        del V12, init12
+        # n = 12, one start, then four starts (512 MiB of complex64 builders:
+        # beyond the MALL)
+        extra.update(n12_workload(qf, torch, max(2, K // 4)))
         # n = 6 and n = 3 full instantiations (resident mode)
         import qfinputs as I
         p2 = I.config2()
@@ -441,9 +537,10 @@ def main():
 
     if not args.no_cpu:
         cb = cpu_baseline()
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "one_thread")}
         out["cpu_baseline"]["value"] = round(cb["value"], 4)
         out["cpu_baseline"]["unit"] = "start-sweeps/s"
+        out["oracle_error"] = oracle_error(qf, torch, V, pr, init, cb)
     print(json.dumps(out), flush=True)
 
 

@@ -180,13 +180,15 @@ typedef struct {
 } qf_stats;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
- * NULL = the device's null stream).  Allocates a few KiB of pinned host
- * memory for per-sweep cost read-back.  qf_instantiate works in the caller's
- * workspace; the stand-alone step calls (qf_environment, qf_update_gate) use
- * a small device scratch owned by the context (partial sums of the
- * environment, a few KiB per builder), allocated on first use and grown on
- * demand; qf_destroy frees it.  A context may be used by one host thread at
- * a time. */
+ * NULL = the device's null stream).  This is the only call that allocates:
+ * 32 KiB of pinned host memory for per-sweep cost read-back, a device
+ * scratch of about 2.3 MiB for the stand-alone step calls (qf_environment,
+ * qf_update_gate: environment partial sums, arrival counters and u_old; they
+ * process their builders in chunks so the scratch never grows), a 4 x 4
+ * identity operand, and the library's three auxiliary streams (default
+ * priority) and events.  qf_instantiate and the other drivers work in the
+ * caller's workspace.  qf_destroy frees everything.  A context may be used
+ * by one host thread at a time. */
 int qf_create(qf_ctx** ctx, int device, void* hip_stream);
 int qf_destroy(qf_ctx* ctx);
 int qf_set_stream(qf_ctx* ctx, void* hip_stream);
@@ -391,15 +393,33 @@ typedef struct {
 } qf_lbfgs_options;
 void qf_lbfgs_options_default(qf_lbfgs_options* o);
 size_t qf_lbfgs_workspace_size(int n, int n_gates, int n_starts, const qf_lbfgs_options* opt);
+/* Outcome of qf_lbfgs (host memory). */
+typedef struct {
+  int32_t iterations;    /* L-BFGS iterations run (lockstep over starts) */
+  int32_t evaluations;   /* cost + gradient evaluations, line-search trials included */
+  int32_t best_start;    /* start with the smallest final cost, lowest index on ties */
+  int32_t status;        /* QF_CONVERGED, QF_PLATEAU (every start stopped) or QF_MAX_ITER */
+  double best_cost;      /* final cost of the best start */
+  double elapsed_ms;     /* wall time of the call */
+  double* cost_history;  /* in, optional (host): rows x n_starts doubles; row i
+                            receives the costs after iteration i (row 0 = theta0) */
+  int32_t cost_history_rows;
+} qf_lbfgs_result;
 /* theta0, theta_out: device, n_starts x n_gates x 15 FP64;  out_costs: host,
  * n_starts final costs.  The job stops when a start's cost falls below tol,
- * when every start has stopped, or after max_iter iterations.  stats (optional):
- * sweeps = iterations, best_start, status (QF_CONVERGED / QF_PLATEAU = every
- * start stopped / QF_MAX_ITER), best_cost, elapsed_ms, cost_history as in
- * qf_instantiate (rows = iterations + 1), pass_launches = evaluations. */
+ * when every start has stopped, or after max_iter iterations.  result:
+ * optional host qf_lbfgs_result. */
 int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const double* theta0,
              int n_starts, double tol, const qf_lbfgs_options* opt, void* workspace, size_t ws_bytes,
-             double* theta_out, double* out_costs, qf_stats* stats);
+             double* theta_out, double* out_costs, qf_lbfgs_result* result);
+
+/* Outcome of qf_delete_gates (host memory). */
+typedef struct {
+  int32_t attempts;    /* deletions tried (one re-instantiation each) */
+  int32_t deleted;     /* deletions kept */
+  int32_t sweeps;      /* sweeps of all the attempts' instantiations together */
+  double elapsed_ms;   /* wall time of the call */
+} qf_delete_result;
 
 /* Gate deletion (the re-synthesis workflow QFactor drives in Sec. V,
  * "Circuit Optimization Scaling"): one uni-directional sweep over the gates
@@ -420,15 +440,13 @@ int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t*
  *   out_gates:  device, n_gates x 4 x 4 c128 out: the kept gates in order,
  *               compacted to the front (the rest left unspecified)
  *   out_cost:   host, FP64 cost of the final circuit
- *   stats:      optional: sweeps = total sweeps of all attempts,
- *               n_resets = attempts, n_rechecks = deletions kept,
- *               elapsed_ms
+ *   result:     optional host qf_delete_result
  * Returns QF_EINVAL if `gates` does not realise target within tol. */
 size_t qf_delete_gates_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt);
 int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
                     const void* gates, const void* pool, int n_starts, double tol, const qf_options* opt,
                     void* workspace, size_t ws_bytes, int32_t* keep, void* out_gates, double* out_cost,
-                    qf_stats* stats);
+                    qf_delete_result* result);
 
 #ifdef __cplusplus
 }

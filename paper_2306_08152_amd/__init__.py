@@ -17,7 +17,7 @@ _API = ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "c
         "default_options", "workspace_size", "Result", "instantiate_batch", "pack_batch",
         "batch_workspace_size", "BatchResult", "gradient", "cost_fn", "su4_gates", "su4_vjp", "su4",
         "lbfgs", "lbfgs_options", "LbfgsResult", "set_pass_tile", "delete_gates", "DeletionResult",
-        "instantiate3", "optimize_gate3")
+        "instantiate3", "optimize_gate3", "cost_of_gates")
 
 
 def __getattr__(name):

@@ -65,6 +65,28 @@ class QfStats(ctypes.Structure):
     ]
 
 
+class QfLbfgsResult(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("evaluations", ctypes.c_int32),
+        ("best_start", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("best_cost", ctypes.c_double),
+        ("elapsed_ms", ctypes.c_double),
+        ("cost_history", ctypes.POINTER(ctypes.c_double)),
+        ("cost_history_rows", ctypes.c_int32),
+    ]
+
+
+class QfDeleteResult(ctypes.Structure):
+    _fields_ = [
+        ("attempts", ctypes.c_int32),
+        ("deleted", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("elapsed_ms", ctypes.c_double),
+    ]
+
+
 class QfLbfgsOptions(ctypes.Structure):
     _fields_ = [
         ("history", ctypes.c_int32),
@@ -121,12 +143,12 @@ _SIGS = {
                                                          ctypes.POINTER(QfOptions)]),
     "qf_delete_gates": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, _VP, ctypes.c_int,
                                        ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _I32P, _VP,
-                                       _DP, ctypes.POINTER(QfStats)]),
+                                       _DP, ctypes.POINTER(QfDeleteResult)]),
     "qf_lbfgs_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.POINTER(QfLbfgsOptions)]),
     "qf_lbfgs": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int, ctypes.c_double,
                                 ctypes.POINTER(QfLbfgsOptions), _VP, ctypes.c_size_t, _VP, _DP,
-                                ctypes.POINTER(QfStats)]),
+                                ctypes.POINTER(QfLbfgsResult)]),
 }
 
 _lib = None

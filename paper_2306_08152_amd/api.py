@@ -410,12 +410,24 @@ def gradient(target: torch.Tensor, locs, gates: torch.Tensor, precision: int = n
     return cost_t, grad
 
 
+def cost_of_gates(target: torch.Tensor, locs, gates: torch.Tensor, precision: int = nat.QF_C128) -> torch.Tensor:
+    """Cost of gate sets without a gradient: builders from qf_build, costs
+    from qf_cost.  gates (S, p, 4, 4) -> (S,) float64, or (p, 4, 4) -> scalar."""
+    g4, squeeze = _gates4(gates)
+    X = build(target, locs, g4.contiguous(), torch.complex64 if precision == nat.QF_C64 else torch.complex128)
+    c, _ = cost(X)
+    return c[0] if squeeze else c
+
+
 class _CostFn(torch.autograd.Function):
     """Delta(gates) with the backward from qf_gradient (forward and gradient
-    are taken together; the gradient is kept for the backward)."""
+    are taken together when the gates need a gradient, and the gradient is
+    kept for the backward; otherwise only the cost is computed)."""
 
     @staticmethod
     def forward(ctx, gates, target, locs, precision):
+        if not ctx.needs_input_grad[0]:
+            return cost_of_gates(target, locs, gates.detach(), precision)
         c, G = gradient(target, locs, gates.detach(), precision)
         ctx.save_for_backward(G)
         return c
@@ -515,7 +527,7 @@ def lbfgs(target: torch.Tensor, locs, theta0: torch.Tensor, tol: float = 1e-10, 
     workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
     out = torch.empty_like(th)
     costs = (ctypes.c_double * S)()
-    st = nat.QfStats()
+    st = nat.QfLbfgsResult()
     hist = None
     if history_rows > 0:
         hist = np.full((history_rows, S), np.nan, dtype=np.float64)
@@ -524,8 +536,8 @@ def lbfgs(target: torch.Tensor, locs, theta0: torch.Tensor, tol: float = 1e-10, 
     ctx = _ctx(target.device)
     nat.check(lib.qf_lbfgs(ctx, n, _ptr(target), p, _loc(locs), _ptr(th), S, float(tol), ctypes.byref(opt),
                            _ptr(workspace), need, _ptr(out), costs, ctypes.byref(st)), ctx)
-    h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
-    return LbfgsResult(out, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.pass_launches,
+    h = hist[: min(history_rows, st.iterations + 1)] if hist is not None else np.zeros((0, S))
+    return LbfgsResult(out, np.array(costs[:]), st.best_start, st.iterations, st.status, st.evaluations,
                        st.elapsed_ms, h)
 
 
@@ -561,12 +573,12 @@ def delete_gates(target: torch.Tensor, locs, gates: torch.Tensor, pool: torch.Te
     out = torch.empty((p, 4, 4), dtype=torch.complex128, device=target.device)
     keep = (ctypes.c_int32 * p)()
     cost_out = ctypes.c_double()
-    st = nat.QfStats()
+    st = nat.QfDeleteResult()
     ctx = _ctx(target.device)
     nat.check(lib.qf_delete_gates(ctx, n, _ptr(target), p, _loc(locs), _ptr(gates), _ptr(pool), S, float(tol),
                                   ctypes.byref(opt), _ptr(workspace), need, keep, _ptr(out),
                                   ctypes.byref(cost_out), ctypes.byref(st)), ctx)
     km = np.array(keep[:], np.int32)
     kcount = int(km.sum())
-    return DeletionResult(km, out[:kcount].clone(), locs[km == 1], float(cost_out.value), st.n_resets,
-                          st.n_rechecks, st.sweeps, st.elapsed_ms)
+    return DeletionResult(km, out[:kcount].clone(), locs[km == 1], float(cost_out.value), st.attempts,
+                          st.deleted, st.sweeps, st.elapsed_ms)

@@ -26,10 +26,8 @@ struct qf_ctx {
   // of starts concurrently, forked from and joined to `stream` by events.
   hipStream_t aux[kMaxGroups] = {};
   hipEvent_t fork = nullptr, join[kMaxGroups] = {}, stagger[kMaxGroups] = {};
-  double* pinned = nullptr;     // host read-back buffer
-  size_t pinned_count = 0;      // doubles
-  void* scratch = nullptr;      // device scratch for the stand-alone calls
-  size_t scratch_bytes = 0;
+  double* pinned = nullptr;     // host read-back buffer (kPinnedCount doubles)
+  void* scratch = nullptr;      // device scratch of the stand-alone step calls
   // Autotuned pass tile width per (precision, n); 0 = not tuned yet.
   int tuned_tcols[2][2][17] = {};
   double* identity = nullptr;   // one 4x4 c128 identity (tuning operand)
@@ -73,6 +71,22 @@ int fail(qf_ctx* ctx, int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Everything a context allocates is allocated by qf_create: the pinned
+// read-back buffer, the tuner's identity operand and the scratch of the
+// stand-alone step calls, which process their builders in chunks of at most
+// kScratchChunk so that the scratch has a fixed size (environment partial
+// sums for kScratchSlots (builder, workgroup) pairs, arrival counters and
+// u_old of one chunk).  No call allocates afterwards.
+constexpr size_t kPinnedCount = 4096;
+constexpr int kScratchChunk = 1024;
+constexpr size_t kScratchSlots = 4096;
+constexpr size_t kScratchPartials = 0;
+constexpr size_t kScratchCounters = kScratchSlots * 256;
+constexpr size_t kScratchUold = kScratchCounters + (size_t)kScratchChunk * 4;
+constexpr size_t kScratchBytes = kScratchUold + (size_t)kScratchChunk * 256;
+static_assert(kScratchSlots >= (size_t)kScratchChunk * 4 && kScratchSlots >= 256,
+              "a chunk's spread environment must fit: at most max(4 per builder at n = 16, 256) slots");
+
 size_t elem_bytes(int precision) { return precision == QF_C64 ? 8 : 16; }
 
 bool valid_loc(int n, const int32_t* loc) {
@@ -105,7 +119,7 @@ Layout make_layout(int n, int p, int S, const qf_options& o, int mode, int histo
   if (mode == QF_MODE_STREAMING) {
     L.X = take((size_t)S * N * N * elem_bytes(o.precision));
     if (o.precision == QF_C64) L.R = take((size_t)S * N * N * 16);
-    L.partials = take((size_t)S * env_workgroups(n) * 16 * 16);
+    L.partials = take((size_t)S * env_workgroups(n, 1) * 16 * 16);
     L.counters = take((size_t)S * 4);
     L.uold = take((size_t)S * 16 * 16);
     L.trace = take((size_t)S * 16);
@@ -169,15 +183,6 @@ int validate_kinds(qf_ctx* ctx, const int32_t* kinds, int count) {
   return QF_OK;
 }
 
-int ensure_pinned(qf_ctx* ctx, size_t count) {
-  if (ctx->pinned_count >= count) return QF_OK;
-  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  ctx->pinned = nullptr;
-  ctx->pinned_count = 0;
-  QF_HIP(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), count * sizeof(double), hipHostMallocDefault));
-  ctx->pinned_count = count;
-  return QF_OK;
-}
 
 int ensure_aux_streams(qf_ctx* ctx) {
   if (ctx->aux[0]) return QF_OK;
@@ -191,18 +196,6 @@ int ensure_aux_streams(qf_ctx* ctx) {
   return QF_OK;
 }
 
-
-int ensure_scratch(qf_ctx* ctx, size_t bytes) {
-  if (ctx->scratch_bytes >= bytes) return QF_OK;
-  QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->scratch) (void)hipFree(ctx->scratch);
-  ctx->scratch = nullptr;
-  ctx->scratch_bytes = 0;
-  QF_HIP(ctx, hipMalloc(&ctx->scratch, bytes));
-  QF_HIP(ctx, hipMemsetAsync(ctx->scratch, 0, bytes, ctx->stream));
-  ctx->scratch_bytes = bytes;
-  return QF_OK;
-}
 
 // Pass form of a gate: the tile width of the LDS-staged pass, kPassDirect
 // for the register-direct one or kPassMicro for the micro-tile register one
@@ -230,12 +223,6 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
   const int cands64[] = {kPassDirect, kPassMicro, 256, 512, 1024}, cands128[] = {kPassDirect, 256, 512};
   const int* cands = precision == QF_C64 ? cands64 : cands128;
   const int nc = precision == QF_C64 ? 5 : 3;
-  if (!ctx->identity) {
-    QF_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->identity), 16 * 16));
-    double id[32] = {};
-    for (int k = 0; k < 4; ++k) id[2 * (5 * k)] = 1.0;
-    QF_HIP(ctx, hipMemcpy(ctx->identity, id, sizeof id, hipMemcpyHostToDevice));
-  }
   const Operand I{ctx->identity, 0, 0};
   for (int cls = 0; cls < 2; ++cls) {
     int& slot = ctx->tuned_tcols[precision == QF_C64][cls][n];
@@ -329,11 +316,13 @@ int cast_to_c64(qf_ctx* ctx, const void* R, void* X, size_t count) {
 }
 
 int read_costs(qf_ctx* ctx, const double* dev, int S, std::vector<double>& out) {
-  int rc = ensure_pinned(ctx, (size_t)S);
-  if (rc) return rc;
-  QF_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, (size_t)S * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  out.assign(ctx->pinned, ctx->pinned + S);
+  out.resize((size_t)S);
+  for (size_t at = 0; at < (size_t)S; at += kPinnedCount) {  // through the fixed pinned buffer
+    const size_t cnt = std::min(kPinnedCount, (size_t)S - at);
+    QF_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev + at, cnt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    QF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::copy(ctx->pinned, ctx->pinned + cnt, out.begin() + (ptrdiff_t)at);
+  }
   return QF_OK;
 }
 
@@ -434,7 +423,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   if (stats && stats->timing) G = 1;
   // Default schedule: two groups on the caller's stream, each launch carrying
   // one group's environment step beside the other group's pass (k_fused).
-  const bool fused = o.stream_groups == 0 && !(stats && stats->timing) && S >= 2 && env_workgroups(n) == 1;
+  const bool fused = o.stream_groups == 0 && !(stats && stats->timing) && S >= 2 && env_min_workgroups(n) == 1;
   constexpr int kFusedPairs = 2;  // pairs of groups, one stream each
   static_assert(kFusedPairs >= 1 && kFusedPairs <= kMaxGroups, "one stream per pair: the caller's and kMaxGroups - 1 own");
   const int pairs = fused ? std::min(kFusedPairs, S / 2) : 0;
@@ -450,7 +439,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     EnvArgs ea{};
   };
   Group grp[2 * kMaxGroups];
-  const uint32_t nwg = env_workgroups(n);
+  const uint32_t nwg_stride = env_workgroups(n, 1);  // partial-sum slots per start
   for (int gi = 0; gi < G; ++gi) {
     Group& q = grp[gi];
     q.s0 = gi * S / G;
@@ -467,8 +456,9 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     ea.uold = uold + (size_t)q.s0 * 32;
     ea.env_out = nullptr;
     ea.frozen = frozen + q.s0;
-    ea.partials = reinterpret_cast<double*>(ws + L.partials) + (size_t)q.s0 * nwg * 32;
+    ea.partials = reinterpret_cast<double*>(ws + L.partials) + (size_t)q.s0 * nwg_stride * 32;
     ea.counters = reinterpret_cast<int32_t*>(ws + L.counters) + q.s0;
+    ea.nwg = (int)env_workgroups(n, q.ns);
   }
 
   KernelTimer timer;
@@ -899,7 +889,7 @@ GradLayout make_grad_layout(int n, int p, int S, int precision) {
   };
   const size_t N = (size_t)1 << n;
   L.X = take((size_t)S * N * N * elem_bytes(precision));
-  L.partials = take((size_t)S * env_workgroups(n) * 16 * 16);
+  L.partials = take((size_t)S * env_workgroups(n, 1) * 16 * 16);
   L.counters = take((size_t)S * 4);
   L.envP = take((size_t)p * S * 16 * 16);
   L.trace = take((size_t)S * 16);
@@ -926,6 +916,7 @@ int run_gradient(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs, 
   ea.do_update = 0;
   ea.partials = reinterpret_cast<double*>(ws + L.partials);
   ea.counters = counters;
+  ea.nwg = (int)env_workgroups(n, S);
   for (int g = p - 1; g >= 0; --g) {
     ea.q0 = locs[2 * g];
     ea.q1 = locs[2 * g + 1];
@@ -1016,8 +1007,19 @@ int qf_create(qf_ctx** out, int device, void* hip_stream) {
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   DeviceGuard dg(device);
-  if (ensure_pinned(ctx, 4096) != QF_OK) {
-    delete ctx;
+  double id[32] = {};
+  for (int k = 0; k < 4; ++k) id[2 * (5 * k)] = 1.0;
+  const bool ok =
+      dg.ok &&
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kPinnedCount * sizeof(double), hipHostMallocDefault) ==
+          hipSuccess &&
+      hipMalloc(&ctx->scratch, kScratchBytes) == hipSuccess &&
+      hipMalloc(reinterpret_cast<void**>(&ctx->identity), sizeof id) == hipSuccess &&
+      hipMemcpy(ctx->identity, id, sizeof id, hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemset(ctx->scratch, 0, kScratchBytes) == hipSuccess &&  // arrival counters start at zero
+      ensure_aux_streams(ctx) == QF_OK;
+  if (!ok) {
+    (void)qf_destroy(ctx);
     return QF_EHIP;
   }
   *out = ctx;
@@ -1115,21 +1117,22 @@ int qf_environment(qf_ctx* ctx, int n, int n_builders, const void* builder, int 
   if (!builder || !env_out) return fail(ctx, QF_EINVAL, "NULL pointer argument");
   if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
   DeviceGuard dg(ctx->device);
-  const size_t part = align_up((size_t)n_builders * env_workgroups(n) * 256);
-  int rc = ensure_scratch(ctx, part + align_up((size_t)n_builders * 4));
-  if (rc) return rc;
-  EnvArgs ea{};
-  ea.n = n;
-  ea.q0 = loc[0];
-  ea.q1 = loc[1];
-  ea.S = n_builders;
-  ea.do_update = 0;
-  ea.env_out = reinterpret_cast<double*>(env_out);
-  ea.partials = reinterpret_cast<double*>(ctx->scratch);
-  ea.counters = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(ctx->scratch) + part);
-  // the scratch layout depends on (n, n_builders): clear the arrival counters
-  QF_HIP(ctx, launch_fill_i32(ctx->stream, ea.counters, 0, (uint32_t)n_builders));
-  QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
+  unsigned char* sc = reinterpret_cast<unsigned char*>(ctx->scratch);
+  const size_t bstride = ((size_t)1 << (2 * n)) * elem_bytes(precision);
+  for (int c0 = 0; c0 < n_builders; c0 += kScratchChunk) {
+    const int cs = std::min(kScratchChunk, n_builders - c0);
+    EnvArgs ea{};
+    ea.n = n;
+    ea.q0 = loc[0];
+    ea.q1 = loc[1];
+    ea.S = cs;
+    ea.nwg = (int)env_workgroups(n, cs);
+    ea.do_update = 0;
+    ea.env_out = reinterpret_cast<double*>(env_out) + (size_t)c0 * 32;
+    ea.partials = reinterpret_cast<double*>(sc + kScratchPartials);
+    ea.counters = reinterpret_cast<int32_t*>(sc + kScratchCounters);  // left zero by every launch
+    QF_HIP(ctx, launch_env(ctx->stream, precision, reinterpret_cast<const unsigned char*>(builder) + c0 * bstride, ea));
+  }
   return QF_OK;
 }
 
@@ -1155,36 +1158,36 @@ int qf_update_gate(qf_ctx* ctx, int n, int n_builders, void* builder, int precis
   if (half != 0 && half != 1) return fail(ctx, QF_EINVAL, "half must be 0 or 1");
   if (!(beta >= 0.0 && beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
   DeviceGuard dg(ctx->device);
-  const size_t part = align_up((size_t)n_builders * env_workgroups(n) * 256);
-  const size_t cnt = align_up((size_t)n_builders * 4);
-  const size_t uo = align_up((size_t)n_builders * 256);
-  int rc = ensure_scratch(ctx, part + cnt + uo);
-  if (rc) return rc;
   unsigned char* sc = reinterpret_cast<unsigned char*>(ctx->scratch);
-  EnvArgs ea{};
-  ea.n = n;
-  ea.q0 = loc[0];
-  ea.q1 = loc[1];
-  ea.S = n_builders;
-  ea.do_update = 1;
-  ea.half = half;
-  ea.beta = beta;
-  ea.gates = reinterpret_cast<double*>(gates);
-  ea.gstride = 16;
-  ea.gidx = 0;
-  ea.uold = reinterpret_cast<double*>(sc + part + cnt);
-  ea.env_out = reinterpret_cast<double*>(env_out);
-  ea.partials = reinterpret_cast<double*>(sc);
-  ea.counters = reinterpret_cast<int32_t*>(sc + part);
-  QF_HIP(ctx, launch_fill_i32(ctx->stream, ea.counters, 0, (uint32_t)n_builders));
-  QF_HIP(ctx, launch_env(ctx->stream, precision, builder, ea));
+  const size_t bstride = ((size_t)1 << (2 * n)) * elem_bytes(precision);
   const PassGeom geo = make_pass_geom(n, loc[0], loc[1], pass_tcols(ctx, precision, n, loc[0], loc[1]));
-  Operand gnew{reinterpret_cast<const double*>(gates), 16, 0};
-  Operand gold{ea.uold, 16, 1};
-  if (half == 0)
-    QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, gold, gnew));
-  else
-    QF_HIP(ctx, launch_pass(ctx->stream, precision, builder, n_builders, geo, gnew, gold));
+  for (int c0 = 0; c0 < n_builders; c0 += kScratchChunk) {
+    const int cs = std::min(kScratchChunk, n_builders - c0);
+    void* Xc = reinterpret_cast<unsigned char*>(builder) + c0 * bstride;
+    EnvArgs ea{};
+    ea.n = n;
+    ea.q0 = loc[0];
+    ea.q1 = loc[1];
+    ea.S = cs;
+    ea.nwg = (int)env_workgroups(n, cs);
+    ea.do_update = 1;
+    ea.half = half;
+    ea.beta = beta;
+    ea.gates = reinterpret_cast<double*>(gates) + (size_t)c0 * 32;
+    ea.gstride = 16;
+    ea.gidx = 0;
+    ea.uold = reinterpret_cast<double*>(sc + kScratchUold);
+    ea.env_out = env_out ? reinterpret_cast<double*>(env_out) + (size_t)c0 * 32 : nullptr;
+    ea.partials = reinterpret_cast<double*>(sc + kScratchPartials);
+    ea.counters = reinterpret_cast<int32_t*>(sc + kScratchCounters);  // left zero by every launch
+    QF_HIP(ctx, launch_env(ctx->stream, precision, Xc, ea));
+    Operand gnew{ea.gates, 16, 0};
+    Operand gold{ea.uold, 16, 1};
+    if (half == 0)
+      QF_HIP(ctx, launch_pass(ctx->stream, precision, Xc, cs, geo, gold, gnew));
+    else
+      QF_HIP(ctx, launch_pass(ctx->stream, precision, Xc, cs, geo, gnew, gold));
+  }
   return QF_OK;
 }
 
@@ -1768,7 +1771,7 @@ size_t qf_lbfgs_workspace_size(int n, int n_gates, int n_starts, const qf_lbfgs_
 
 int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations, const double* theta0,
              int n_starts, double tol, const qf_lbfgs_options* opt, void* workspace, size_t ws_bytes,
-             double* theta_out, double* out_costs, qf_stats* stats) {
+             double* theta_out, double* out_costs, qf_lbfgs_result* stats) {
   if (!ctx) return QF_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   qf_lbfgs_options o;
@@ -1968,17 +1971,11 @@ int qf_lbfgs(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t*
   QF_HIP(ctx, hipStreamSynchronize(st));
   if (status != QF_CONVERGED && f[best] < tol) status = QF_CONVERGED;
   if (stats) {
-    stats->sweeps = it;
+    stats->iterations = it;
+    stats->evaluations = evals;
     stats->best_start = best;
     stats->status = status;
-    stats->n_resets = 0;
-    stats->n_rechecks = 0;
-    stats->mode_used = QF_MODE_STREAMING;
     stats->best_cost = f[best];
-    stats->pass_launches = evals;
-    stats->env_launches = 0;
-    stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
-    stats->pass_tcols = pass_tcols(ctx, o.precision, n, n / 2 - 1, n / 2);
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;
@@ -1994,7 +1991,7 @@ size_t qf_delete_gates_workspace_size(int n, int n_gates, int n_starts, const qf
 int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
                     const void* gates, const void* pool, int n_starts, double tol, const qf_options* opt,
                     void* workspace, size_t ws_bytes, int32_t* keep, void* out_gates, double* out_cost,
-                    qf_stats* stats) {
+                    qf_delete_result* result) {
   if (!ctx) return QF_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   const int p = n_gates, S = n_starts;
@@ -2092,14 +2089,11 @@ int qf_delete_gates(qf_ctx* ctx, int n, const void* target, int n_gates, const i
   QF_HIP(ctx, hipMemcpyAsync(out_gates, cur, kept.size() * 256, hipMemcpyDeviceToDevice, st));
   QF_HIP(ctx, hipStreamSynchronize(st));
   *out_cost = cost_now;
-  if (stats) {
-    stats->sweeps = sweeps;
-    stats->n_resets = attempts;
-    stats->n_rechecks = deleted;
-    stats->best_start = 0;
-    stats->status = QF_CONVERGED;
-    stats->best_cost = cost_now;
-    stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (result) {
+    result->attempts = attempts;
+    result->deleted = deleted;
+    result->sweeps = sweeps;
+    result->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;
 }

@@ -96,11 +96,16 @@ struct EnvArgs {
   double* uold;    // c128 S x 16 (update mode)
   double* env_out; // c128 S x 16, optional
   const int32_t* frozen;  // optional per-start flag: nonzero keeps the gate
-  double* partials;       // c128 S x env_workgroups(n) x 16 (needed when > 1 workgroup)
+  double* partials;       // c128 S x nwg x 16 (needed when nwg > 1)
   int32_t* counters;      // S ints, zero before the first launch; left zero
   int kind;               // qf_gate_kind of the updated gate (update mode)
+  int nwg;                // workgroups per start; 0 = env_workgroups(n, S)
 };
-uint32_t env_workgroups(int n);
+// Workgroups per start of the partial trace: at least env_min_workgroups(n)
+// (more than one for n >= 15); env_workgroups(n, S) spreads a launch of S
+// starts over more of them when S is small (at most env_workgroups(n, 1)).
+uint32_t env_min_workgroups(int n);
+uint32_t env_workgroups(int n, int S);
 // Small fill kernel (used instead of hipMemsetAsync so the enqueued work can
 // be captured in a HIP graph).
 hipError_t launch_fill_i32(hipStream_t st, int32_t* p, int32_t v, uint32_t count);

@@ -581,10 +581,15 @@ hipError_t launch_pass(hipStream_t st, int precision, void* X, int S, const Pass
 }
 
 // k_env: 256 threads = 16 (i,j) pairs x 16 rest lanes; one workgroup covers
-// up to kEnvRestsPerWG rests (every n <= 14 in one workgroup per start, so no
-// cross-workgroup step is needed there).
+// at most kEnvRestsPerWG rests (so n <= 14 fits one workgroup per start).
+// A thread keeps eight loads in flight, so a workgroup takes in
+// kEnvRestsPerRound rests per round of loads.
 constexpr uint32_t kEnvThreads = 256;
 constexpr uint32_t kEnvRestsPerWG = 4096;
+constexpr uint32_t kEnvRestsPerRound = 128;
+// Workgroups of all starts of one launch that the spread aims for: enough to
+// put every start's rests on many CUs when starts are few.
+constexpr uint32_t kEnvSpreadTarget = 256;
 
 // ------------------------------------------------------------------ k_build_init
 
@@ -630,7 +635,7 @@ hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void*
 
 struct EnvDev {
   EnvArgs a;
-  uint32_t N, nrest, b0, b1, rlo, rhi, nwg;
+  uint32_t N, nrest, b0, b1, rlo, rhi, nwg, rests_per_wg;
 };
 
 // Finish one start on the 4 lanes of a quad (lane r = row r): P (16 FP64
@@ -738,8 +743,8 @@ __device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvD
   const uint32_t ij = t & 15u, i = ij >> 2, j = ij & 3u;
   const uint32_t ro = local_off(i, d.b0, d.b1), co = local_off(j, d.b0, d.b1);
   const cx<R>* Xs = X + (size_t)s * d.N * d.N;
-  const uint32_t r_begin = w * kEnvRestsPerWG;
-  const uint32_t r_end = min(d.nrest, r_begin + kEnvRestsPerWG);
+  const uint32_t r_begin = w * d.rests_per_wg;
+  const uint32_t r_end = min(d.nrest, r_begin + d.rests_per_wg);
   constexpr uint32_t kLanes = kEnvThreads / 16;
   cd acc = mk(0.0, 0.0);
   for (uint32_t r0 = r_begin + (t >> 4); r0 < r_end; r0 += 8 * kLanes) {
@@ -801,9 +806,23 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X
   env_body<R>(X, d, blockIdx.x);
 }
 
-uint32_t env_workgroups(int n) {
+uint32_t env_min_workgroups(int n) {
   const uint32_t nrest = (1u << n) >> 2;
   return (nrest + kEnvRestsPerWG - 1) / kEnvRestsPerWG;
+}
+
+// Up to two rounds of loads stay in one workgroup per start (the last-arrival
+// hand-off would cost more than the round it saves); beyond that the rests
+// are spread so that each workgroup needs one round, as long as the launch
+// stays within kEnvSpreadTarget workgroups (never below the minimum).
+uint32_t env_workgroups(int n, int S) {
+  const uint32_t nrest = (1u << n) >> 2;
+  const uint32_t base = env_min_workgroups(n);
+  if (nrest <= 2u * kEnvRestsPerRound) return base;
+  const uint32_t one_round = (nrest + kEnvRestsPerRound - 1) / kEnvRestsPerRound;
+  const uint32_t cap = S >= (int)kEnvSpreadTarget ? 1u : kEnvSpreadTarget / (uint32_t)(S < 1 ? 1 : S);
+  const uint32_t spread = one_round < cap ? one_round : cap;
+  return spread > base ? spread : base;
 }
 
 static EnvDev make_env_dev(const EnvArgs& a) {
@@ -815,12 +834,14 @@ static EnvDev make_env_dev(const EnvArgs& a) {
   d.b1 = (uint32_t)(a.n - 1 - a.q1);
   d.rlo = d.b0 < d.b1 ? d.b0 : d.b1;
   d.rhi = d.b0 < d.b1 ? d.b1 : d.b0;
-  d.nwg = env_workgroups(a.n);
+  d.nwg = a.nwg > 0 ? (uint32_t)a.nwg : env_workgroups(a.n, a.S);
+  d.rests_per_wg = (d.nrest + d.nwg - 1) / d.nwg;
   return d;
 }
 
 hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArgs& a, KernelEvents ev) {
   const EnvDev d = make_env_dev(a);
+  if (d.nwg < env_min_workgroups(a.n) || d.rests_per_wg > kEnvRestsPerWG) return hipErrorInvalidValue;
   if (d.nwg > 1 && (!a.partials || !a.counters)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)a.S * d.nwg), block(kEnvThreads);
   if (precision == QF_C64) return launch_k(k_env<float>, grid, block, 0u, st, ev, reinterpret_cast<const cf*>(X), d);
@@ -855,7 +876,7 @@ __global__ __launch_bounds__(256) void k_fused(const cx<R>* Xe, EnvDev ed, uint3
 }
 
 bool fused_supported(int precision, int n, const PassGeom& g) {
-  if (env_workgroups(n) != 1) return false;
+  if (env_min_workgroups(n) != 1) return false;
   if (g.micro) return precision == QF_C64;
   return g.direct != 0;
 }
@@ -871,8 +892,10 @@ static hipError_t launch_fused_t(hipStream_t st, const void* Xe, const EnvDev& d
 
 hipError_t launch_fused(hipStream_t st, int precision, const void* Xe, const EnvArgs& ea, void* Xp, int Sp,
                         const PassGeom& g, Operand A, Operand B) {
-  const EnvDev d = make_env_dev(ea);
-  if (d.nwg != 1 || !ea.do_update || !A.ptr || !B.ptr) return hipErrorInvalidValue;
+  EnvArgs one = ea;
+  one.nwg = 1;  // the fused launch keeps each start's environment in one workgroup
+  const EnvDev d = make_env_dev(one);
+  if (d.rests_per_wg > kEnvRestsPerWG || !ea.do_update || !A.ptr || !B.ptr) return hipErrorInvalidValue;
   const uint32_t n_env = (uint32_t)ea.S;
   if (g.micro) {
     if (precision != QF_C64 || (reinterpret_cast<uintptr_t>(Xp) & 15u) != 0) return hipErrorInvalidValue;

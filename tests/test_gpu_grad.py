@@ -49,6 +49,23 @@ def test_gradient_c128_matches_oracle(qf, n, p):
         assert np.abs(G[s] - Gr).max() <= 1e-10, s
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cost_fn_forward_only(qf, precision):
+    """cost_fn on gates that need no gradient takes only the cost (build +
+    trace), equal to the oracle's and to the cost the gradient path gives."""
+    locs, V, g = problem(700, 6, 9, 3)
+    c_fwd = host(qf.cost_fn(dev(g), dev(V), locs, precision))
+    c_grad, _ = qf.gradient(dev(V), locs, dev(g), precision)
+    tol = 1e-12 if precision == 0 else 1e-5
+    for s in range(3):
+        assert abs(c_fwd[s] - O.cost(V, g[s], locs, 6)) <= tol
+    assert np.abs(c_fwd - host(c_grad)).max() <= tol
+    gg = dev(g).requires_grad_(True)
+    c = qf.cost_fn(gg, dev(V), locs, precision)
+    c.sum().backward()
+    assert gg.grad is not None and np.abs(host(c) - c_fwd).max() <= tol
+
+
 @pytest.mark.parametrize("n,p", [(5, 9), (8, 14)])
 def test_gradient_c64_matches_oracle(qf, n, p):
     locs, V, g = problem(600 + n, n, p, 2)

@@ -125,6 +125,50 @@ def test_environment_alternating_layouts(qf):
         assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (n, S)
 
 
+def test_standalone_calls_in_chunks(qf):
+    """More builders than the stand-alone calls take per launch (they walk
+    their builders in chunks of 1024 through the context's fixed scratch):
+    every builder's environment and update equal the oracle's."""
+    rng = np.random.default_rng(2400)
+    n, S = 4, 2500
+    X0 = I.random_builder(rng, S, n)
+    loc = (1, 3)
+    got = host(qf.environment(dev(X0), loc))
+    ref = O.partial_trace(X0, loc, n)
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    V = I.haar_unitary(rng, 1 << n)
+    locs = np.array([loc, (0, 2)], np.int32)
+    gates = np.stack([I.haar_gates(rng, 2) for _ in range(S)])
+    ob = O.BuilderOracle(V, gates, locs, n)
+    X = qf.build(dev(V), locs, dev(gates), torch.complex128)
+    rec = []
+    ob.update(1, 0, record=rec)
+    gcol = dev(gates[:, 1].copy())
+    _, env = qf.update_gate(X, tuple(locs[1]), 0, gcol, 0.0, want_env=True)
+    assert np.abs(host(env) - rec[0][2]).max() <= 1e-10 * max(1.0, np.abs(rec[0][2]).max())
+    assert np.abs(host(gcol) - rec[0][3]).max() <= 1e-9
+    assert np.abs(host(X) - ob.X).max() <= C128_TOL
+
+
+@pytest.mark.parametrize("n,S", [(11, 1), (12, 1), (12, 3), (13, 1)])
+def test_environment_spread_over_workgroups(qf, n, S):
+    """Few builders of n >= 11: the partial trace of each is spread over
+    several workgroups (finished by the last to arrive); the sums equal the
+    oracle's for every start, and a repeated call gives bitwise the same
+    values (the hand-off sums the partials in workgroup order)."""
+    rng = np.random.default_rng(1100 + 10 * n + S)
+    X0 = (rng.standard_normal((S, 1 << n, 1 << n)) + 1j * rng.standard_normal((S, 1 << n, 1 << n)))
+    X0 = X0.astype(np.complex64)
+    X = dev(X0)
+    for loc in [(0, 1), (n - 1, 2), (n // 2, n - 2)]:
+        got = host(qf.environment(X, loc))
+        ref = O.partial_trace(X0.astype(np.complex128), loc, n)
+        assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), loc
+        assert np.array_equal(got, host(qf.environment(X, loc)))
+    del X
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------------------------- gate update
 
 def test_optimize_gate_vs_lapack(qf):
