@@ -271,6 +271,28 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
                    void* workspace, size_t ws_bytes, void* out_gates, void* out_all_gates,
                    double* out_costs, qf_stats* stats);
 
+/* qf_instantiate without a caller workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, behaviour and results
+ * as qf_instantiate, minus workspace/ws_bytes: the workspace is a fixed
+ * device array of QF_NOALLOC_WORKSPACE_BYTES (64 MiB) that the library holds
+ * on every device it runs on until the process ends; the call itself
+ * allocates nothing.  Problems whose qf_workspace_size exceeds it return
+ * QF_EWORKSPACE before any device work.  For circuits of about 5n gates
+ * it holds, in complex64 / complex128 builders: n = 10 with up to 2 / 3
+ * starts, n = 9 with 10 / 15,
+ * n = 8 with 42 / 63, and every resident problem (n <= 6); no n >= 11
+ * problem fits.  qf_workspace_size gives the exact need.  All calls on
+ * one device share the array, so calls that overlap on a device (several
+ * host threads, or contexts on different streams) race and must be
+ * serialised by the caller; a call leaves the array's contents behind and
+ * clears what it needs at its start.  stats->timing (which creates HIP
+ * events) is refused with QF_EUNSUPPORTED. */
+#define QF_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int qf_instantiate_noalloc(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                           const void* init_gates, int n_starts, double tol, const qf_options* opt, void* out_gates,
+                           void* out_all_gates, double* out_costs, qf_stats* stats);
+
 /* Form of the fused remove/re-apply pass (the hot loop of every gate update,
  * Alg. 1) used for builders of n qubits in `precision`, for one class of
  * gates: gate_class 0 = the higher of the gate's two column bits (bit

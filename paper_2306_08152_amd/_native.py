@@ -20,8 +20,9 @@ EXPORTED = [
     "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
     "qf_gradient_workspace_size", "qf_gradient", "qf_su4_gates", "qf_su4_vjp", "qf_lbfgs_options_default",
     "qf_lbfgs_workspace_size", "qf_lbfgs", "qf_set_pass_tile", "qf_delete_gates_workspace_size", "qf_delete_gates",
-    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3",
+    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3", "qf_instantiate_noalloc",
 ]
+QF_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 
 class QfOptions(ctypes.Structure):
@@ -122,6 +123,9 @@ _SIGS = {
     "qf_instantiate": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int,
                                       ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _VP, _VP,
                                       _DP, ctypes.POINTER(QfStats)]),
+    "qf_instantiate_noalloc": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int,
+                                              ctypes.c_double, ctypes.POINTER(QfOptions), _VP, _VP, _DP,
+                                              ctypes.POINTER(QfStats)]),
     "qf_workspace_size3": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(QfOptions)]),
     "qf_instantiate3": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, ctypes.c_int,
                                        ctypes.c_double, ctypes.POINTER(QfOptions), _VP, ctypes.c_size_t, _VP, _VP,

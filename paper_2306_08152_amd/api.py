@@ -202,9 +202,12 @@ def workspace_size(n: int, p: int, S: int, opt: nat.QfOptions) -> int:
 
 def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float = 1e-10,
                 options: nat.QfOptions | None = None, history_rows: int = 0,
-                workspace: torch.Tensor | None = None, timing: bool = False, **kw) -> Result:
+                workspace: torch.Tensor | None = None, timing: bool = False, noalloc: bool = False,
+                **kw) -> Result:
     """QFactor multistart instantiation (qf_instantiate); gate_kinds=[...]
-    selects restricted gate kinds (QF_KIND_*)."""
+    selects restricted gate kinds (QF_KIND_*).  noalloc=True calls
+    qf_instantiate_noalloc instead (the library's fixed workspace; no
+    `workspace` argument)."""
     opt = options if options is not None else default_options()
     _kinds_keep = _apply_kw(opt, kw)  # noqa: F841
     N = target.shape[0]
@@ -218,7 +221,9 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
     if need == 0:
         # invalid sizes or options: let the library reject them with its message
         need = 1
-    if workspace is None or workspace.numel() < need:
+    if noalloc:
+        workspace = None
+    elif workspace is None or workspace.numel() < need:
         workspace = torch.empty((need,), dtype=torch.uint8, device=target.device)
     out = torch.empty((p, 4, 4), dtype=torch.complex128, device=target.device)
     out_all = torch.empty((S, p, 4, 4), dtype=torch.complex128, device=target.device)
@@ -231,9 +236,13 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
         st.cost_history_rows = history_rows
     st.timing = 1 if timing else 0
     ctx = _ctx(target.device)
-    rc = lib.qf_instantiate(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
-                            ctypes.byref(opt), _ptr(workspace), need, _ptr(out), _ptr(out_all), costs,
-                            ctypes.byref(st))
+    if noalloc:
+        rc = lib.qf_instantiate_noalloc(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
+                                        ctypes.byref(opt), _ptr(out), _ptr(out_all), costs, ctypes.byref(st))
+    else:
+        rc = lib.qf_instantiate(ctx, n, _ptr(target), p, _loc(locs), _ptr(init_gates), S, float(tol),
+                                ctypes.byref(opt), _ptr(workspace), need, _ptr(out), _ptr(out_all), costs,
+                                ctypes.byref(st))
     if rc not in (nat.QF_OK, nat.QF_ENUMERIC):
         nat.check(rc, ctx)
     h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,13 +27,23 @@ struct qf_ctx {
   // of starts concurrently, forked from and joined to `stream` by events.
   hipStream_t aux[kMaxGroups] = {};
   hipEvent_t fork = nullptr, join[kMaxGroups] = {}, stagger[kMaxGroups] = {};
+  hipEvent_t tune[2] = {};      // timing events of the pass-form tuner
   double* pinned = nullptr;     // host read-back buffer (kPinnedCount doubles)
   void* scratch = nullptr;      // device scratch of the stand-alone step calls
   // Autotuned pass tile width per (precision, n); 0 = not tuned yet.
   int tuned_tcols[2][2][17] = {};
   double* identity = nullptr;   // one 4x4 c128 identity (tuning operand)
+  void* static_ws = nullptr;    // this device's address of `scratch` (below); null if unresolved
   std::string last_error;
 };
+
+// Workspace of qf_instantiate_noalloc: a fixed device array, one copy per
+// device, held from the library's load on that device until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (its
+// host-side name is only a stand-in for the symbol); it uses the address
+// hipGetSymbolAddress gives on each device, resolved once per device by
+// qf_create (static_scratch_ptr).  Every call on a device shares the array.
+static __device__ __align__(256) unsigned char scratch[QF_NOALLOC_WORKSPACE_BYTES];
 
 namespace {
 
@@ -60,6 +71,24 @@ int fail(qf_ctx* ctx, int code, const char* fmt, ...) {
     ctx->last_error = buf;
   }
   return code;
+}
+
+// Device address of `scratch` on `device` (which must be current), resolved
+// once per device and kept for the process's lifetime.  Null when the
+// lookup fails; qf_instantiate_noalloc then reports QF_EHIP.
+constexpr int kMaxDevices = 64;
+void* static_scratch_ptr(int device) {
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  static bool tried[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!tried[device]) {
+    tried[device] = true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) ptr[device] = p;
+  }
+  return ptr[device];
 }
 
 #define QF_HIP(ctx, expr)                                                                     \
@@ -193,6 +222,8 @@ int ensure_aux_streams(qf_ctx* ctx) {
     QF_HIP(ctx, hipEventCreateWithFlags(&ctx->stagger[i], hipEventDisableTiming));
   }
   QF_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  QF_HIP(ctx, hipEventCreate(&ctx->tune[0]));
+  QF_HIP(ctx, hipEventCreate(&ctx->tune[1]));
   return QF_OK;
 }
 
@@ -232,9 +263,7 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
       continue;
     }
     const int q0 = cls == 0 ? n / 2 - 1 : n - 2, q1 = q0 + 1;  // a mid-circuit pair / the two lowest bits
-    hipEvent_t e0, e1;
-    QF_HIP(ctx, hipEventCreate(&e0));
-    QF_HIP(ctx, hipEventCreate(&e1));
+    hipEvent_t e0 = ctx->tune[0], e1 = ctx->tune[1];
     // Two rounds over the candidates (warm-up launch, then 4 timed launches);
     // each candidate keeps its better round.
     float t_best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
@@ -250,11 +279,7 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) {
-          (void)hipEventDestroy(e0);
-          (void)hipEventDestroy(e1);
-          return fail(ctx, QF_EHIP, "pass autotune: %s", hipGetErrorString(err));
-        }
+        if (err != hipSuccess) return fail(ctx, QF_EHIP, "pass autotune: %s", hipGetErrorString(err));
         t_best[c] = std::min(t_best[c], ms);
       }
     float best = 1e30f;
@@ -264,8 +289,6 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
         best = t_best[c];
         best_t = cands[c];
       }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     slot = best_t;
   }
   return QF_OK;
@@ -1022,6 +1045,7 @@ int qf_create(qf_ctx** out, int device, void* hip_stream) {
     (void)qf_destroy(ctx);
     return QF_EHIP;
   }
+  ctx->static_ws = static_scratch_ptr(device);  // device current (DeviceGuard)
   *out = ctx;
   return QF_OK;
 }
@@ -1040,6 +1064,8 @@ int qf_destroy(qf_ctx* ctx) {
       if (ctx->stagger[i]) (void)hipEventDestroy(ctx->stagger[i]);
     }
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    for (hipEvent_t e : ctx->tune)
+      if (e) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->identity) (void)hipFree(ctx->identity);
@@ -1286,6 +1312,27 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
   }
   if (all_numeric) return fail(ctx, QF_ENUMERIC, "every start produced non-finite values");
   return QF_OK;
+}
+
+int qf_instantiate_noalloc(qf_ctx* ctx, int n, const void* target, int n_gates, const int32_t* locations,
+                           const void* init_gates, int n_starts, double tol, const qf_options* opt, void* out_gates,
+                           void* out_all_gates, double* out_costs, qf_stats* stats) {
+  if (!ctx) return QF_EINVAL;
+  const size_t need = qf_workspace_size(n, n_gates, n_starts, opt);
+  if (need == 0)  // invalid sizes or options: let qf_instantiate name the problem
+    return qf_instantiate(ctx, n, target, n_gates, locations, init_gates, n_starts, tol, opt, nullptr, 0,
+                          out_gates, out_all_gates, out_costs, stats);
+  if (need > (size_t)QF_NOALLOC_WORKSPACE_BYTES)
+    return fail(ctx, QF_EWORKSPACE,
+                "qf_instantiate_noalloc: this problem needs %zu bytes of workspace, more than the fixed %zu "
+                "(use qf_instantiate with a caller workspace)",
+                need, (size_t)QF_NOALLOC_WORKSPACE_BYTES);
+  if (stats && stats->timing)
+    return fail(ctx, QF_EUNSUPPORTED, "qf_instantiate_noalloc: stats->timing creates HIP events per launch");
+  if (!ctx->static_ws)
+    return fail(ctx, QF_EHIP, "qf_instantiate_noalloc: the fixed workspace's device address is unavailable");
+  return qf_instantiate(ctx, n, target, n_gates, locations, init_gates, n_starts, tol, opt, ctx->static_ws,
+                        (size_t)QF_NOALLOC_WORKSPACE_BYTES, out_gates, out_all_gates, out_costs, stats);
 }
 
 // ------------------------------------------------------- three-qubit gates
