@@ -37,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_pass_n10_s16_c64_traffic.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_pass2_n10_s16_c64_traffic.json")
 
 
 def measured_traffic():
@@ -447,6 +447,7 @@ def main():
     pass_avg_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
     achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
     env_avg_us = 1e3 * tm["env_ms"] / max(1, tm["env_launches"])
+    moved_bytes = int(round(tm["pass_launches"] / K)) * pass_bytes  # builder passes per sweep x bytes each
     sweep_loop_rate = S * K / (tm["sweep_ms"] * 1e-3) if tm["sweep_ms"] > 0 else None
     rmw128 = rmw_ceiling(torch, pass_bytes // 2)
 
@@ -468,22 +469,29 @@ def main():
                    "timed_calls": 5, "call_seconds": [round(x, 5) for x in calls]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "fused remove + re-apply pass, complex64, 16 builders per launch (register-direct "
-                               "k_pass_block, micro-tile k_pass_micro or LDS-tiled k_pass, as tuned per gate class); "
-                               "one read + one write of every builder entry; timed alone (all starts in one "
-                               "group, kernel-stamped HIP events) in a second call of the same K sweeps",
+                     "kernel": "builder pass, complex64, 16 builders per launch: the two-gate pass k_pass2 (remove "
+                               "+ re-apply of two consecutive gates in one pass; 44 of the 46 launches of a sweep), "
+                               "and the one-gate pass (k_pass_block / k_pass_micro / k_pass) for the gate left "
+                               "over in each half-sweep; one read + one write of every builder entry per launch; "
+                               "timed alone (all starts in one group, kernel-stamped HIP events) in a second call "
+                               "of the same K sweeps",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
                      "launches_timed": tm["pass_launches"], "pass_form_mid_gate": tm.get("pass_tcols"),
-                     "traffic_source": "profiles/k_pass_n10_s16_c64_traffic.json (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
-                                       "scaled by a 256 MiB copy)",
+                     "traffic_source": TRAFFIC_JSON.replace(ROOT + os.sep, "") + " (FETCH_SIZE and WRITE_SIZE, "
+                                       "scaled by the same counters on a 256 MiB copy)",
                      "sweep_bytes": sweep_bytes,
+                     "sweep_bytes_note": "one read + one write of every builder per gate update (2p per sweep); "
+                                         "two-gate passes move half of that, see sweep_moved_*",
                      "sweep_achieved": round(sweep_bytes * value / S / 1e9, 1),
                      "sweep_frac": round(sweep_bytes * value / S / 1e9 / HBM_PEAK_GBS, 4),
+                     "sweep_moved_bytes": moved_bytes,
+                     "sweep_moved_frac": round(moved_bytes * value / S / 1e9 / HBM_PEAK_GBS, 4),
                      "rmw_ceiling_GBps": round(rmw128, 1),
                      "frac_of_rmw_ceiling": round(achieved / rmw128, 4),
                      "mall_note": "the 128 MiB builder set fits in the 256 MB MALL (Infinity Cache), so this "
                                   "working set can exceed HBM peak; extra.n12_s4_* is the 512 MiB point beyond it"},
         "breakdown": {"pass_avg_us": round(1e3 * pass_avg_ms, 2), "env_svd_avg_us": round(env_avg_us, 2),
+                      "passes_per_sweep": round(tm["pass_launches"] / K, 2),
                       "sweep_loop_start_sweeps_per_s": round(sweep_loop_rate, 2) if sweep_loop_rate else None,
                       "final_best_cost": float(np.min(res.costs))},
     }

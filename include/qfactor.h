@@ -100,7 +100,8 @@ typedef enum {
  * paper recommends: dist_tol 1e-10, diff_tol_a 0, diff_tol_r 1e-5,
  * long_diff_count 100, long_diff_r 0.1, min_iter 0, max_iter 1e5,
  * reset_iter 40, beta 0; plus precision QF_C128, mode QF_MODE_AUTO,
- * recheck_below 1e-3, stream_groups 0 (automatic) and gate_kinds NULL.
+ * recheck_below 1e-3, stream_groups 0 (automatic), gate_kinds NULL and
+ * gate_pairs 1.
  * Readings of the garbled tests (c_i = cost after sweep i, c_0 = initial):
  *   short plateau: c_{i-1} - c_i <= diff_tol_a + diff_tol_r * c_i
  *                  (off when both are 0);
@@ -132,18 +133,30 @@ typedef struct {
   double recheck_below;
   int32_t stream_groups; /* streaming mode: how the environment + SVD step
                             of some starts runs under the pass of others.
-                            0 = automatic: four groups in two pairs, each
-                            pair on one stream (the caller's, qf_set_stream,
-                            and one of the library's), every launch carrying
-                            one group's environment step beside the other
-                            group's pass (two groups on the caller's stream
-                            for 2-3 starts; one group for one start or n >=
-                            15).  1..4 = that many groups on separate
-                            streams (group 0 on the caller's), staggered;
-                            at most n_starts groups */
+                            0 = automatic: with two-gate updates (see
+                            gate_pairs) three groups on separate streams
+                            (the caller's and two of the library's),
+                            staggered; with one pass per update four groups
+                            in two pairs, each pair on one stream, every
+                            launch carrying one group's environment step
+                            beside the other group's pass (two groups on
+                            the caller's stream for 2-3 starts; one group
+                            for one start or n >= 15).  1..4 = that many
+                            groups on separate streams (group 0 on the
+                            caller's), staggered; at most n_starts groups.
+                            Every choice gives bitwise the same results */
   const int32_t* gate_kinds; /* host, one qf_gate_kind per gate (for
                                 qf_instantiate_batch: per gate of the whole
                                 batch); NULL = every gate QF_KIND_U4 */
+  int32_t gate_pairs;        /* streaming mode: 1 (default) runs two
+                                consecutive gate updates of a sweep with one
+                                partial trace and one builder pass when the
+                                builder is QF_C64, the two gates span 3 or 4
+                                qubits and neither is QF_KIND_FIXED (each
+                                update still sees its own environment;
+                                results agree with one pass per update up to
+                                rounding); 2 = the same for QF_C128 builders
+                                too; 0 = one pass per update */
 } qf_options;
 
 /* Outcome of qf_instantiate (host memory). */

@@ -41,6 +41,7 @@ class QfOptions(ctypes.Structure):
         ("recheck_below", ctypes.c_double),
         ("stream_groups", ctypes.c_int32),
         ("gate_kinds", ctypes.POINTER(ctypes.c_int32)),
+        ("gate_pairs", ctypes.c_int32),
     ]
 
 

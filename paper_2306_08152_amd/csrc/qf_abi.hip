@@ -32,6 +32,8 @@ struct qf_ctx {
   void* scratch = nullptr;      // device scratch of the stand-alone step calls
   // Autotuned pass tile width per (precision, n); 0 = not tuned yet.
   int tuned_tcols[2][2][17] = {};
+  // Tuned tiles per workgroup of the two-gate pass per (precision, n); 0 = not tuned yet.
+  int tuned_pass2[2][17] = {};
   double* identity = nullptr;   // one 4x4 c128 identity (tuning operand)
   void* static_ws = nullptr;    // this device's address of `scratch` (below); null if unresolved
   std::string last_error;
@@ -131,7 +133,8 @@ int resolve_mode(int n, const qf_options& o) {
 // Workspace layout of qf_instantiate.
 struct Layout {
   size_t X = 0, R = 0, gates = 0, uold = 0, partials = 0, counters = 0, costs = 0, trace = 0,
-         frozen = 0, locs = 0, kinds = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0;
+         frozen = 0, locs = 0, kinds = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0,
+         uold2 = 0, ops2 = 0, partials2 = 0;
   size_t total = 0;
   int ring = 2;
 };
@@ -153,6 +156,13 @@ Layout make_layout(int n, int p, int S, const qf_options& o, int mode, int histo
     L.uold = take((size_t)S * 16 * 16);
     L.trace = take((size_t)S * 16);
     L.frozen = take((size_t)S * 4);
+    if (o.gate_pairs == 2 || (o.gate_pairs == 1 && o.precision == QF_C64)) {
+      // two-gate updates: both gates' u_old, the pass's operands, partial traces
+      L.uold2 = take((size_t)S * 32 * 16);
+      L.ops2 = take((size_t)S * 64 * elem_bytes(o.precision));
+      const uint32_t nwg2 = env2_workgroups_cap(n);
+      if (nwg2 > 1) L.partials2 = take((size_t)S * nwg2 * 256 * 16);
+    }
   }
   L.gates = take((size_t)S * p * 16 * 16);
   L.costs = take((size_t)S * 8);
@@ -187,6 +197,7 @@ int validate_options(qf_ctx* ctx, const qf_options& o) {
   if (o.min_iter < 0 || o.max_iter < 0 || o.reset_iter < 0) return fail(ctx, QF_EINVAL, "iteration counts must be >= 0");
   if (!(o.beta >= 0.0 && o.beta <= 1.0)) return fail(ctx, QF_EINVAL, "beta must be in [0, 1]");
   if (o.precision != QF_C128 && o.precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision %d", o.precision);
+  if (o.gate_pairs < 0 || o.gate_pairs > 2) return fail(ctx, QF_EINVAL, "gate_pairs must be 0, 1 or 2");
   if (o.mode < QF_MODE_AUTO || o.mode > QF_MODE_STREAMING) return fail(ctx, QF_EINVAL, "unknown mode %d", o.mode);
   if (!(o.recheck_below >= 0) || !std::isfinite(o.recheck_below)) return fail(ctx, QF_EINVAL, "recheck_below must be >= 0");
   if (o.stream_groups < 0 || o.stream_groups > kMaxGroups) return fail(ctx, QF_EINVAL, "stream_groups must be in [0, 4]");
@@ -291,6 +302,51 @@ int autotune_pass(qf_ctx* ctx, int precision, int n, void* X, int S) {
       }
     slot = best_t;
   }
+  return QF_OK;
+}
+
+// Tiles per workgroup of the two-gate pass, tuned once per context and
+// (precision, n) by timing the candidates on the caller's builder with
+// identity operands (the builder is left bit-for-bit unchanged), two rounds
+// of four launches each; the geometry is the circuit's first two-gate unit.
+__global__ void k_identity_ops(void* ops, int precision, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t e = i & 15u;
+  const double v = ((e >> 2) == (e & 3u)) ? 1.0 : 0.0;
+  if (precision == QF_C64)
+    reinterpret_cast<float2*>(ops)[i] = make_float2((float)v, 0.f);
+  else
+    reinterpret_cast<double2*>(ops)[i] = make_double2(v, 0.0);
+}
+
+int autotune_pass2(qf_ctx* ctx, int precision, int n, void* X, int S, const Pair2Geom& g0, void* ops) {
+  int& slot = ctx->tuned_pass2[precision == QF_C64][n];
+  if (slot) return QF_OK;
+  const uint32_t count = (uint32_t)S * 64;
+  hipLaunchKernelGGL(k_identity_ops, dim3((count + 255) / 256), dim3(256), 0, ctx->stream, ops, precision, count);
+  QF_HIP(ctx, hipGetLastError());
+  const int cands[] = {1, 2, 4, 8};
+  float t_best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+  hipEvent_t e0 = ctx->tune[0], e1 = ctx->tune[1];
+  for (int round = 0; round < 2; ++round)
+    for (int c = 0; c < 4; ++c) {
+      Pair2Geom g = g0;
+      g.tiles_per_wg = (uint32_t)cands[c];
+      hipError_t err = launch_pass2(ctx->stream, precision, X, S, g, ops);
+      if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < 4 && err == hipSuccess; ++r) err = launch_pass2(ctx->stream, precision, X, S, g, ops);
+      if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) return fail(ctx, QF_EHIP, "two-gate pass autotune: %s", hipGetErrorString(err));
+      t_best[c] = std::min(t_best[c], ms);
+    }
+  int best = 0;
+  for (int c = 1; c < 4; ++c)
+    if (t_best[c] < t_best[best]) best = c;
+  slot = cands[best];
   return QF_OK;
 }
 
@@ -433,6 +489,46 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   std::vector<PassGeom> geo(p);
   for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n, locs[2 * g], locs[2 * g + 1]));
 
+  // Update units of each half-sweep, in Alg. 1's order (g = p..1, then
+  // 1..p): one gate, or two consecutive gates F then S whose updates share
+  // one partial trace and one builder pass (k_env2 + k_pass2) when they span
+  // 3 or 4 qubits and neither is fixed.
+  struct Unit {
+    int g1 = 0, g2 = -1;  // g2 < 0: a single gate
+    Pair2Geom pg{};
+  };
+  auto pair_geom = [&](int f, int sg, Pair2Geom& pg) -> bool {
+    if (o.gate_pairs == 0 || (o.gate_pairs == 1 && prec != QF_C64)) return false;
+    if (o.gate_kinds && (o.gate_kinds[f] == QF_KIND_FIXED || o.gate_kinds[sg] == QF_KIND_FIXED)) return false;
+    uint32_t mask = 0;
+    for (int k = 0; k < 2; ++k) mask |= (1u << (n - 1 - locs[2 * f + k])) | (1u << (n - 1 - locs[2 * sg + k]));
+    const int m = __builtin_popcount(mask);
+    if (m != 3 && m != 4) return false;
+    return make_pair2_geom(n, locs + 2 * f, locs + 2 * sg, pair2_wlog(prec, m), pg);
+  };
+  std::vector<Unit> units[2];
+  bool any_pair = false;
+  for (int half = 0; half < 2; ++half) {
+    std::vector<int> order(p);
+    for (int k = 0; k < p; ++k) order[k] = half == 0 ? p - 1 - k : k;
+    for (int k = 0; k < p;) {
+      Unit u;
+      u.g1 = order[k];
+      if (k + 1 < p && pair_geom(order[k], order[k + 1], u.pg)) {
+        u.g2 = order[k + 1];
+        any_pair = true;
+        k += 2;
+      } else {
+        k += 1;
+      }
+      units[half].push_back(u);
+    }
+  }
+  double* uold2 = reinterpret_cast<double*>(ws + L.uold2);
+  unsigned char* ops2 = ws + L.ops2;
+  double* partials2 = reinterpret_cast<double*>(ws + L.partials2);
+  const uint32_t nwg2_stride = L.partials2 ? env2_workgroups_cap(n) : 0;
+
   // The starts split into G groups whose sweeps run on separate streams:
   // while one group's latency-bound environment + SVD step runs, the other
   // group's pass keeps HBM busy.  Groups share nothing but the join.  Group
@@ -446,7 +542,14 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   if (stats && stats->timing) G = 1;
   // Default schedule: two groups on the caller's stream, each launch carrying
   // one group's environment step beside the other group's pass (k_fused).
-  const bool fused = o.stream_groups == 0 && !(stats && stats->timing) && S >= 2 && env_min_workgroups(n) == 1;
+  const bool fused =
+      o.stream_groups == 0 && !(stats && stats->timing) && S >= 2 && !any_pair && env_min_workgroups(n) == 1;
+  // With two-gate updates, three staggered groups: a group's environment
+  // step (two FP64 updates in a row) runs while the others' passes stream
+  // (measured at n = 10, 16 starts: 1 group 3758, 2: 3828, 3: 3898, 4: 3657
+  // start-sweeps/s; the pairing of one group's environment with another's
+  // pass in one launch, as for single updates, gave 3830-3874).
+  if (any_pair && o.stream_groups == 0 && !(stats && stats->timing)) G = std::min(3, S);
   constexpr int kFusedPairs = 2;  // pairs of groups, one stream each
   static_assert(kFusedPairs >= 1 && kFusedPairs <= kMaxGroups, "one stream per pair: the caller's and kMaxGroups - 1 own");
   const int pairs = fused ? std::min(kFusedPairs, S / 2) : 0;
@@ -517,6 +620,40 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
       QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[g], gnew, gold, te));
     return QF_OK;
   };
+  auto env2_args = [&](Group& q, const Unit& u, int half) -> Env2Args {
+    Env2Args a2{};
+    a2.geom = u.pg;
+    a2.n_starts = q.ns;
+    for (int k = 0; k < 2; ++k) {
+      EnvArgs& e = k == 0 ? a2.F : a2.S;
+      const int g = k == 0 ? u.g1 : u.g2;
+      e = q.ea;
+      e.kind = o.gate_kinds ? o.gate_kinds[g] : QF_KIND_U4;
+      e.q0 = locs[2 * g];
+      e.q1 = locs[2 * g + 1];
+      e.half = half;
+      e.gidx = g;
+      e.uold = uold2 + (size_t)q.s0 * 64 + 32 * k;
+      e.uold_stride = 32;
+      e.env_out = nullptr;
+    }
+    a2.frozen = frozen + q.s0;
+    a2.partials = nwg2_stride ? partials2 + (size_t)q.s0 * nwg2_stride * 512 : nullptr;
+    a2.counters = q.ea.counters;
+    a2.ops = ops2 + (size_t)q.s0 * 64 * elem_bytes(prec);
+    // the same gather split for every group and schedule: bitwise the same sums
+    a2.nwg = (int)env2_workgroups(n, (int)u.pg.m, S);
+    return a2;
+  };
+  auto ops_of = [&](const Group& q) -> const void* { return ops2 + (size_t)q.s0 * 64 * elem_bytes(prec); };
+  auto update_unit = [&](Group& q, const Unit& u, int half, hipEvent_t after_env) -> int {
+    if (u.g2 < 0) return update(q, u.g1, half, after_env);
+    const Env2Args a2 = env2_args(q, u, half);
+    QF_HIP(ctx, launch_env2(q.st, prec, q.X, a2, timer.next(1)));
+    if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
+    QF_HIP(ctx, launch_pass2(q.st, prec, q.X, q.ns, u.pg, a2.ops, timer.next(0)));
+    return QF_OK;
+  };
   // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved,
   // forked from and joined back to stream `home`.
   auto sweep_on = [&](hipStream_t home) -> int {
@@ -529,15 +666,16 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     // is done, so the groups' latency-bound steps fall under each other's
     // passes instead of running in lockstep.
     int rc1;
-    for (int g = p - 1; g >= 0; --g)
+    for (size_t k = 0; k < units[0].size(); ++k)
       for (int gi = 0; gi < G; ++gi) {
-        const bool first = (g == p - 1);
+        const bool first = (k == 0);
         if (first && gi > 0) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->stagger[gi - 1], 0));
-        if ((rc1 = update(grp[gi], g, 0, (first && gi + 1 < G) ? ctx->stagger[gi] : nullptr))) return rc1;
+        if ((rc1 = update_unit(grp[gi], units[0][k], 0, (first && gi + 1 < G) ? ctx->stagger[gi] : nullptr)))
+          return rc1;
       }
-    for (int g = 0; g < p; ++g)
+    for (size_t k = 0; k < units[1].size(); ++k)
       for (int gi = 0; gi < G; ++gi)
-        if ((rc1 = update(grp[gi], g, 1, nullptr))) return rc1;
+        if ((rc1 = update_unit(grp[gi], units[1][k], 1, nullptr))) return rc1;
     if (G > 1) {
       for (int gi = 0; gi < G; ++gi) {
         if (grp[gi].st == home) continue;
@@ -553,44 +691,52 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   // the other's pass.  Steps that do not pair (two passes, a pass form
   // without a fused kernel) are launched alone, in order.
   struct Step {
-    int g, half, env;
+    int u, half, env;  // unit index within units[half]; env: 1 = environment step, 0 = pass
   };
   std::vector<Step> steps;
   if (fused) {
-    for (int g = p - 1; g >= 0; --g) {
-      const bool fx = o.gate_kinds && o.gate_kinds[g] == QF_KIND_FIXED;
-      if (!fx) steps.push_back({g, 0, 1});
-      steps.push_back({g, 0, 0});
-    }
-    for (int g = 0; g < p; ++g) {
-      const bool fx = o.gate_kinds && o.gate_kinds[g] == QF_KIND_FIXED;
-      if (!fx) steps.push_back({g, 1, 1});
-      steps.push_back({g, 1, 0});
-    }
+    for (int half = 0; half < 2; ++half)
+      for (int k = 0; k < (int)units[half].size(); ++k) {
+        const Unit& un = units[half][k];
+        const bool fx = un.g2 < 0 && o.gate_kinds && o.gate_kinds[un.g1] == QF_KIND_FIXED;
+        if (!fx) steps.push_back({k, half, 1});
+        steps.push_back({k, half, 0});
+      }
   }
+  auto unit_of = [&](const Step& k) -> const Unit& { return units[k.half][k.u]; };
   auto prep_env = [&](Group& q, const Step& k) -> EnvArgs& {
+    const int g = unit_of(k).g1;
     EnvArgs& ea = q.ea;
-    ea.kind = o.gate_kinds ? o.gate_kinds[k.g] : QF_KIND_U4;
-    ea.q0 = locs[2 * k.g];
-    ea.q1 = locs[2 * k.g + 1];
+    ea.kind = o.gate_kinds ? o.gate_kinds[g] : QF_KIND_U4;
+    ea.q0 = locs[2 * g];
+    ea.q1 = locs[2 * g + 1];
     ea.half = k.half;
-    ea.gidx = k.g;
+    ea.gidx = g;
     return ea;
   };
   auto pass_ops = [&](Group& q, const Step& k, Operand& A, Operand& B) {
-    const bool fx = o.gate_kinds && o.gate_kinds[k.g] == QF_KIND_FIXED;
-    const Operand gnew{q.ea.gates + 2 * 16 * (int64_t)k.g, gstride, 0};
-    const Operand gold = fx ? Operand{q.ea.gates + 2 * 16 * (int64_t)k.g, gstride, 1} : Operand{q.ea.uold, 16, 1};
+    const int g = unit_of(k).g1;
+    const bool fx = o.gate_kinds && o.gate_kinds[g] == QF_KIND_FIXED;
+    const Operand gnew{q.ea.gates + 2 * 16 * (int64_t)g, gstride, 0};
+    const Operand gold = fx ? Operand{q.ea.gates + 2 * 16 * (int64_t)g, gstride, 1} : Operand{q.ea.uold, 16, 1};
     A = k.half == 0 ? gold : gnew;
     B = k.half == 0 ? gnew : gold;
   };
   auto run_alone = [&](Group& q, const Step& k) -> int {
+    const Unit& un = unit_of(k);
+    if (un.g2 >= 0) {
+      if (k.env)
+        QF_HIP(ctx, launch_env2(q.st, prec, q.X, env2_args(q, un, k.half)));
+      else
+        QF_HIP(ctx, launch_pass2(q.st, prec, q.X, q.ns, un.pg, ops_of(q)));
+      return QF_OK;
+    }
     if (k.env) {
       QF_HIP(ctx, launch_env(q.st, prec, q.X, prep_env(q, k)));
     } else {
       Operand A, B;
       pass_ops(q, k, A, B);
-      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[k.g], A, B));
+      QF_HIP(ctx, launch_pass(q.st, prec, q.X, q.ns, geo[un.g1], A, B));
     }
     return QF_OK;
   };
@@ -609,10 +755,15 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
       Group& qp = a->env ? q1 : q0;
       const Step& ke = a->env ? *a : *b;
       const Step& kp = a->env ? *b : *a;
-      if (fused_supported(prec, n, geo[kp.g])) {
+      const Unit& ue = unit_of(ke);
+      const Unit& up = unit_of(kp);
+      hipError_t e = hipErrorNotReady;  // not launched
+      if (ue.g2 < 0 && up.g2 < 0 && fused_supported(prec, n, geo[up.g1])) {
         Operand A, B;
         pass_ops(qp, kp, A, B);
-        const hipError_t e = launch_fused(q0.st, prec, qe.X, prep_env(qe, ke), qp.X, qp.ns, geo[kp.g], A, B);
+        e = launch_fused(q0.st, prec, qe.X, prep_env(qe, ke), qp.X, qp.ns, geo[up.g1], A, B);
+      }
+      if (e != hipErrorNotReady) {
         if (e != hipSuccess) {
           rc1 = fail(ctx, QF_EHIP, "fused launch: %s", hipGetErrorString(e));
           return true;
@@ -677,6 +828,17 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     }
   }
   for (int g = 0; g < p; ++g) geo[g] = make_pass_geom(n, locs[2 * g], locs[2 * g + 1], pass_tcols(ctx, prec, n, locs[2 * g], locs[2 * g + 1]));
+  if (any_pair) {
+    const Unit* first = nullptr;
+    for (const Unit& u : units[0])
+      if (u.g2 >= 0 && !first) first = &u;
+    if (!first)
+      for (const Unit& u : units[1])
+        if (u.g2 >= 0 && !first) first = &u;
+    if ((rc = autotune_pass2(ctx, prec, n, X, S, first->pg, ops2))) return rc;
+    for (auto& hv : units)
+      for (Unit& u : hv) u.pg.tiles_per_wg = (uint32_t)ctx->tuned_pass2[prec == QF_C64][n];
+  }
   QF_HIP(ctx, launch_cost(st, prec, X, n, S, costs, trace));
   std::vector<double> c;
   rc = read_costs(ctx, costs, S, c);
@@ -1018,6 +1180,7 @@ void qf_options_default(qf_options* o) {
   o->recheck_below = 1e-3;
   o->stream_groups = 0;
   o->gate_kinds = nullptr;
+  o->gate_pairs = 1;
 }
 
 int qf_create(qf_ctx** out, int device, void* hip_stream) {

@@ -2,10 +2,13 @@
 // kernels.  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include "qf_device.h"
+#include "qf_pair_geom.h"
 #include "qfactor.h"
 
 namespace qf {
@@ -93,13 +96,14 @@ struct EnvArgs {
   double* gates;   // c128, per start stride gstride complex entries
   int64_t gstride;
   int gidx;
-  double* uold;    // c128 S x 16 (update mode)
+  double* uold;    // c128, u_old of start s at uold + 2 * uold_stride * s (update mode)
   double* env_out; // c128 S x 16, optional
   const int32_t* frozen;  // optional per-start flag: nonzero keeps the gate
   double* partials;       // c128 S x nwg x 16 (needed when nwg > 1)
   int32_t* counters;      // S ints, zero before the first launch; left zero
   int kind;               // qf_gate_kind of the updated gate (update mode)
   int nwg;                // workgroups per start; 0 = env_workgroups(n, S)
+  int64_t uold_stride = 16;  // complex entries between consecutive starts' u_old
 };
 // Workgroups per start of the partial trace: at least env_min_workgroups(n)
 // (more than one for n >= 15); env_workgroups(n, S) spreads a launch of S
@@ -116,6 +120,29 @@ hipError_t launch_env(hipStream_t st, int precision, const void* X, const EnvArg
 bool fused_supported(int precision, int n, const PassGeom& g);
 hipError_t launch_fused(hipStream_t st, int precision, const void* Xe, const EnvArgs& ea, void* Xp, int Sp,
                         const PassGeom& g, Operand A, Operand B);
+
+// Two consecutive gate updates F then S with one partial trace and one
+// builder pass (qf_pair.hip).  The geometry comes from make_pair2_geom with
+// wlog = pair2_wlog(precision, m).
+struct Env2Args {
+  Pair2Geom geom;
+  int n_starts;
+  EnvArgs F, S;            // per-gate update arguments: gates, gstride, gidx, half, beta, kind, uold
+                           // (slot of the gate; uold_stride between starts)
+  const int32_t* frozen;   // per start, nullptr = none
+  double* partials;        // c128, env2_workgroups_cap(n) x 4^m sums per start (when more than one)
+  int32_t* counters;       // per start, zero before the launch; left zero
+  void* ops;               // out: per start the pass's operands A_F, B_F, A_S, B_S (64 entries in the
+                           // builder precision)
+  int nwg;                 // gather workgroups per start; 0 = env2_workgroups(n, m, n_starts).  The sums
+                           // depend on it, so every launch of one instantiation passes the same value
+};
+uint32_t pair2_wlog(int precision, int m);
+uint32_t env2_workgroups(int n, int m, int S);  // gather workgroups per start for a launch of S starts
+uint32_t env2_workgroups_cap(int n);            // the most of them for any m and S (workspace sizing)
+hipError_t launch_env2(hipStream_t st, int precision, const void* X, const Env2Args& a, KernelEvents ev = {});
+hipError_t launch_pass2(hipStream_t st, int precision, void* X, int S, const Pair2Geom& g, const void* ops,
+                        KernelEvents ev = {});
 
 hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int S, double* cost,
                        double* trace);
@@ -183,5 +210,45 @@ hipError_t launch_su4_vjp(hipStream_t st, const double* theta, const double* gra
                           double* dtheta);
 hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs& a);
 size_t resident_lds_bytes(int n, int precision);
+
+
+// Read a value that is the same in every lane into a scalar register.
+template <typename R>
+__device__ __forceinline__ R uniform_r(R v);
+template <>
+__device__ __forceinline__ float uniform_r<float>(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+template <>
+__device__ __forceinline__ double uniform_r<double>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Operand of a workgroup-uniform start s, held in scalar registers.
+template <typename R>
+__device__ __forceinline__ void load_operand_uniform(cx<R> m[16], const Operand& op, uint32_t s) {
+  const cd* src = reinterpret_cast<const cd*>(op.ptr) + (int64_t)s * op.stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cd v = op.dagger ? conj(src[4 * c + r]) : src[4 * r + c];
+      m[4 * r + c] = cx<R>{uniform_r<R>((R)v.re), uniform_r<R>((R)v.im)};
+    }
+}
+
+// Plain launch, or one whose dispatch stamps the events of `ev`.
+template <typename F, typename... Args>
+inline hipError_t launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, KernelEvents ev,
+                           Args... args) {
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, st, ev.start, ev.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+  return hipGetLastError();
+}
 
 }  // namespace qf

@@ -1,0 +1,479 @@
+// Two consecutive gate updates of a sweep (Alg. 1, TwoSidedSweep) with one
+// partial trace and one pass over the builder.
+//
+// Let F be updated first and S second, U the union of their qubits (3 or 4
+// qubits) and X the builder before F's update.  In the first half of a
+// sweep F's update is X' = (u_F^dagger (x) I) X (u_F' (x) I); every operator
+// on U commutes with the partial trace over the qubits outside U, so with
+// T = Tr_{rest U} X (a 2^|U| x 2^|U| matrix):
+//   P_F = Tr_{U \ F} T                                 (F's partial trace)
+//   P_S = Tr_{U \ S} [(u_F^dagger)_U T (u_F')_U]       (S's, after F's update)
+// (second half: (u_F')_U T (u_F^dagger)_U).  So one gather of T gives both
+// environments, the two FP64 updates run back to back, and the builder takes
+// both updates in one pass: X'' = (A_S A_F (x) I) X (B_F B_S (x) I), applied
+// block by block as F's two-sided 4x4 update followed by S's.  Every update
+// sees the environment it sees in Alg. 1; only the summation order differs.
+//
+//   k_env2   T in FP64 (gathered by several workgroups per start, whose
+//            partial sums the last to arrive adds in a fixed order), then
+//            F's and S's gate updates
+//   k_pass2  the pass: LDS tiles of 2^|U| rows x 2^|U| W columns, loaded and
+//            stored in address order, F's then S's 4x4 block updates on the
+//            tile in LDS; each workgroup walks several tiles with the next
+//            tile's loads in flight under the current tile's products
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "qf_device.h"
+#include "qf_env_finish.h"
+#include "qf_internal.h"
+#include "qf_pair_geom.h"
+
+namespace qf {
+
+// ------------------------------------------------------------------ k_pass2
+
+// Tile shape per (builder precision, union size M): 4^M W entries, 32 KiB of
+// builder data plus one pad entry per (row, column variant) of LDS; memory
+// phases move 16-byte units (two complex64 entries or one complex128), 8 per
+// thread; in a product phase a thread owns one 4x4 block of the gate.
+template <typename R, int M>
+struct Pair2Cfg {
+  static constexpr uint32_t kWlog = (sizeof(R) == 4 ? 4u : 3u) + (M == 3 ? 2u : 0u);
+  static constexpr uint32_t kW = 1u << kWlog;
+  static constexpr uint32_t kEpu = sizeof(R) == 4 ? 2u : 1u;   // entries per 16-byte unit
+  static constexpr uint32_t kUprLog = M == 4 ? 7u : 8u;         // units per tile row, log2
+  static constexpr uint32_t kRowStep = 256u >> kUprLog;        // rows between a thread's units
+  static constexpr uint32_t kRowStride = (1u << M) * (kW + 1u);
+  static constexpr uint32_t kLds = (1u << M) * kRowStride;     // entries
+  static constexpr uint32_t kActive = 1u << (kWlog + 2u * (M - 2u));  // threads owning a block
+};
+static_assert(Pair2Cfg<float, 4>::kActive == 256 && Pair2Cfg<float, 3>::kActive == 256, "one block per thread");
+static_assert(Pair2Cfg<double, 4>::kActive == 128 && Pair2Cfg<double, 3>::kActive == 128, "one block per thread");
+static_assert((1u << 4) * (1u << Pair2Cfg<float, 4>::kUprLog) == 2048u, "8 units per thread");
+static_assert((1u << 3) * (1u << Pair2Cfg<float, 3>::kUprLog) == 2048u, "8 units per thread");
+
+uint32_t pair2_wlog(int precision, int m) {
+  if (precision == QF_C64) return m == 4 ? Pair2Cfg<float, 4>::kWlog : Pair2Cfg<float, 3>::kWlog;
+  return m == 4 ? Pair2Cfg<double, 4>::kWlog : Pair2Cfg<double, 3>::kWlog;
+}
+
+// One gate's two-sided 4x4 block update on the LDS tile: x <- A x B for the
+// block of thread t (rows and columns varying in the gate's two union
+// indices gi, the other union bits and the rest column offset fixed by t).
+template <typename R, int M>
+__device__ __forceinline__ void pair2_phase(cx<R>* tile, const Pair2Geom& g, const uint32_t gi[2],
+                                            const uint32_t oi[2], const cx<R>* __restrict__ a,
+                                            const cx<R>* __restrict__ b, uint32_t t) {
+  using C = Pair2Cfg<R, M>;
+  // Recomputed in every phase rather than kept across the tile loop: the
+  // sixteen LDS addresses would otherwise be hoisted out of it and spilled.
+  __asm__ volatile("" : "+v"(t));
+  const uint32_t w = t & (C::kW - 1u);
+  const uint32_t orow = (t >> C::kWlog) & ((1u << (M - 2)) - 1u);
+  const uint32_t ocol = t >> (C::kWlog + M - 2);
+  const uint32_t vr = var_other(orow, oi, M), vc = var_other(ocol, oi, M);
+  uint32_t ar[4], ac[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    ar[i] = (var_local(i, gi[0], gi[1]) | vr) * C::kRowStride;
+    ac[i] = (var_local(i, gi[0], gi[1]) | vc) * (C::kW + 1u) + w;
+  }
+  cx<R> x[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * i + j] = tile[ar[i] + ac[j]];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {  // x <- A x
+    cx<R> r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cmac(acc, a[4 * i + k], x[4 * k + j]);
+      r[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[4 * i + j] = r[i];
+  }
+  __asm__ volatile("" ::: "memory");  // B's scalar loads after A's products: half the registers
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // x <- x B
+    cx<R> r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) cmac(acc, x[4 * i + l], b[4 * l + j]);
+      r[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * i + j] = r[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[ar[i] + ac[j]] = x[4 * i + j];
+}
+
+// 16-byte unit of the memory phases: two complex64 entries or one complex128.
+template <typename R>
+struct Unit16T;
+template <>
+struct Unit16T<float> {
+  using type = float4;
+};
+template <>
+struct Unit16T<double> {
+  using type = double2;
+};
+
+// ops: per start the four 4x4 operands A_F, B_F, A_S, B_S in the builder
+// precision (64 entries, written by k_env2): x <- A_S A_F x B_F B_S.
+template <typename R, int M>
+__device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geom& g, uint32_t total,
+                                           const cx<R>* __restrict__ ops, uint32_t wg, uint32_t n_wg) {
+  using C = Pair2Cfg<R, M>;
+  using Unit16 = typename Unit16T<R>::type;
+  __shared__ cx<R> tile[C::kLds];
+  const uint32_t t = threadIdx.x;
+  const uint32_t N = g.N;
+  // This thread's memory-order unit: the same column set in every row it
+  // moves (rows a0, a0 + kRowStep, ...).
+  const uint32_t ku = t & ((1u << C::kUprLog) - 1u);
+  const uint32_t a0 = t >> C::kUprLog;
+  const uint32_t k = ku * C::kEpu;
+  const uint32_t colk = dep_free(g, k);
+  const uint32_t lk0 = lds_of_k(g, k);
+  const uint32_t lk1 = C::kEpu == 2 ? lds_of_k(g, k + 1) : 0u;
+  // Row of unit jj: a0 + jj * kRowStep, whose bits split into the thread's
+  // a0 (below kRowStep) and a workgroup-uniform part, so its element offset
+  // is the thread's part plus a scalar.
+  const uint32_t row_t = dep_union(g, a0) * N;
+  uint32_t row_u[8];
+#pragma unroll
+  for (uint32_t jj = 0; jj < 8; ++jj) row_u[jj] = __builtin_amdgcn_readfirstlane(dep_union(g, jj * C::kRowStep) * N);
+
+  auto tile_origin = [&](uint32_t tl, uint32_t& s, size_t& origin) {
+    s = tl / g.tiles_per_start;
+    const uint32_t rem = tl - s * g.tiles_per_start;
+    const uint32_t rq = rem / g.col_tiles;
+    const uint32_t ct = rem - rq * g.col_tiles;
+    origin = (size_t)s * N * N + (size_t)dep_rest(g, rq) * N + dep_rest(g, ct << g.wlog);
+  };
+  Unit16 buf[8];
+  auto load_tile = [&](size_t origin) {
+    const Unit16* src = reinterpret_cast<const Unit16*>(X + origin + colk);
+#pragma unroll
+    for (uint32_t jj = 0; jj < 8; ++jj) buf[jj] = src[(row_t + row_u[jj]) / C::kEpu];
+  };
+
+  uint32_t tl = wg;
+  if (tl >= total) return;
+  uint32_t s;
+  size_t origin;
+  tile_origin(tl, s, origin);
+  load_tile(origin);
+  while (true) {
+    // scatter the tile's units into LDS
+#pragma unroll
+    for (uint32_t jj = 0; jj < 8; ++jj) {
+      const uint32_t base = (a0 + jj * C::kRowStep) * C::kRowStride;
+      if constexpr (C::kEpu == 2) {
+        const float4 u = buf[jj];
+        tile[base + lk0] = cx<R>{u.x, u.y};
+        tile[base + lk1] = cx<R>{u.z, u.w};
+      } else {
+        const double2 u = buf[jj];
+        tile[base + lk0] = cx<R>{u.x, u.y};
+      }
+    }
+    __syncthreads();
+    // next tile's loads go out now and land under this tile's products
+    const uint32_t next = tl + n_wg;
+    uint32_t s_next = s;
+    size_t origin_next = origin;
+    if (next < total) {
+      tile_origin(next, s_next, origin_next);
+      load_tile(origin_next);
+    }
+    const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
+    if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
+    __syncthreads();
+    if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    __syncthreads();
+    // gather in address order and store
+    Unit16* dst = reinterpret_cast<Unit16*>(X + origin + colk);
+#pragma unroll
+    for (uint32_t jj = 0; jj < 8; ++jj) {
+      const uint32_t base = (a0 + jj * C::kRowStep) * C::kRowStride;
+      Unit16 u;
+      if constexpr (C::kEpu == 2) {
+        const cx<R> lo = tile[base + lk0], hi = tile[base + lk1];
+        u = Unit16{lo.re, lo.im, hi.re, hi.im};
+      } else {
+        const cx<R> v = tile[base + lk0];
+        u = Unit16{v.re, v.im};
+      }
+      dst[(row_t + row_u[jj]) / C::kEpu] = u;
+    }
+    if (next >= total) break;
+    __syncthreads();  // the tile's LDS is rewritten next
+    tl = next;
+    s = s_next;
+    origin = origin_next;
+  }
+}
+
+template <typename R, int M>
+__global__ __launch_bounds__(256, 4) void k_pass2(cx<R>* __restrict__ X, Pair2Geom g, uint32_t total,
+                                                  const cx<R>* __restrict__ ops) {
+  pass2_body<R, M>(X, g, total, ops, blockIdx.x, gridDim.x);
+}
+
+// Tiles per workgroup of the two-gate pass (each workgroup walks this many
+// tiles, the next one's loads in flight under the current one's products)
+// unless the caller passes its own (the runtime tunes it per precision and
+// n).
+constexpr uint32_t kPass2TilesPerWG = 2;
+
+template <typename R, int M>
+static hipError_t launch_pass2_t(hipStream_t st, void* X, int S, const Pair2Geom& g, const void* ops,
+                                 KernelEvents ev) {
+  if (g.wlog != Pair2Cfg<R, M>::kWlog || g.m != (uint32_t)M) return hipErrorInvalidValue;
+  const uint32_t total = (uint32_t)S * g.tiles_per_start;
+  const uint32_t tpw = g.tiles_per_wg ? g.tiles_per_wg : kPass2TilesPerWG;
+  const uint32_t grid = (total + tpw - 1) / tpw;
+  return launch_k(k_pass2<R, M>, dim3(grid), dim3(256), 0u, st, ev, reinterpret_cast<cx<R>*>(X), g, total,
+                  reinterpret_cast<const cx<R>*>(ops));
+}
+
+hipError_t launch_pass2(hipStream_t st, int precision, void* X, int S, const Pair2Geom& g, const void* ops,
+                        KernelEvents ev) {
+  if (!ops || (reinterpret_cast<uintptr_t>(X) & 15u) != 0) return hipErrorInvalidValue;
+  if (precision == QF_C64)
+    return g.m == 4 ? launch_pass2_t<float, 4>(st, X, S, g, ops, ev) : launch_pass2_t<float, 3>(st, X, S, g, ops, ev);
+  return g.m == 4 ? launch_pass2_t<double, 4>(st, X, S, g, ops, ev) : launch_pass2_t<double, 3>(st, X, S, g, ops, ev);
+}
+
+// ------------------------------------------------------------------ k_env2
+
+constexpr uint32_t kEnv2Threads = 256;
+constexpr uint32_t kEnv2Loads = 16;  // loads in flight per thread and round
+
+struct Env2Dev {
+  Pair2Geom g;
+  EnvDev dF, dS;             // per-gate update arguments (gates, kinds, u_old slots, half, beta)
+  void* ops;                 // per start 64 builder-precision entries: A_F, B_F, A_S, B_S
+  const int32_t* frozen;
+  double* partials;          // c128, per start nwg x 4^M partial sums (nwg > 1)
+  int32_t* counters;         // per start, zero before the launch; left zero
+  uint32_t nrest, nwg, rests_per_wg;
+};
+
+// Workgroups per start of the gather of T.  The gather reads 4^M entries per
+// rest, often one cache line each, so one workgroup per start leaves it to a
+// few CUs' load bandwidth; it is spread so that a launch has about 64
+// workgroups (at most 16 per start, whose partial sums the last one to
+// arrive adds), and so that no workgroup needs more than four rounds of
+// loads.  (Each extra workgroup costs a device-scope release, an L2
+// write-back, which is why the spread stays small and why the launch that
+// runs beside another group's pass keeps one workgroup per start.)
+static uint32_t env2_lanes(int m) { return kEnv2Threads >> (2 * m); }
+uint32_t env2_workgroups(int n, int m, int S) {
+  const uint32_t lanes = env2_lanes(m);
+  const uint32_t per_lane = ((1u << n) >> m) / lanes;   // rests per lane with one workgroup
+  const uint32_t rounds4 = (per_lane + 4 * kEnv2Loads - 1) / (4 * kEnv2Loads);
+  const uint32_t spread = std::min(16u, std::max(1u, 64u / (uint32_t)std::max(1, S)));
+  return std::max(1u, std::min(per_lane, std::max(rounds4, spread)));
+}
+uint32_t env2_workgroups_cap(int n) {
+  return std::max(std::max(env2_workgroups(n, 3, 1), env2_workgroups(n, 4, 1)), 1u);
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void env2_body(const cx<R>* __restrict__ X, const Env2Dev& d, uint32_t wg) {
+  constexpr uint32_t E = 1u << (2 * M);  // entries of T
+  constexpr uint32_t V = 1u << M;        // variants per side
+  constexpr uint32_t LP = kEnv2Threads / E;
+  static_assert(LP >= 1, "one thread per entry at least");
+  __shared__ cd red[kEnv2Threads];
+  __shared__ cd uF[16], uS[16], unF[16], unS[16], P[16];
+  __shared__ cd Msh[16 << (M - 2)];
+  __shared__ int last, frz;
+  const Pair2Geom& g = d.g;
+  const uint32_t t = threadIdx.x;
+  const uint32_t s = wg / d.nwg;
+  const uint32_t w = wg - s * d.nwg;
+  const EnvArgs& aF = d.dF.a;
+  const EnvArgs& aS = d.dS.a;
+  // old gates and the frozen flag, fetched under the gather
+  if (t < 16)
+    uF[t] = reinterpret_cast<const cd*>(aF.gates)[(int64_t)s * aF.gstride + 16 * (int64_t)aF.gidx + t];
+  else if (t < 32)
+    uS[t - 16] = reinterpret_cast<const cd*>(aS.gates)[(int64_t)s * aS.gstride + 16 * (int64_t)aS.gidx + t - 16];
+  else if (t == 32)
+    frz = (d.frozen && d.frozen[s]) ? 1 : 0;
+  // T[a][b] = sum over rests r of X[(r, a), (r, b)]
+  const uint32_t e = t & (E - 1u), lane = t / E;
+  const uint32_t ro = dep_union(g, e / V), co = dep_union(g, e & (V - 1u));
+  const cx<R>* Xs = X + (size_t)s * g.N * g.N;
+  const uint32_t r_begin = w * d.rests_per_wg;
+  const uint32_t r_end = min(d.nrest, r_begin + d.rests_per_wg);
+  cd acc = mk(0.0, 0.0);
+  for (uint32_t r0 = r_begin + lane; r0 < r_end; r0 += kEnv2Loads * LP) {
+    cx<R> v[kEnv2Loads];
+#pragma unroll
+    for (uint32_t kk = 0; kk < kEnv2Loads; ++kk) {
+      const uint32_t rest = r0 + kk * LP;
+      v[kk] = mk<R>(0, 0);
+      if (rest < r_end) {
+        const uint32_t base = dep_rest(g, rest);
+        v[kk] = Xs[(size_t)(base | ro) * g.N + (base | co)];
+      }
+    }
+#pragma unroll
+    for (uint32_t kk = 0; kk < kEnv2Loads; ++kk) acc = acc + mk((double)v[kk].re, (double)v[kk].im);
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (uint32_t stride = kEnv2Threads / 2; stride >= E; stride >>= 1) {
+    if (t < stride) red[t] = red[t] + red[t + stride];
+    __syncthreads();
+  }
+  if (d.nwg > 1) {
+    // Hand-off to the last workgroup of the start: the partial sums are
+    // stored, the workgroup's barrier orders them before thread 0's
+    // release at device scope (one L2 write-back per workgroup), and only
+    // the last to arrive acquires (one invalidate), then reads them with
+    // device-scope loads.
+    cd* part = reinterpret_cast<cd*>(d.partials) + ((size_t)s * d.nwg + w) * E;
+    if (t < E) part[t] = red[t];
+    __syncthreads();
+    if (t == 0) {
+      const int old = __hip_atomic_fetch_add(&d.counters[s], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      last = (old == (int)d.nwg - 1);
+      if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!last) return;
+    if (t < E) {
+      const cd* ps = reinterpret_cast<const cd*>(d.partials) + (size_t)s * d.nwg * E;
+      cd sum = mk(0.0, 0.0);
+      for (uint32_t kk = 0; kk < d.nwg; ++kk) {
+        const double* q = reinterpret_cast<const double*>(&ps[kk * E + t]);
+        const double re = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double im = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sum = sum + mk(re, im);
+      }
+      red[t] = sum;
+    }
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(&d.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const cd* T = red;
+  // F's partial trace: P_F[i][j] = sum over the variants o of U \ F of
+  // T[(F = i, o), (F = j, o)]
+  if (t < 16) {
+    const uint32_t i = t >> 2, j = t & 3u;
+    cd sum = mk(0.0, 0.0);
+    for (uint32_t o = 0; o < (1u << (M - 2)); ++o) {
+      const uint32_t vo = var_other(o, g.o_f, M);
+      sum = sum + T[(var_local(i, g.f_idx[0], g.f_idx[1]) | vo) * V + (var_local(j, g.f_idx[0], g.f_idx[1]) | vo)];
+    }
+    P[t] = sum;
+  }
+  __syncthreads();
+  env_finish(d.dF, s, P, uF, frz != 0, t, unF);
+  __syncthreads();
+  // S's partial trace after F's update: P_S = Tr_{U\S}[A_F T B_F] with
+  // (A_F, B_F) = (u_F^dagger, u_F') in the first half, (u_F', u_F^dagger) in
+  // the second (A_F acts on the row variant's F bits, B_F on the column's).
+  if (t < (16u << (M - 2))) {
+    const uint32_t o = t >> 4, i = (t >> 2) & 3u, j = t & 3u;
+    const uint32_t vo = var_other(o, g.o_s, M);
+    const uint32_t ra = var_local(i, g.s_idx[0], g.s_idx[1]) | vo;
+    const uint32_t cb = var_local(j, g.s_idx[0], g.s_idx[1]) | vo;
+    const uint32_t fmask = (1u << g.f_idx[0]) | (1u << g.f_idx[1]);
+    const uint32_t xa = (((ra >> g.f_idx[0]) & 1u) << 1) | ((ra >> g.f_idx[1]) & 1u);  // F-local row of ra
+    const uint32_t yb = (((cb >> g.f_idx[0]) & 1u) << 1) | ((cb >> g.f_idx[1]) & 1u);  // F-local column of cb
+    const bool h0 = aF.half == 0;
+    cd sum = mk(0.0, 0.0);
+#pragma unroll
+    for (uint32_t kk = 0; kk < 4; ++kk) {
+      const uint32_t rk = (ra & ~fmask) | var_local(kk, g.f_idx[0], g.f_idx[1]);
+      cd inner = mk(0.0, 0.0);
+#pragma unroll
+      for (uint32_t l = 0; l < 4; ++l) {
+        const uint32_t cl = (cb & ~fmask) | var_local(l, g.f_idx[0], g.f_idx[1]);
+        const cd bfl = h0 ? unF[4 * l + yb] : conj(uF[4 * yb + l]);
+        cmac(inner, T[rk * V + cl], bfl);
+      }
+      const cd afk = h0 ? conj(uF[4 * kk + xa]) : unF[4 * xa + kk];
+      cmac(sum, afk, inner);
+    }
+    Msh[t] = sum;
+  }
+  __syncthreads();
+  if (t < 16) {
+    cd sum = mk(0.0, 0.0);
+    for (uint32_t o = 0; o < (1u << (M - 2)); ++o) sum = sum + Msh[(o << 4) | t];
+    P[t] = sum;
+  }
+  __syncthreads();
+  env_finish(d.dS, s, P, uS, frz != 0, t, unS);
+  __syncthreads();
+  // the pass's operands: (A, B) = (u^dagger, u') per gate in the first half,
+  // (u', u^dagger) in the second; x <- A_S A_F x B_F B_S
+  if (t < 64) {
+    const uint32_t which = t >> 4, r = (t >> 2) & 3u, c = t & 3u;
+    const cd* uo = which < 2 ? uF : uS;
+    const cd* un = which < 2 ? unF : unS;
+    const bool dag = (which & 1u) == (aF.half == 0 ? 0u : 1u);
+    const cd v = dag ? conj(uo[4 * c + r]) : un[4 * r + c];
+    reinterpret_cast<cx<R>*>(d.ops)[(size_t)s * 64 + t] = cx<R>{(R)v.re, (R)v.im};
+  }
+}
+
+template <typename R, int M>
+__global__ __launch_bounds__(kEnv2Threads) void k_env2(const cx<R>* __restrict__ X, Env2Dev d) {
+  env2_body<R, M>(X, d, blockIdx.x);
+}
+
+static hipError_t make_env2_dev(const Env2Args& a, Env2Dev& d) {
+  d = Env2Dev{};
+  d.g = a.geom;
+  const int M = (int)a.geom.m;
+  if (M != 3 && M != 4) return hipErrorInvalidValue;
+  d.dF.a = a.F;
+  d.dS.a = a.S;
+  d.dF.a.do_update = d.dS.a.do_update = 1;
+  d.dF.a.env_out = d.dS.a.env_out = nullptr;
+  d.frozen = a.frozen;
+  d.ops = a.ops;
+  d.partials = a.partials;
+  d.counters = a.counters;
+  d.nrest = a.geom.N >> M;
+  d.nwg = a.nwg > 0 ? (uint32_t)a.nwg : env2_workgroups((int)a.geom.n, M, a.n_starts);
+  if (d.nwg > env2_workgroups_cap((int)a.geom.n) || d.nwg > d.nrest) return hipErrorInvalidValue;
+  d.rests_per_wg = (d.nrest + d.nwg - 1) / d.nwg;
+  if (!a.ops || !a.counters) return hipErrorInvalidValue;
+  if (d.nwg > 1 && !a.partials) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+hipError_t launch_env2(hipStream_t st, int precision, const void* X, const Env2Args& a, KernelEvents ev) {
+  Env2Dev d;
+  const hipError_t e = make_env2_dev(a, d);
+  if (e != hipSuccess) return e;
+  const dim3 grid((uint32_t)a.n_starts * d.nwg), block(kEnv2Threads);
+  if (precision == QF_C64)
+    return d.g.m == 4 ? launch_k(k_env2<float, 4>, grid, block, 0u, st, ev, reinterpret_cast<const cf*>(X), d)
+                      : launch_k(k_env2<float, 3>, grid, block, 0u, st, ev, reinterpret_cast<const cf*>(X), d);
+  return d.g.m == 4 ? launch_k(k_env2<double, 4>, grid, block, 0u, st, ev, reinterpret_cast<const cd*>(X), d)
+                    : launch_k(k_env2<double, 3>, grid, block, 0u, st, ev, reinterpret_cast<const cd*>(X), d);
+}
+
+}  // namespace qf

@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 
 #include "qf_device.h"
+#include "qf_env_finish.h"
 #include "qf_internal.h"
 
 namespace qf {
@@ -247,33 +248,6 @@ __global__ __launch_bounds__(256) void k_pass(cx<R>* __restrict__ X, PassGeom g,
 // faster).  The runtime's tuner picks between the forms per (precision, n,
 // gate class).
 
-template <typename R>
-__device__ __forceinline__ R uniform_r(R v);
-template <>
-__device__ __forceinline__ float uniform_r<float>(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-template <>
-__device__ __forceinline__ double uniform_r<double>(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
-
-// Operand of a workgroup-uniform start s, held in scalar registers.
-template <typename R>
-__device__ __forceinline__ void load_operand_uniform(cx<R> m[16], const Operand& op, uint32_t s) {
-  const cd* src = reinterpret_cast<const cd*>(op.ptr) + (int64_t)s * op.stride;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const cd v = op.dagger ? conj(src[4 * c + r]) : src[4 * r + c];
-      m[4 * r + c] = cx<R>{uniform_r<R>((R)v.re), uniform_r<R>((R)v.im)};
-    }
-}
-
 template <typename R, bool HA, bool HB>
 __device__ __forceinline__ void pass_block_body(cx<R>* __restrict__ X, const PassGeom& g, uint32_t wg_per_start,
                                                 const Operand& A, const Operand& B, uint32_t wg) {
@@ -492,16 +466,6 @@ __global__ __launch_bounds__(256) void k_pass_micro(cf* __restrict__ X, uint32_t
 }
 
 // A launch, with the kernel's own start / stop timestamps when asked for.
-template <typename F, typename... Args>
-static hipError_t launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, KernelEvents ev,
-                           Args... args) {
-  if (ev.start || ev.stop)
-    hipExtLaunchKernelGGL(kernel, grid, block, lds, st, ev.start, ev.stop, 0u, args...);
-  else
-    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
-  return hipGetLastError();
-}
-
 template <int B0, int B1, bool HA, bool HB>
 static hipError_t launch_pass_micro_t(hipStream_t st, cf* x, int S, const PassGeom& g, Operand A, Operand B,
                                       KernelEvents ev) {
@@ -632,95 +596,6 @@ hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void*
 }
 
 // ------------------------------------------------------------------ k_env
-
-struct EnvDev {
-  EnvArgs a;
-  uint32_t N, nrest, b0, b1, rlo, rhi, nwg, rests_per_wg;
-};
-
-// Finish one start on the 4 lanes of a quad (lane r = row r): P (16 FP64
-// complex, LDS) -> env_out and/or the gate update.
-__device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
-                                       int r) {
-  const EnvArgs& a = d.a;
-  if (!a.do_update) {
-    if (a.env_out) {
-      cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) eo[4 * r + c] = P[4 * r + c];
-    }
-    return;
-  }
-  cd* gp = reinterpret_cast<cd*>(a.gates) + (int64_t)s * a.gstride + 16 * (int64_t)a.gidx;
-  cd uold[16];  // loaded into LDS at kernel start, under the partial trace
-#pragma unroll
-  for (int k = 0; k < 16; ++k) uold[k] = u_sh[k];
-  // E = u_old^dagger P (half 0) or P u_old^dagger (half 1): the removal of the
-  // old gate commutes with the partial trace.  Row r of E:
-  cd erow[4], urow[4], unew[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cd acc = mk(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (a.half == 0)
-        cmac(acc, conj(at_kr(uold, k, r)), P[4 * k + c]);
-      else
-        cmac(acc, P[4 * r + k], conj(uold[4 * c + k]));
-    }
-    erow[c] = acc;
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cd v = uold[c];
-#pragma unroll
-    for (int rr = 1; rr < 4; ++rr) v = sel(r == rr, uold[4 * rr + c], v);
-    urow[c] = v;
-  }
-  if (a.env_out) {
-    cd* eo = reinterpret_cast<cd*>(a.env_out) + 16 * (size_t)s;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) eo[4 * r + c] = erow[c];
-  }
-  if (frozen) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) unew[c] = urow[c];
-  } else {
-    update_gate_quad(a.kind, erow, uold, r, a.beta, unew);
-  }
-  cd* uo = reinterpret_cast<cd*>(a.uold) + 16 * (size_t)s;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    uo[4 * r + c] = urow[c];
-    gp[4 * r + c] = unew[c];
-  }
-}
-
-// The general U(4) update on the 16 lanes of a hex (lane i = entry
-// (hex_row(i), i & 3)); bitwise the quad form's result in about two thirds of
-// its time.
-__device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
-                                      int i) {
-  const EnvArgs& a = d.a;
-  const int r = hex_row(i), c = i & 3;
-  const cd e = env_entry(P, u_sh, a.half, r, c);
-  const cd urc = u_sh[4 * r + c];
-  if (a.env_out) reinterpret_cast<cd*>(a.env_out)[16 * (size_t)s + 4 * r + c] = e;
-  cd unew = urc;
-  if (!frozen) optimize_gate_f64_hex(e, u_sh[4 * c + r], urc, r, c, a.beta, unew);
-  reinterpret_cast<cd*>(a.uold)[16 * (size_t)s + 4 * r + c] = urc;
-  reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 16 * (int64_t)a.gidx + 4 * r + c] = unew;
-}
-
-// The finishing step of one start by the lanes it needs.
-__device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
-                                          uint32_t t) {
-  if (d.a.do_update && d.a.kind == kKindU4) {
-    if (t < 16) env_finish_hex(d, s, P, u_sh, frozen, (int)t);
-  } else if (t < 4) {
-    env_finish_quad(d, s, P, u_sh, frozen, (int)t);
-  }
-}
 
 // Grid: S x nwg workgroups of kEnvThreads threads.  Thread t sums entry (i,j) = t%16
 // over its rests (eight loads in flight at a time); the workgroup reduces to

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "lib")
 LIBNAME = "libqfactor_mi355x.so"
-SOURCES = ["qf_stream.hip", "qf_resident.hip", "qf_batch.hip", "qf_grad.hip", "qf_k3.hip", "qf_abi.hip"]
+SOURCES = ["qf_stream.hip", "qf_pair.hip", "qf_resident.hip", "qf_batch.hip", "qf_grad.hip", "qf_k3.hip",
+           "qf_abi.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for every HIP translation unit.

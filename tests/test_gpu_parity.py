@@ -520,14 +520,15 @@ def test_stream_schedules_bitwise_equal(qf, S):
 
 
 def test_timing_run_same_results_and_consistent_durations(qf):
-    """The per-kernel timing run (starts as one group, every pass and
+    """One pass per gate update (gate_pairs = 0): the per-kernel timing run
+    (starts as one group, every pass and
     environment launch stamped by its own dispatch) gives bitwise the
     default schedule's gates and costs, counts 2p passes and 2p environment
     steps per sweep, and its kernels, which run one after another on one
     stream, sum to no more than the sweep loop's device time."""
     pr = I.config3(n_starts=4)
     sweeps = 2
-    kw = dict(tol=1e-300, max_iter=sweeps, precision=1, diff_tol_r=0.0, long_diff_count=0)
+    kw = dict(tol=1e-300, max_iter=sweeps, precision=1, diff_tol_r=0.0, long_diff_count=0, gate_pairs=0)
     V, g = dev(pr.target), dev(pr.init_gates)
     a = qf.instantiate(V, pr.locs, g, **kw)
     b = qf.instantiate(V, pr.locs, g, timing=True, **kw)
