@@ -351,7 +351,12 @@ def n12_workload(qf, torch, K3) -> dict:
     _, r12, _ = timed_sweeps(qf, torch, V12, pr12.locs, one, 1, K3, 0, timing=True)
     t12 = r12.timing
     b12 = 2 * N * N * 8
-    a12 = b12 / (t12["pass_ms"] / max(1, t12["pass_launches"]) * 1e-3) / 1e9
+
+    def pass_avg_ms(t):
+        if t.get("pass2_launches", 0) > 0:
+            return t["pass2_ms"] / t["pass2_launches"]
+        return t["pass_ms"] / max(1, t["pass_launches"])
+    a12 = b12 / (pass_avg_ms(t12) * 1e-3) / 1e9
     out["n12_c64_sweeps_per_s"] = round(K3 / d12, 3)
     out["n12_c64_pass_GBps"] = round(a12, 1)
     out["n12_c64_env_us"] = round(1e3 * t12["env_ms"] / max(1, t12["env_launches"]), 2)
@@ -364,7 +369,7 @@ def n12_workload(qf, torch, K3) -> dict:
     _, r4, _ = timed_sweeps(qf, torch, V12, pr12.locs, init12, 1, K3, 0, timing=True)
     t4 = r4.timing
     b4 = S4 * b12
-    a4 = b4 / (t4["pass_ms"] / max(1, t4["pass_launches"]) * 1e-3) / 1e9
+    a4 = b4 / (pass_avg_ms(t4) * 1e-3) / 1e9
     rmw512 = rmw_ceiling(torch, b4 // 2)
     out["n12_s4_c64_start_sweeps_per_s"] = round(S4 * K3 / d4, 3)
     out["n12_s4_c64_pass_GBps"] = round(a4, 1)
@@ -444,7 +449,13 @@ def main():
     _, rt, _ = timed_sweeps(qf, torch, V, pr.locs, init, 1, K, 0, timing=True)
     tm = rt.timing
     pass_bytes = 2 * S * N * N * 8          # read + write of every builder, complex64
-    pass_avg_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+    # the two-gate pass (k_pass2) when the sweep has them, else every pass
+    if tm.get("pass2_launches", 0) > 0:
+        pass_avg_ms = tm["pass2_ms"] / tm["pass2_launches"]
+        timed_launches = tm["pass2_launches"]
+    else:
+        pass_avg_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+        timed_launches = tm["pass_launches"]
     achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
     env_avg_us = 1e3 * tm["env_ms"] / max(1, tm["env_launches"])
     moved_bytes = int(round(tm["pass_launches"] / K)) * pass_bytes  # builder passes per sweep x bytes each
@@ -469,14 +480,14 @@ def main():
                    "timed_calls": 5, "call_seconds": [round(x, 5) for x in calls]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "builder pass, complex64, 16 builders per launch: the two-gate pass k_pass2 (remove "
-                               "+ re-apply of two consecutive gates in one pass; 44 of the 46 launches of a sweep), "
-                               "and the one-gate pass (k_pass_block / k_pass_micro / k_pass) for the gate left "
-                               "over in each half-sweep; one read + one write of every builder entry per launch; "
-                               "timed alone (all starts in one group, kernel-stamped HIP events) in a second call "
-                               "of the same K sweeps",
+                     "kernel": "qf::k_pass2<float, 4>: the two-gate builder pass (remove + re-apply of two "
+                               "consecutive gates in one pass, complex64, 16 builders per launch; 44 of the 46 "
+                               "passes of a sweep, the other 2 are one-gate passes for the gate left over in each "
+                               "half-sweep); one read + one write of every builder entry per launch; timed alone "
+                               "(all starts in one group, kernel-stamped HIP events) in a second call of the same "
+                               "K sweeps",
                      "bytes_per_launch": pass_bytes, "avg_launch_us": round(1e3 * pass_avg_ms, 2),
-                     "launches_timed": tm["pass_launches"], "pass_form_mid_gate": tm.get("pass_tcols"),
+                     "launches_timed": timed_launches, "pass_form_mid_gate": tm.get("pass_tcols"),
                      "traffic_source": TRAFFIC_JSON.replace(ROOT + os.sep, "") + " (FETCH_SIZE and WRITE_SIZE, "
                                        "scaled by the same counters on a 256 MiB copy)",
                      "sweep_bytes": sweep_bytes,

@@ -190,6 +190,9 @@ typedef struct {
                             for the register-direct pass; chosen on first use
                             per (precision, gate class, n) by timing the
                             candidates on the caller's builder */
+  int32_t pass2_launches; /* out (timing): the two-gate passes among
+                             pass_launches */
+  double pass2_ms;        /* out (timing): their summed durations */
 } qf_stats;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -362,7 +365,11 @@ int qf_optimize_gate3(qf_ctx* ctx, int count, const void* env, const void* u_old
  *               c128 initial gates (block b starts at n_starts *
  *               gate_offsets[b] * 16 entries)
  *   n_starts:   1..16 starts per block
- *   opt:        as for qf_instantiate (precision applies; mode is ignored);
+ *   opt:        as for qf_instantiate (mode is ignored; both precisions run
+ *               complex128 builders: blocks are at most 16 x 16, held in
+ *               LDS, and their sweeps are chains of FP64 gate updates, so a
+ *               complex64 builder would save nothing and need FP64 cost
+ *               re-evaluations);
  *               tol replaces dist_tol
  *   workspace:  device, >= qf_batch_workspace_size(...)
  *   out_gates:  device, same layout as init_gates: every start's final gates

@@ -64,6 +64,8 @@ class QfStats(ctypes.Structure):
         ("env_ms", ctypes.c_double),
         ("sweep_ms", ctypes.c_double),
         ("pass_tcols", ctypes.c_int32),
+        ("pass2_launches", ctypes.c_int32),
+        ("pass2_ms", ctypes.c_double),
     ]
 
 

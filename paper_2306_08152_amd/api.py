@@ -247,7 +247,8 @@ def instantiate(target: torch.Tensor, locs, init_gates: torch.Tensor, tol: float
         nat.check(rc, ctx)
     h = hist[: min(history_rows, st.sweeps + 1)] if hist is not None else np.zeros((0, S))
     tm = dict(pass_ms=st.pass_ms, pass_launches=st.pass_launches, env_ms=st.env_ms,
-              env_launches=st.env_launches, sweep_ms=st.sweep_ms, pass_tcols=st.pass_tcols) if timing \
+              env_launches=st.env_launches, sweep_ms=st.sweep_ms, pass_tcols=st.pass_tcols,
+              pass2_ms=st.pass2_ms, pass2_launches=st.pass2_launches) if timing \
         else dict(pass_tcols=st.pass_tcols)
     return Result(out, out_all, np.array(costs[:]), st.best_start, st.sweeps, st.status, st.n_resets,
                   st.n_rechecks, st.mode_used, st.elapsed_ms, h, tm)

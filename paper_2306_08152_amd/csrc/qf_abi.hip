@@ -412,10 +412,10 @@ int read_costs(qf_ctx* ctx, const double* dev, int S, std::vector<double>& out) 
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> ev;  // pairs
-  std::vector<int> kind;       // 0 = pass, 1 = env
+  std::vector<int> kind;       // 0 = pass, 1 = env, 2 = two-gate pass
   size_t used = 0;
-  double pass_ms = 0, env_ms = 0, sweep_ms = 0;
-  int pass_n = 0, env_n = 0;
+  double pass_ms = 0, env_ms = 0, sweep_ms = 0, pass2_ms = 0;
+  int pass_n = 0, env_n = 0, pass2_n = 0;
   hipEvent_t s0 = nullptr, s1 = nullptr;
   ~KernelTimer() {
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -434,7 +434,8 @@ struct KernelTimer {
     if (r != hipSuccess) return r;
     return hipEventCreate(&s1);
   }
-  // the event pair for the next launch of kind k (0 = pass, 1 = env), or none
+  // the event pair for the next launch of kind k (0 = pass, 1 = env, 2 =
+  // two-gate pass, which also counts as a pass), or none
   KernelEvents next(int k) {
     if (!on || used >= kind.size()) return {};
     kind[used] = k;
@@ -448,9 +449,13 @@ struct KernelTimer {
       float ms = 0.f;
       hipError_t r = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
       if (r != hipSuccess) return r;
-      if (kind[i] == 0) {
+      if (kind[i] == 0 || kind[i] == 2) {
         pass_ms += ms;
         ++pass_n;
+        if (kind[i] == 2) {
+          pass2_ms += ms;
+          ++pass2_n;
+        }
       } else {
         env_ms += ms;
         ++env_n;
@@ -651,7 +656,7 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     const Env2Args a2 = env2_args(q, u, half);
     QF_HIP(ctx, launch_env2(q.st, prec, q.X, a2, timer.next(1)));
     if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
-    QF_HIP(ctx, launch_pass2(q.st, prec, q.X, q.ns, u.pg, a2.ops, timer.next(0)));
+    QF_HIP(ctx, launch_pass2(q.st, prec, q.X, q.ns, u.pg, a2.ops, timer.next(2)));
     return QF_OK;
   };
   // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved,
@@ -936,6 +941,8 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     stats->env_ms = timer.env_ms;
     stats->pass_launches = timer.pass_n;
     stats->env_launches = timer.env_n;
+    stats->pass2_launches = timer.pass2_n;
+    stats->pass2_ms = timer.pass2_ms;
     stats->sweep_ms = ms;
   }
   out.sweeps = i;
@@ -1430,8 +1437,8 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
     QF_HIP(ctx, hipMemcpyAsync(ws + L.kinds, o.gate_kinds, (size_t)n_gates * 4, hipMemcpyHostToDevice, st));
 
   if (stats) {
-    stats->pass_launches = stats->env_launches = 0;
-    stats->pass_ms = stats->env_ms = stats->sweep_ms = 0.0;
+    stats->pass_launches = stats->env_launches = stats->pass2_launches = 0;
+    stats->pass_ms = stats->env_ms = stats->sweep_ms = stats->pass2_ms = 0.0;
   }
   RunOut out;
   if (mode == QF_MODE_RESIDENT)

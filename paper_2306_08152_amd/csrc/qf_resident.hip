@@ -218,9 +218,13 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
 
   rebuild();
   double c_cur = builder_cost();
+  // complex64: once the cost is below recheck_below the sweeps run on the
+  // FP64 builder Y (escalated), whose costs need no recheck.
+  bool esc = false;
   if (c64 && c_cur < o.recheck_below) {  // the FP64 build is still in Y
     const cd tr = lds_trace<double>(L.Y, N, L.red);
     c_cur = 1.0 - sqrt(norm2(tr)) / (double)N;
+    esc = true;
   }
   double* hist = a.hist + (size_t)s * a.ring;
   if (t == 0) {
@@ -245,7 +249,10 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
       const int half = step < a.p ? 0 : 1;
       const int g = half == 0 ? a.p - 1 - step : step - a.p;
       const uint32_t b0 = n - 1 - a.locs[2 * g], b1 = n - 1 - a.locs[2 * g + 1];
-      lds_ptrace<R>(L.X, n, b0, b1, L.red);
+      if (c64 && esc)
+        lds_ptrace<double>(L.Y, n, b0, b1, L.red);
+      else
+        lds_ptrace<R>(L.X, n, b0, b1, L.red);
       const int kind = a.kinds ? a.kinds[g] : kKindU4;
       if (kind == kKindU4) {
         if (t < 16) {  // general U(4) update on one hex, lane t = entry (hex_row(t), t & 3)
@@ -259,6 +266,8 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
           const cd Av = sel(half == 0, udc, unew), Bv = sel(half == 0, unew, udc);
           L.opsR[4 * r + c] = cx<R>{(R)Av.re, (R)Av.im};
           L.opsR[16 + 4 * r + c] = cx<R>{(R)Bv.re, (R)Bv.im};
+          L.opsD[4 * r + c] = Av;
+          L.opsD[16 + 4 * r + c] = Bv;
         }
       } else if (t < 4) {  // restricted kinds on one quad, lane r = row r
         const int r = (int)t;
@@ -299,10 +308,15 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
           const cd Av = sel(half == 0, udc, unew[c]), Bv = sel(half == 0, unew[c], udc);
           L.opsR[4 * r + c] = cx<R>{(R)Av.re, (R)Av.im};
           L.opsR[16 + 4 * r + c] = cx<R>{(R)Bv.re, (R)Bv.im};
+          L.opsD[4 * r + c] = Av;
+          L.opsD[16 + 4 * r + c] = Bv;
         }
       }
       __syncthreads();
-      lds_pass<R, true, true>(L.X, n, b0, b1, L.opsR, L.opsR + 16);
+      if (c64 && esc)
+        lds_pass<double, true, true>(L.Y, n, b0, b1, L.opsD, L.opsD + 16);
+      else
+        lds_pass<R, true, true>(L.X, n, b0, b1, L.opsR, L.opsR + 16);
       __syncthreads();
     }
     // ---------------- cost, reset, recheck
@@ -310,13 +324,19 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
       rebuild();
       ++resets;
     }
-    double c_i = builder_cost();
-    if (c64 && c_i < o.recheck_below) {
+    double c_i;
+    if (c64 && esc) {
+      const cd tr = lds_trace<double>(L.Y, N, L.red);
+      c_i = 1.0 - sqrt(norm2(tr)) / (double)N;
+    } else {
+      c_i = builder_cost();
+    }
+    if (c64 && !esc && c_i < o.recheck_below) {
+      // FP64 cost from a fresh complex128 builder, which the sweeps use from
+      // now on
       c_i = fp64_cost();
       ++rechecks;
-      // refresh the complex64 builder from the exact one just built
-      for (uint32_t e = t; e < N * N; e += blockDim.x) L.X[e] = cx<R>{(R)L.Y[e].re, (R)L.Y[e].im};
-      __syncthreads();
+      esc = true;
     }
     // ---------------- termination (lockstep over starts)
     if (t == 0) {

@@ -86,9 +86,10 @@ def test_batch_c128_matches_oracle(qf, n_starts):
 
 
 def test_batch_c64_fp64_costs(qf):
-    """Complex64 builders with FP64 updates, recheck and final cost: each
-    returned cost is the oracle's cost of the returned gates, the gates are
-    unitary, and reachable blocks converge."""
+    """A complex64 request (run on complex128 builders, see
+    qf_instantiate_batch): each returned cost is the oracle's cost of the
+    returned gates, the gates are unitary, reachable blocks converge, and the
+    results are bitwise those of the complex128 request."""
     probs = mixed_blocks(31, 12, 4)
     res = run_batch(qf, probs, 1e-8, precision=1)
     for b, pr in enumerate(probs):
@@ -100,6 +101,8 @@ def test_batch_c64_fp64_costs(qf):
         assert res.status[b] == (0 if res.costs[b].min() < 1e-8 else res.status[b])
         if b % 2 == 0:
             assert res.status[b] == 0 and res.costs[b, res.best[b]] < 1e-8, b
+    r128 = run_batch(qf, probs, 1e-8, precision=0)
+    assert np.array_equal(res.costs, r128.costs) and np.array_equal(res.sweeps, r128.sweeps)
 
 
 def test_batch_one_start_and_tiny(qf):
