@@ -334,8 +334,9 @@ int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile
  *   out_all_gates: optional device, n_starts x n_gates x 8 x 8 c128
  *   target, out_costs, tol, stats: as for qf_instantiate.
  * The same sweep order, termination tests, multistart rule, complex64
- * recheck and final FP64 costs as qf_instantiate; all starts run on the
- * context stream (stream_groups and stats->timing are ignored).  Needs
+ * recheck and final FP64 costs as qf_instantiate; the starts run in
+ * stream_groups staggered groups on separate streams (0 = one; results do
+ * not depend on the grouping; stats->timing is ignored).  Needs
  * 3 <= n <= 14, opt->gate_kinds == NULL and mode AUTO or STREAMING (RESIDENT
  * gives QF_EUNSUPPORTED).  The caller owns the workspace
  * (qf_workspace_size3 bytes, 0 for invalid sizes).  Errors as

@@ -19,6 +19,12 @@
 #include "qfactor.h"
 
 constexpr int kMaxGroups = 4;
+// Default stream groups of the three-qubit sweep: one.  Two to four
+// staggered groups were measured at n = 10, 8 starts and gave no overlap
+// (complex64 62.5 us per gate update with one group, 64.6-65.7 with more;
+// complex128 89.6-91.6 either way): every pass fills all CUs, so another
+// group's environment step cannot run beside it.
+constexpr int kDefaultGroups3 = 1;
 
 struct qf_ctx {
   int device = 0;
@@ -1580,24 +1586,73 @@ int run_streaming3(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs
     QF_HIP(ctx, launch_cost(st, QF_C128, dst, n, S, costs, trace));
     return read_costs(ctx, costs, S, c);
   };
-  Env8Args ea{};
-  ea.S = S;
-  ea.do_update = 1;
-  ea.beta = o.beta;
-  ea.gates = gates;
-  ea.gstride = gstride;
-  ea.uold = uold;
-  ea.frozen = frozen;
-  auto update = [&](int g, int half) -> int {
-    ea.half = half;
-    ea.gidx = g;
-    QF_HIP(ctx, launch_env8(st, prec, X, geo[g], ea));
-    const Operand gnew{gates + 2 * 64 * (int64_t)g, gstride, 0};
-    const Operand gold{uold, 64, 1};
+  // The starts split into G groups whose sweeps run on separate streams
+  // (group 0 on the caller's), staggered, so that one group's environment
+  // step (the 8x8 FP64 update's latency) runs while another group's pass
+  // streams.  Every start sees the same kernels in the same order, so the
+  // results do not depend on G.
+  int G = o.stream_groups > 0 ? o.stream_groups : kDefaultGroups3;
+  G = std::min(std::min(G, kMaxGroups), S);
+  if (G > 1) {
+    int rc0 = ensure_aux_streams(ctx);
+    if (rc0) return rc0;
+  }
+  struct Group3 {
+    int s0 = 0, ns = 0;
+    hipStream_t st = nullptr;
+    void* X = nullptr;
+    Env8Args ea{};
+  };
+  Group3 grp[kMaxGroups];
+  for (int gi = 0; gi < G; ++gi) {
+    Group3& q = grp[gi];
+    q.s0 = gi * S / G;
+    q.ns = (gi + 1) * S / G - q.s0;
+    q.st = gi == 0 ? st : ctx->aux[gi - 1];
+    q.X = reinterpret_cast<unsigned char*>(X) + (size_t)q.s0 * N * N * elem_bytes(prec);
+    q.ea.S = q.ns;
+    q.ea.do_update = 1;
+    q.ea.beta = o.beta;
+    q.ea.gates = gates + (size_t)q.s0 * gstride * 2;
+    q.ea.gstride = gstride;
+    q.ea.uold = uold + (size_t)q.s0 * 64 * 2;
+    q.ea.frozen = frozen + q.s0;
+  }
+  auto update = [&](Group3& q, int g, int half, hipEvent_t after_env) -> int {
+    q.ea.half = half;
+    q.ea.gidx = g;
+    QF_HIP(ctx, launch_env8(q.st, prec, q.X, geo[g], q.ea));
+    if (after_env) QF_HIP(ctx, hipEventRecord(after_env, q.st));
+    const Operand gnew{q.ea.gates + 2 * 64 * (int64_t)g, gstride, 0};
+    const Operand gold{q.ea.uold, 64, 1};
     if (half == 0)
-      QF_HIP(ctx, launch_pass8(st, prec, X, S, geo[g], gold, gnew));
+      QF_HIP(ctx, launch_pass8(q.st, prec, q.X, q.ns, geo[g], gold, gnew));
     else
-      QF_HIP(ctx, launch_pass8(st, prec, X, S, geo[g], gnew, gold));
+      QF_HIP(ctx, launch_pass8(q.st, prec, q.X, q.ns, geo[g], gnew, gold));
+    return QF_OK;
+  };
+  // One TwoSidedSweep of every start (Alg. 1 order), groups interleaved,
+  // forked from and joined back to the caller's stream; group k starts once
+  // group k-1's first environment step is done.
+  auto sweep = [&]() -> int {
+    if (G > 1) {
+      QF_HIP(ctx, hipEventRecord(ctx->fork, st));
+      for (int gi = 1; gi < G; ++gi) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->fork, 0));
+    }
+    int rc1;
+    for (int g = p - 1; g >= 0; --g)
+      for (int gi = 0; gi < G; ++gi) {
+        const bool first = (g == p - 1);
+        if (first && gi > 0) QF_HIP(ctx, hipStreamWaitEvent(grp[gi].st, ctx->stagger[gi - 1], 0));
+        if ((rc1 = update(grp[gi], g, 0, (first && gi + 1 < G) ? ctx->stagger[gi] : nullptr))) return rc1;
+      }
+    for (int g = 0; g < p; ++g)
+      for (int gi = 0; gi < G; ++gi)
+        if ((rc1 = update(grp[gi], g, 1, nullptr))) return rc1;
+    for (int gi = 1; gi < G; ++gi) {
+      QF_HIP(ctx, hipEventRecord(ctx->join[gi], grp[gi].st));
+      QF_HIP(ctx, hipStreamWaitEvent(st, ctx->join[gi], 0));
+    }
     return QF_OK;
   };
 
@@ -1648,10 +1703,7 @@ int run_streaming3(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs
   int32_t decision = o.max_iter <= 0 ? kStopMaxIter : kContinue;
   while (decision == kContinue) {
     ++i;
-    for (int g = p - 1; g >= 0; --g)
-      if ((rc = update(g, 0))) return rc;
-    for (int g = 0; g < p; ++g)
-      if ((rc = update(g, 1))) return rc;
+    if ((rc = sweep())) return rc;
     if (o.reset_iter > 0 && i % o.reset_iter == 0) {
       if ((rc = build(prec, X))) return rc;
       ++out.resets;

@@ -186,3 +186,20 @@ def test_instantiate3_rejects_invalid(qf):
         qf.instantiate3(V, pr.locs, g, mode=1)                            # streaming only
     with pytest.raises(QfError):
         qf.optimize_gate3(dev(np.zeros((1, 8, 8), complex)), dev(pr.init_gates[0, :1]), beta=2.0)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_instantiate3_stream_groups_bitwise_equal(qf, precision):
+    """The starts in 1 (the default), 2 or 3 staggered groups on separate
+    streams: every start sees the same kernels in the same order, so gates
+    and costs are bitwise the same (n = 10, 8 starts, one sweep)."""
+    n = 10
+    pr = I.k3_problem(39, n, 3, 8)
+    V = dev(I.haar_unitary(np.random.default_rng(3500), 1 << n))
+    g = dev(pr.init_gates)
+    kw = dict(tol=1e-300, max_iter=1, precision=precision, **NOPLATEAU)
+    a = qf.instantiate3(V, pr.locs, g, **kw)
+    for groups in (1, 2, 3):
+        b = qf.instantiate3(V, pr.locs, g, stream_groups=groups, **kw)
+        assert np.array_equal(host(a.all_gates), host(b.all_gates)), groups
+        assert np.array_equal(a.costs, b.costs), groups
