@@ -28,8 +28,24 @@ HIP_FLAGS = [
 ]
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# sources (device code unchanged): each -fsanitize= applies to the host pass
+# only.  Loaded in a process that preloads the ASan runtime; see
+# tests/test_sanitized_host.py.
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SANITIZED_LIBNAME = "libqfactor_mi355x_asan.so"
+
+
 def lib_path() -> str:
-    return os.path.join(LIBDIR, LIBNAME)
+    """Path of the library the binding loads: the environment variable
+    QF_LIBRARY when set (the sanitized build in its test), else the in-tree
+    build."""
+    return os.environ.get("QF_LIBRARY") or os.path.join(LIBDIR, LIBNAME)
+
+
+def sanitized_lib_path() -> str:
+    return os.path.join(LIBDIR, SANITIZED_LIBNAME)
 
 
 def hipcc() -> str:
@@ -48,26 +64,29 @@ def _run(cmd, verbose):
     return r
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 3, sanitize: bool = False) -> str:
     """Compile every source for gfx950 and link the shared library.  Always
-    rebuilds.  Returns the library path."""
+    rebuilds.  sanitize=True builds the host-sanitized variant instead
+    (sanitized_lib_path()).  Returns the library path."""
     cc = hipcc()
     os.makedirs(LIBDIR, exist_ok=True)
-    objdir = os.path.join(PKG, "_build")
+    objdir = os.path.join(PKG, "_build_asan" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", INCLUDE, "-I", CSRC]
+    extra = SANITIZE_FLAGS if sanitize else []
     objs = []
     cmds = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmds.append([cc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([cc, *HIP_FLAGS, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    tmp = lib_path() + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-    os.replace(tmp, lib_path())
-    return lib_path()
+    out = sanitized_lib_path() if sanitize else os.path.join(LIBDIR, LIBNAME)
+    tmp = out + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, *objs, "-o", tmp], verbose)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
