@@ -19,8 +19,9 @@
 //            F's and S's gate updates
 //   k_pass2  the pass: LDS tiles of 2^|U| rows x 2^|U| W columns, loaded and
 //            stored in address order, F's then S's 4x4 block updates on the
-//            tile in LDS; each workgroup walks several tiles with the next
-//            tile's loads in flight under the current tile's products
+//            tile in LDS (complex64 on the matrix cores); each workgroup
+//            walks several tiles with the next tile's loads in flight under
+//            the current tile's products
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,6 +119,99 @@ __device__ __forceinline__ void pair2_phase(cx<R>* tile, const Pair2Geom& g, con
     for (int j = 0; j < 4; ++j) tile[ar[i] + ac[j]] = x[4 * i + j];
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// complex64 two-sided 4x4 block update x <- A x B on the matrix cores, x in
+// registers (entry (i, j) in x[4 i + j]), every lane of the wavefront owning
+// a block.  v_mfma_f32_4x4x1f32 runs sixteen independent 4 x 4 x 1 products
+// per wavefront: in block b = lane / 4, lane 4 b + r supplies row r of the
+// 4 x 1 left factor, lane 4 b + c column c of the 1 x 4 right factor, and
+// lane 4 b + c receives column c of the 4 x 4 result (entry i in
+// accumulator i).  So every lane's own 4-vector is one column: with lane
+// (lane % 4 = q) supplying row q of the gate matrix, four k-steps give M v
+// for each lane's vector v.  Real and imaginary parts take two accumulators
+// (Re y = Re M Re v - Im M Im v, Im y = Re M Im v + Im M Re v: sixteen
+// products per vector).  The block update is four such products for A x
+// (the block's columns) and four for x B = (B^T x^T)^T (its rows): the same
+// arithmetic as the vector form at twice its rate, off the vector ALUs.
+__device__ __forceinline__ void block_update_mfma(cf (&x)[16], const cf* __restrict__ a, const cf* __restrict__ b,
+                                                  uint32_t t) {
+  const uint32_t q = t & 3u;
+  float mr[4], mi[4], mn[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {  // row q of A
+    const cf v = a[4u * q + k];
+    mr[k] = v.re;
+    mi[k] = v.im;
+    mn[k] = -v.im;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v4f yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      yr = __builtin_amdgcn_mfma_f32_4x4x1f32(mr[k], x[4 * k + j].re, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_4x4x1f32(mr[k], x[4 * k + j].im, yi, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_4x4x1f32(mn[k], x[4 * k + j].im, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_4x4x1f32(mi[k], x[4 * k + j].re, yi, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[4 * i + j] = cf{yr[i], yi[i]};
+  }
+  __asm__ volatile("" ::: "memory");  // B's loads after A's products: fewer live registers
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {  // row q of B^T
+    const cf v = b[4u * k + q];
+    mr[k] = v.re;
+    mi[k] = v.im;
+    mn[k] = -v.im;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v4f yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      yr = __builtin_amdgcn_mfma_f32_4x4x1f32(mr[l], x[4 * i + l].re, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_4x4x1f32(mr[l], x[4 * i + l].im, yi, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_4x4x1f32(mn[l], x[4 * i + l].im, yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_4x4x1f32(mi[l], x[4 * i + l].re, yi, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * i + j] = cf{yr[j], yi[j]};
+  }
+}
+
+// complex64 form of pair2_phase: the block from the LDS tile, its update on
+// the matrix cores (every thread of the workgroup owns a block), and back.
+template <int M>
+__device__ __forceinline__ void pair2_phase_mfma(cf* tile, const Pair2Geom& g, const uint32_t gi[2],
+                                                 const uint32_t oi[2], const cf* __restrict__ a,
+                                                 const cf* __restrict__ b, uint32_t t) {
+  using C = Pair2Cfg<float, M>;
+  static_assert(C::kActive == 256, "every thread owns a block");
+  __asm__ volatile("" : "+v"(t));
+  const uint32_t w = t & (C::kW - 1u);
+  const uint32_t orow = (t >> C::kWlog) & ((1u << (M - 2)) - 1u);
+  const uint32_t ocol = t >> (C::kWlog + M - 2);
+  const uint32_t vr = var_other(orow, oi, M), vc = var_other(ocol, oi, M);
+  uint32_t ar[4], ac[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    ar[i] = (var_local(i, gi[0], gi[1]) | vr) * C::kRowStride;
+    ac[i] = (var_local(i, gi[0], gi[1]) | vc) * (C::kW + 1u) + w;
+  }
+  cf x[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * i + j] = tile[ar[i] + ac[j]];
+  block_update_mfma(x, a, b, t);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[ar[i] + ac[j]] = x[4 * i + j];
+}
+
 // 16-byte unit of the memory phases: two complex64 entries or one complex128.
 template <typename R>
 struct Unit16T;
@@ -165,9 +259,9 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
   };
   Unit16 buf[8];
   auto load_tile = [&](size_t origin) {
-    const Unit16* src = reinterpret_cast<const Unit16*>(X + origin + colk);
+    const Unit16* src = reinterpret_cast<const Unit16*>(X + origin + colk) + row_t / C::kEpu;
 #pragma unroll
-    for (uint32_t jj = 0; jj < 8; ++jj) buf[jj] = src[(row_t + row_u[jj]) / C::kEpu];
+    for (uint32_t jj = 0; jj < 8; ++jj) buf[jj] = src[row_u[jj] / C::kEpu];
   };
 
   uint32_t tl = wg;
@@ -200,12 +294,18 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
       load_tile(origin_next);
     }
     const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
-    if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
-    __syncthreads();
-    if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    if constexpr (sizeof(R) == 4) {
+      pair2_phase_mfma<M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
+      __syncthreads();
+      pair2_phase_mfma<M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    } else {
+      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
+      __syncthreads();
+      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    }
     __syncthreads();
     // gather in address order and store
-    Unit16* dst = reinterpret_cast<Unit16*>(X + origin + colk);
+    Unit16* dst = reinterpret_cast<Unit16*>(X + origin + colk) + row_t / C::kEpu;
 #pragma unroll
     for (uint32_t jj = 0; jj < 8; ++jj) {
       const uint32_t base = (a0 + jj * C::kRowStep) * C::kRowStride;
@@ -217,7 +317,7 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
         const cx<R> v = tile[base + lk0];
         u = Unit16{v.re, v.im};
       }
-      dst[(row_t + row_u[jj]) / C::kEpu] = u;
+      dst[row_u[jj] / C::kEpu] = u;
     }
     if (next >= total) break;
     __syncthreads();  // the tile's LDS is rewritten next
