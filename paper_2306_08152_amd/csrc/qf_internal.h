@@ -64,6 +64,8 @@ struct Pass8Geom {
   uint32_t s[3];             // the same positions in ascending order
   uint32_t W, wlog;          // column groups per tile (a power of two <= 32) and its log2
   uint32_t col_tiles, tiles_per_start;
+  Pair2Geom tg[2];           // the two-gate pass's tiles for this gate (complex64, complex128)
+  int tg_ok[2];              // whether those tiles fit (n >= 3 + their width's log2)
 };
 Pass8Geom make_pass8_geom(int n, const int32_t loc[3]);
 hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B);
@@ -141,6 +143,9 @@ uint32_t pair2_wlog(int precision, int m);
 uint32_t env2_workgroups(int n, int m, int S);  // gather workgroups per start for a launch of S starts
 uint32_t env2_workgroups_cap(int n);            // the most of them for any m and S (workspace sizing)
 hipError_t launch_env2(hipStream_t st, int precision, const void* X, const Env2Args& a, KernelEvents ev = {});
+// One three-qubit gate's two-sided pass on the two-gate pass's tiles
+// (qf_pair.hip); g from make_pair2_geom with F = (l0, l1), S = (l1, l2).
+hipError_t launch_pass3(hipStream_t st, int precision, void* X, int S, const Pair2Geom& g, Operand A, Operand B);
 hipError_t launch_pass2(hipStream_t st, int precision, void* X, int S, const Pair2Geom& g, const void* ops,
                         KernelEvents ev = {});
 

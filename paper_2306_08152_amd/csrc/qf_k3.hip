@@ -46,6 +46,10 @@ Pass8Geom make_pass8_geom(int n, const int32_t loc[3]) {
   while ((1u << g.wlog) < g.W) ++g.wlog;
   g.col_tiles = groups >> g.wlog;
   g.tiles_per_start = groups * g.col_tiles;
+  // the two-gate pass's tiles, whose union is this gate's three qubits
+  const int32_t f[2] = {loc[0], loc[1]}, sg[2] = {loc[1], loc[2]};
+  for (int ti = 0; ti < 2; ++ti)
+    g.tg_ok[ti] = make_pair2_geom(n, f, sg, pair2_wlog(ti == 0 ? QF_C64 : QF_C128, 3), g.tg[ti]) ? 1 : 0;
   return g;
 }
 
@@ -264,6 +268,12 @@ static hipError_t launch_pass8_pipe(hipStream_t st, void* X, int S, const Pass8G
 }
 
 hipError_t launch_pass8(hipStream_t st, int precision, void* X, int S, const Pass8Geom& g, Operand A, Operand B) {
+  // Where the two-gate pass's tiles fit (n >= 9 for complex64, n >= 8 for
+  // complex128), the gate runs on them (k_pass3: address-order 16-byte
+  // loads and stores, the next tile's loads under the current one's
+  // products).
+  const int ti = precision == QF_C64 ? 0 : 1;
+  if (g.tg_ok[ti]) return launch_pass3(st, precision, X, S, g.tg[ti], A, B);
   // complex128 keeps k_pass8 also at W = 32: a pipelined form with vector
   // FP64 products (34 KiB of LDS, four workgroups per CU) was measured
   // slower, 83 against 54 us at n = 10, 8 starts.

@@ -224,14 +224,18 @@ struct Unit16T<double> {
   using type = double2;
 };
 
-// ops: per start the four 4x4 operands A_F, B_F, A_S, B_S in the builder
-// precision (64 entries, written by k_env2): x <- A_S A_F x B_F B_S.
-template <typename R, int M>
-__device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geom& g, uint32_t total,
-                                           const cx<R>* __restrict__ ops, uint32_t wg, uint32_t n_wg) {
+// The tile loop shared by the two-gate pass and the three-qubit pass: each
+// workgroup walks tiles wg, wg + n_wg, ... < total; a tile's 16-byte units
+// are loaded in address order (8 per thread) and scattered into the LDS
+// image, the next tile's loads go out, P::run applies the products on the
+// image, and the units are gathered and stored in address order.  P::prep(s)
+// runs before the barrier that publishes the image (the operands of start s
+// into LDS).
+template <typename R, int M, typename P>
+__device__ __forceinline__ void tile_loop(cx<R>* __restrict__ X, const Pair2Geom& g, uint32_t total, uint32_t wg,
+                                          uint32_t n_wg, cx<R>* tile, P& prod) {
   using C = Pair2Cfg<R, M>;
   using Unit16 = typename Unit16T<R>::type;
-  __shared__ cx<R> tile[C::kLds];
   const uint32_t t = threadIdx.x;
   const uint32_t N = g.N;
   // This thread's memory-order unit: the same column set in every row it
@@ -284,6 +288,7 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
         tile[base + lk0] = cx<R>{u.x, u.y};
       }
     }
+    prod.prep(s);
     __syncthreads();
     // next tile's loads go out now and land under this tile's products
     const uint32_t next = tl + n_wg;
@@ -293,16 +298,7 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
       tile_origin(next, s_next, origin_next);
       load_tile(origin_next);
     }
-    const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
-    if constexpr (sizeof(R) == 4) {
-      pair2_phase_mfma<M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
-      __syncthreads();
-      pair2_phase_mfma<M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
-    } else {
-      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
-      __syncthreads();
-      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
-    }
+    prod.run(s);
     __syncthreads();
     // gather in address order and store
     Unit16* dst = reinterpret_cast<Unit16*>(X + origin + colk) + row_t / C::kEpu;
@@ -327,10 +323,37 @@ __device__ __forceinline__ void pass2_body(cx<R>* __restrict__ X, const Pair2Geo
   }
 }
 
+// Two-gate products.  ops: per start the four 4x4 operands A_F, B_F, A_S,
+// B_S in the builder precision (64 entries, written by k_env2):
+// x <- A_S A_F x B_F B_S.
+template <typename R, int M>
+struct Pair2Products {
+  cx<R>* tile;
+  const Pair2Geom& g;
+  const cx<R>* __restrict__ ops;
+  __device__ __forceinline__ void prep(uint32_t) {}
+  __device__ __forceinline__ void run(uint32_t s) {
+    using C = Pair2Cfg<R, M>;
+    const uint32_t t = threadIdx.x;
+    const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
+    if constexpr (sizeof(R) == 4) {
+      pair2_phase_mfma<M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
+      __syncthreads();
+      pair2_phase_mfma<M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    } else {
+      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
+      __syncthreads();
+      if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
+    }
+  }
+};
+
 template <typename R, int M>
 __global__ __launch_bounds__(256, 4) void k_pass2(cx<R>* __restrict__ X, Pair2Geom g, uint32_t total,
                                                   const cx<R>* __restrict__ ops) {
-  pass2_body<R, M>(X, g, total, ops, blockIdx.x, gridDim.x);
+  __shared__ cx<R> tile[Pair2Cfg<R, M>::kLds];
+  Pair2Products<R, M> prod{tile, g, ops};
+  tile_loop<R, M>(X, g, total, blockIdx.x, gridDim.x, tile, prod);
 }
 
 // Tiles per workgroup of the two-gate pass (each workgroup walks this many
@@ -356,6 +379,160 @@ hipError_t launch_pass2(hipStream_t st, int precision, void* X, int S, const Pai
   if (precision == QF_C64)
     return g.m == 4 ? launch_pass2_t<float, 4>(st, X, S, g, ops, ev) : launch_pass2_t<float, 3>(st, X, S, g, ops, ev);
   return g.m == 4 ? launch_pass2_t<double, 4>(st, X, S, g, ops, ev) : launch_pass2_t<double, 3>(st, X, S, g, ops, ev);
+}
+
+// ------------------------------------------------------------------ k_pass3
+//
+// One three-qubit gate's two-sided update X <- (A (x) I) X (B (x) I) on the
+// same tiles (the union is the gate's three qubits: 8 row variants x 8 column
+// variants x W rest columns, W = 64 for complex64 and 32 for complex128, 32
+// KiB of builder data).  The operands, rounded to the builder precision and
+// permuted to variant order (entry (a, b) = M[local(a)][local(b)]), go to
+// LDS once per tile.  The left product takes the tile's columns (v, w) as
+// vectors over the row variant, the right product its rows (a, w) as vectors
+// over the column variant.
+
+// Entry (r, k) of the real 16 x 16 form [[Mr, -Mi], [Mi, Mr]] of an 8 x 8
+// complex matrix M (rows and columns 0..7 real parts, 8..15 imaginary), with
+// M(a, b) = src[8 a + b], or src[8 b + a] when T.
+template <bool T>
+__device__ __forceinline__ float real16_of(const cf* src, uint32_t r, uint32_t k) {
+  const uint32_t a = r & 7u, b = k & 7u;
+  const cf m = src[T ? 8u * b + a : 8u * a + b];
+  if (r < 8u) return k < 8u ? m.re : -m.im;
+  return k < 8u ? m.im : m.re;
+}
+
+// complex64: y = M x for the tile's 512 vectors on v_mfma_f32_16x16x4f32,
+// the real contraction [Re y; Im y] = M16 [Re x; Im x] (A operand 16 x 4:
+// lane l holds row l % 16, column l / 16; B operand 4 x 16: lane l holds row
+// l / 16, column l % 16; result: lane l holds rows 4 (l / 16) .. + 3 of
+// column l % 16), four k-steps per 16 vectors.  Wavefront v takes vectors
+// 128 v .. 128 v + 127; a vector's entries are read and written by its own
+// wavefront only, so the update in place needs no barrier.  LEFT: M = A on
+// the columns; otherwise M = B^T on the rows.
+template <bool LEFT>
+__device__ __forceinline__ void pass3_products_mfma(cf* tile, const cf* M, uint32_t t) {
+  using C = Pair2Cfg<float, 3>;
+  constexpr uint32_t W = C::kW, RS = C::kRowStride;
+  static_assert(W == 64, "512 vectors per side");
+  const uint32_t l = t & 63u, wv = t >> 6, g = l >> 4, cl = l & 15u;
+  float am[4];
+#pragma unroll
+  for (uint32_t ks = 0; ks < 4; ++ks) am[ks] = real16_of<!LEFT>(M, cl, 4u * ks + g);
+  float* tf = reinterpret_cast<float*>(tile);
+#pragma unroll 2
+  for (uint32_t q = 0; q < 8; ++q) {
+    const uint32_t vec = (wv * 8u + q) * 16u + cl;  // 0..511
+    const uint32_t hi = vec >> 6, w = vec & (W - 1u);  // LEFT: column variant; else row variant
+    auto at = [&](uint32_t c) -> uint32_t {
+      return LEFT ? c * RS + hi * (W + 1u) + w : hi * RS + c * (W + 1u) + w;
+    };
+    // k-row 4 ks + g of the vector: Re x_g, Re x_{4+g}, Im x_g, Im x_{4+g}
+    const cf x0 = tile[at(g)], x1 = tile[at(4u + g)];
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[0], x0.re, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[1], x1.re, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[2], x0.im, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[3], x1.im, acc, 0, 0, 0);
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) {
+      const uint32_t r = 4u * g + v;  // < 8: Re y_r, else Im y_{r-8}
+      tf[2u * at(r & 7u) + (r >> 3)] = acc[v];
+    }
+  }
+}
+
+// complex128: vector FP64 products, one vector per thread (256 per side).
+template <bool LEFT>
+__device__ __forceinline__ void pass3_products_vec(cd* tile, const cd* M, uint32_t t) {
+  using C = Pair2Cfg<double, 3>;
+  constexpr uint32_t W = C::kW, RS = C::kRowStride;
+  static_assert(W == 32, "256 vectors per side");
+  const uint32_t hi = t >> 5, w = t & (W - 1u);
+  auto at = [&](uint32_t c) -> uint32_t { return LEFT ? c * RS + hi * (W + 1u) + w : hi * RS + c * (W + 1u) + w; };
+  cd x[8];
+#pragma unroll
+  for (uint32_t c = 0; c < 8; ++c) x[c] = tile[at(c)];
+#pragma unroll
+  for (uint32_t i = 0; i < 8; ++i) {
+    cd acc = mk(0.0, 0.0);
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) cmac(acc, LEFT ? M[8 * i + k] : M[8 * k + i], x[k]);
+    tile[at(i)] = acc;
+  }
+}
+
+template <typename R, bool HA, bool HB>
+struct Pass3Products {
+  cx<R>* tile;
+  cx<R>* As;
+  cx<R>* Bs;
+  const Pair2Geom& g;
+  Operand A, B;
+  uint32_t s_have;
+  // operands of start s in variant order, once per start
+  __device__ __forceinline__ void prep(uint32_t s) {
+    if (s == s_have) return;
+    s_have = s;
+    const uint32_t t = threadIdx.x;
+    if (t < 128) {
+      const bool left = t < 64;
+      const Operand& o = left ? A : B;
+      if ((left && HA) || (!left && HB)) {
+        const uint32_t e = t & 63u;
+        const uint32_t r = k3_local(g, e >> 3), c = k3_local(g, e & 7u);
+        const cd* src = reinterpret_cast<const cd*>(o.ptr) + (int64_t)s * o.stride;
+        const cd v = o.dagger ? conj(src[8 * c + r]) : src[8 * r + c];
+        (left ? As : Bs)[e] = cx<R>{(R)v.re, (R)v.im};
+      }
+    }
+  }
+  __device__ __forceinline__ void run(uint32_t) {
+    const uint32_t t = threadIdx.x;
+    if constexpr (sizeof(R) == 4) {
+      if (HA) pass3_products_mfma<true>(tile, As, t);
+      if (HA && HB) __syncthreads();
+      if (HB) pass3_products_mfma<false>(tile, Bs, t);
+    } else {
+      if (HA) pass3_products_vec<true>(tile, As, t);
+      if (HA && HB) __syncthreads();
+      if (HB) pass3_products_vec<false>(tile, Bs, t);
+    }
+  }
+};
+
+template <typename R, bool HA, bool HB>
+__global__ __launch_bounds__(256, 4) void k_pass3(cx<R>* __restrict__ X, Pair2Geom g, uint32_t total, Operand A,
+                                                  Operand B) {
+  __shared__ cx<R> tile[Pair2Cfg<R, 3>::kLds];
+  __shared__ cx<R> As[64], Bs[64];
+  Pass3Products<R, HA, HB> prod{tile, As, Bs, g, A, B, 0xffffffffu};
+  tile_loop<R, 3>(X, g, total, blockIdx.x, gridDim.x, tile, prod);
+}
+
+// Tiles per workgroup of the three-qubit pass (n = 10, 8 starts, two-sided:
+// complex64 33.2 / 27.6 / 30.1 us and complex128 54.6 / 48.4 / 45.2 us for
+// 1 / 2 / 4 tiles per workgroup).
+template <typename R>
+constexpr uint32_t kPass3TilesPerWG = sizeof(R) == 4 ? 2u : 4u;
+
+template <typename R>
+static hipError_t launch_pass3_t(hipStream_t st, void* X, int S, const Pair2Geom& g, Operand A, Operand B) {
+  if (g.wlog != Pair2Cfg<R, 3>::kWlog || g.m != 3u) return hipErrorInvalidValue;
+  const uint32_t total = (uint32_t)S * g.tiles_per_start;
+  const uint32_t tpw = g.tiles_per_wg ? g.tiles_per_wg : kPass3TilesPerWG<R>;
+  const dim3 grid((total + tpw - 1) / tpw), block(256);
+  cx<R>* x = reinterpret_cast<cx<R>*>(X);
+  if (A.ptr && B.ptr) return launch_k(k_pass3<R, true, true>, grid, block, 0u, st, KernelEvents{}, x, g, total, A, B);
+  if (A.ptr) return launch_k(k_pass3<R, true, false>, grid, block, 0u, st, KernelEvents{}, x, g, total, A, B);
+  if (B.ptr) return launch_k(k_pass3<R, false, true>, grid, block, 0u, st, KernelEvents{}, x, g, total, A, B);
+  return hipSuccess;
+}
+
+hipError_t launch_pass3(hipStream_t st, int precision, void* X, int S, const Pair2Geom& g, Operand A, Operand B) {
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0) return hipErrorInvalidValue;
+  return precision == QF_C64 ? launch_pass3_t<float>(st, X, S, g, A, B) : launch_pass3_t<double>(st, X, S, g, A, B);
 }
 
 // ------------------------------------------------------------------ k_env2

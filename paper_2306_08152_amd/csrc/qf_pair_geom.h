@@ -82,6 +82,14 @@ __host__ __device__ __forceinline__ uint32_t var_other(uint32_t o, const uint32_
   return v;
 }
 
+// The tiles also serve one three-qubit gate on locations (l0, l1, l2), given
+// as F = (l0, l1), S = (l1, l2): the union is the gate's three qubits, and
+// variant v is the gate-local index (first location most significant)
+// returned here.
+__host__ __device__ __forceinline__ uint32_t k3_local(const Pair2Geom& g, uint32_t v) {
+  return (((v >> g.f_idx[0]) & 1u) << 2) | (((v >> g.f_idx[1]) & 1u) << 1) | ((v >> g.s_idx[1]) & 1u);
+}
+
 // Host: geometry for gates F (locs f[0], f[1]) then S (s[0], s[1]) on n
 // qubits with tile width 2^wlog.  Returns false when the pair does not form
 // a 3- or 4-qubit union or the builder is too small for one tile.

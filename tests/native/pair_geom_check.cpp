@@ -5,8 +5,10 @@
 // read and write every builder entry exactly once, each tile's LDS image
 // holds entry (row variant a, column variant v, rest offset w) of that tile,
 // and each gate's product phase covers every LDS entry of the tile exactly
-// once with 4x4 blocks that vary only in that gate's bits.  Prints "ok" and
-// the number of geometries, or the first failure.
+// once with 4x4 blocks that vary only in that gate's bits; and, for a
+// three-qubit gate run on the same tiles (k_pass3), that each union variant
+// addresses the bits of its gate-local index.  Prints "ok" and the number of
+// geometries, or the first failure.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -103,9 +105,41 @@ static int check(int n, const int32_t* f, const int32_t* sg, bool c64) {
   return 0;
 }
 
+// Three-qubit gate on locations (l0, l1, l2) as the pair F = (l0, l1),
+// S = (l1, l2): variant v of the union must address the bits of gate-local
+// index k3_local(v) (first location most significant).
+static int check3(int n, int l0, int l1, int l2) {
+  const int32_t f[2] = {l0, l1}, sg[2] = {l1, l2};
+  for (int c64 = 0; c64 < 2; ++c64) {
+    Pair2Geom g;
+    const uint32_t wlog = shape(c64 != 0, 3).wlog;
+    if (!make_pair2_geom(n, f, sg, wlog, g)) {
+      if ((uint32_t)n >= 3 + wlog) return fail("k3 geom", n, f, sg);
+      continue;
+    }
+    if (g.m != 3) return fail("k3 union", n, f, sg);
+    uint32_t seen = 0;
+    for (uint32_t v = 0; v < 8; ++v) {
+      const uint32_t l = k3_local(g, v);
+      const uint32_t bits = (((l >> 2) & 1u) << (n - 1 - l0)) | (((l >> 1) & 1u) << (n - 1 - l1)) | ((l & 1u) << (n - 1 - l2));
+      if (l > 7 || (seen & (1u << l)) || dep_union(g, v) != bits) return fail("k3 local index", n, f, sg);
+      seen |= 1u << l;
+    }
+  }
+  return 0;
+}
+
 int main(int argc, char** argv) {
   const int nmax = argc > 1 ? std::atoi(argv[1]) : 11;
   int count = 0;
+  for (int n = 3; n <= nmax; ++n)
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b)
+        for (int c = 0; c < n; ++c) {
+          if (a == b || b == c || a == c) continue;
+          if (check3(n, a, b, c)) return 1;
+          ++count;
+        }
   for (int n = 4; n <= nmax; ++n)
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b)

@@ -106,10 +106,29 @@ def test_instantiate3_n10_one_sweep_both_precisions(qf):
         assert abs(O.cost(V, host(r64.all_gates)[s], pr.locs, n) - r64.costs[s]) <= 1e-12
 
 
+@pytest.mark.parametrize("n,layers,S,sweeps", [(8, 3, 2, 2), (9, 3, 2, 1)])
+def test_instantiate3_c128_tiled_pass_follows_oracle(qf, n, layers, S, sweeps):
+    """n >= 8: complex128 passes run on the two-gate pass's tiles (8 row
+    variants x 8 column variants x 32 rest columns, address-order loads and
+    stores); n = 8 is the smallest builder they fit.  Gates within 1e-9 and
+    costs within 1e-10 of the oracle."""
+    pr = I.k3_problem(40, n, layers, S)
+    rng = np.random.default_rng(3600 + n)
+    V = I.haar_unitary(rng, 1 << n)
+    res = qf.instantiate3(dev(V), pr.locs, dev(pr.init_gates), tol=1e-300, max_iter=sweeps, history_rows=sweeps + 1,
+                          **NOPLATEAU)
+    ref = O.instantiate(V, pr.init_gates, pr.locs, n, tol=1e-300, opt=O.Options(max_iter=sweeps, **NOPLATEAU))
+    assert res.sweeps == ref.sweeps == sweeps
+    assert np.abs(host(res.all_gates) - ref.all_gates).max() <= 1e-9
+    assert np.abs(res.costs - ref.costs).max() <= 1e-10
+    assert np.abs(res.history - ref.history[: res.history.shape[0]]).max() <= 1e-10
+
+
 @pytest.mark.parametrize("n", [8, 9])
 def test_instantiate3_c64_matrix_core_pass_follows_oracle(qf, n):
     """n >= 8: the complex64 pass runs its 8 x 8 products on the matrix
-    cores (32-group tiles).  Three sweeps from three Haar starts: the
+    cores (n = 8: 32-group tiles of k_pass8_pipe; n >= 9: the two-gate
+    pass's 64-column tiles).  Three sweeps from three Haar starts: the
     complex64 sweep costs stay within 1e-5 of the oracle's, the gates within
     1e-4, and the FP64 final costs equal the oracle cost of the returned
     gates."""
@@ -130,9 +149,9 @@ def test_instantiate3_c64_matrix_core_pass_follows_oracle(qf, n):
 
 def test_instantiate3_n10_eight_starts_pipelined_walk(qf):
     """n = 10, 8 starts: the launch configuration the three-qubit timing
-    uses.  The complex64 pass then has 4096 tiles on a grid of 2048
-    workgroups, so every workgroup walks two tiles, four starts apart, and
-    prefetches the second while it finishes the first.  One sweep: complex64
+    uses.  The pass then has 1024 (complex64) or 2048 (complex128) tiles per
+    start set on half as many workgroups, so every workgroup walks two
+    tiles and prefetches the second while it finishes the first.  One sweep: complex64
     costs within 1e-5 of the oracle's, gates within 1e-4, FP64 final costs
     equal to the oracle cost of the returned gates; complex128 gates within
     1e-9."""
