@@ -193,6 +193,10 @@ typedef struct {
   int32_t pass2_launches; /* out (timing): the two-gate passes among
                              pass_launches */
   double pass2_ms;        /* out (timing): their summed durations */
+  int32_t batch_slots;    /* out (qf_instantiate_batch): instantiations per
+                             workgroup of the batched launch (8 or 16) */
+  int32_t batch_wg_per_cu; /* out (qf_instantiate_batch): its workgroups per
+                              compute unit */
 } qf_stats;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -381,6 +385,19 @@ int qf_optimize_gate3(qf_ctx* ctx, int count, const void* env, const void* u_old
  * Returns when all outputs are final. */
 size_t qf_batch_workspace_size(int n_blocks, const int32_t* block_n, const int32_t* gate_offsets, int n_starts,
                                const qf_options* opt);
+
+/* Shape of the batched launch for `n_starts` starts per block: `slots`
+ * instantiations (8 or 16, at least n_starts) per workgroup, one per 16
+ * lanes, and `wg_per_cu` workgroups per compute unit (1 .. the kernel's
+ * occupancy limit).  slots = 0 forgets the choice: the next
+ * qf_instantiate_batch with these starts times every candidate (8 and 16
+ * slots, 1 .. min(4, occupancy limit) workgroups per CU) for up to three
+ * sweeps on its own first 2048 blocks (largest first) and keeps the
+ * fastest; it restores out_gates from init_gates afterwards, and takes 16
+ * slots at the occupancy limit untimed when they are the same buffer or
+ * n_starts > 8.  The shape changes no result: every choice gives bitwise the
+ * same outputs.  Returns QF_EINVAL for other values. */
+int qf_set_batch_config(qf_ctx* ctx, int n_starts, int slots, int wg_per_cu);
 int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, const int32_t* gate_offsets,
                          const int32_t* locations, const void* targets, const void* init_gates, int n_starts,
                          double tol, const qf_options* opt, void* workspace, size_t ws_bytes, void* out_gates,

@@ -20,7 +20,7 @@ EXPORTED = [
     "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
     "qf_gradient_workspace_size", "qf_gradient", "qf_su4_gates", "qf_su4_vjp", "qf_lbfgs_options_default",
     "qf_lbfgs_workspace_size", "qf_lbfgs", "qf_set_pass_tile", "qf_delete_gates_workspace_size", "qf_delete_gates",
-    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3", "qf_instantiate_noalloc",
+    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3", "qf_instantiate_noalloc", "qf_set_batch_config",
 ]
 QF_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -66,6 +66,8 @@ class QfStats(ctypes.Structure):
         ("pass_tcols", ctypes.c_int32),
         ("pass2_launches", ctypes.c_int32),
         ("pass2_ms", ctypes.c_double),
+        ("batch_slots", ctypes.c_int32),
+        ("batch_wg_per_cu", ctypes.c_int32),
     ]
 
 
@@ -146,6 +148,7 @@ _SIGS = {
     "qf_su4_vjp": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "qf_lbfgs_options_default": (None, [ctypes.POINTER(QfLbfgsOptions)]),
     "qf_set_pass_tile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "qf_set_batch_config": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "qf_delete_gates_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(QfOptions)]),
     "qf_delete_gates": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, _VP, ctypes.c_int,

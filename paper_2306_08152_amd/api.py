@@ -84,6 +84,14 @@ def set_pass_tile(device, precision: int, n: int, gate_class: int, tile: int) ->
     nat.check(nat.load().qf_set_pass_tile(ctx, precision, n, gate_class, tile), ctx)
 
 
+def set_batch_config(device, n_starts: int, slots: int, wg_per_cu: int = 1) -> None:
+    """Fix the batched launch's shape for n_starts starts per block: slots
+    (8 or 16) instantiations per workgroup, wg_per_cu workgroups per CU;
+    slots = 0 = tune again (qf_set_batch_config)."""
+    ctx = _ctx(device)
+    nat.check(nat.load().qf_set_batch_config(ctx, n_starts, slots, wg_per_cu), ctx)
+
+
 def _apply_kw(opt: nat.QfOptions, kw: dict):
     """Set option fields; gate_kinds (sequence of qf_gate_kind) becomes a
     ctypes array that the caller keeps alive for the call."""
@@ -313,6 +321,8 @@ class BatchResult:
     sweeps: np.ndarray           # (n_blocks,)
     elapsed_ms: float
     kernel_ms: float
+    slots: int = 0                # instantiations per workgroup of the launch
+    wg_per_cu: int = 0            # its workgroups per compute unit
 
     def block_gates(self, b: int) -> torch.Tensor:
         """(S, p_b, 4, 4) view of block b's gates."""
@@ -383,7 +393,7 @@ def instantiate_batch(block_n, gate_offsets, locations, targets: torch.Tensor, i
                                   status.ctypes.data_as(i32p), sweeps.ctypes.data_as(i32p), ctypes.byref(st))
     nat.check(rc, ctx)
     return BatchResult(out_gates, go, n_starts, costs[:nb], best[:nb], status[:nb], sweeps[:nb], st.elapsed_ms,
-                       st.sweep_ms)
+                       st.sweep_ms, st.batch_slots, st.batch_wg_per_cu)
 
 
 # ------------------------------------------------------------------ gradient

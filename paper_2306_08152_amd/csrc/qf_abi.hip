@@ -40,6 +40,9 @@ struct qf_ctx {
   int tuned_tcols[2][2][17] = {};
   // Tuned tiles per workgroup of the two-gate pass per (precision, n); 0 = not tuned yet.
   int tuned_pass2[2][17] = {};
+  // Batched launch per number of starts: hexes per workgroup and workgroups
+  // per CU; 0 = not tuned yet.
+  int batch_cfg[17][2] = {};
   double* identity = nullptr;   // one 4x4 c128 identity (tuning operand)
   void* static_ws = nullptr;    // this device's address of `scratch` (below); null if unresolved
   std::string last_error;
@@ -1020,7 +1023,7 @@ struct BatchLayout {
   size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, kinds = 0, hist = 0, scratch = 0, cost = 0,
          best = 0, status = 0, sweeps = 0, queue = 0;
   size_t total = 0;
-  int ring = 2, groups = 0;
+  int ring = 2;
 };
 
 BatchLayout make_batch_layout(int n_blocks, int total_gates, int S, const qf_options& o) {
@@ -1040,8 +1043,7 @@ BatchLayout make_batch_layout(int n_blocks, int total_gates, int S, const qf_opt
   L.kinds = take((size_t)total_gates * 4);
   L.ring = std::max(2, o.long_diff_count + 1);
   L.hist = take(nb * S * L.ring * 8);
-  L.groups = batch_groups(n_blocks, S);
-  L.scratch = take(batch_scratch_entries(std::min(L.groups, kBatchMaxGrid)) * 16);
+  L.scratch = take(batch_scratch_entries(n_blocks, S) * 16);
   L.cost = take(nb * S * 8);
   L.best = take(nb * 4);
   L.status = take(nb * 4);
@@ -1848,6 +1850,75 @@ size_t qf_batch_workspace_size(int n_blocks, const int32_t* block_n, const int32
   return make_batch_layout(n_blocks, gate_offsets[n_blocks], n_starts, o).total;
 }
 
+namespace {
+
+// Tuner of the batched launch.  Candidates: 8 or 16 hexes per workgroup (at
+// least n_starts) and 1 .. the kernel's occupancy limit (at most 4)
+// workgroups per CU.  Each runs the first blocks of the processing order (up
+// to 2048) for min(max_iter, 3) sweeps on the caller's own data, timed with
+// events; the fastest wins.  The trials write the caller's output gates,
+// which are then restored from the initial gates; with out_gates ==
+// init_gates nothing can be restored, so the default (16 hexes, the
+// occupancy limit) is taken untimed.  Every candidate gives bitwise the same
+// results.
+int tune_batch(qf_ctx* ctx, const BatchArgs& a, int n_blocks, int S, void* out_gates, const void* init_gates,
+               size_t gate_bytes) {
+  hipStream_t st = ctx->stream;
+  int best_slots = 16, best_per = std::min(4, batch_wg_per_cu_max(16));
+  if (S > 8 || out_gates == init_gates) {
+    ctx->batch_cfg[S][0] = best_slots;
+    ctx->batch_cfg[S][1] = best_per;
+    return QF_OK;
+  }
+  BatchArgs t = a;
+  t.n_blocks = std::min(n_blocks, 2048);
+  t.opt.max_iter = std::max(1, std::min(a.opt.max_iter, 3));
+  float best_ms = 0.f;
+  bool have = false;
+  for (int slots : {16, 8}) {
+    const int per_max = std::min(4, batch_wg_per_cu_max(slots));
+    for (int per = 1; per <= per_max; ++per) {
+      const int grid = batch_grid(slots, per, batch_groups(t.n_blocks, S, slots));
+      QF_HIP(ctx, launch_fill_i32(st, t.queue, 0, 1));
+      QF_HIP(ctx, hipEventRecord(ctx->tune[0], st));
+      QF_HIP(ctx, launch_batch(st, slots, grid, t));
+      QF_HIP(ctx, hipEventRecord(ctx->tune[1], st));
+      QF_HIP(ctx, hipEventSynchronize(ctx->tune[1]));
+      float ms = 0.f;
+      QF_HIP(ctx, hipEventElapsedTime(&ms, ctx->tune[0], ctx->tune[1]));
+      if (!have || ms < best_ms) {
+        have = true;
+        best_ms = ms;
+        best_slots = slots;
+        best_per = per;
+      }
+    }
+  }
+  QF_HIP(ctx, hipMemcpyAsync(out_gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
+  ctx->batch_cfg[S][0] = best_slots;
+  ctx->batch_cfg[S][1] = best_per;
+  return QF_OK;
+}
+
+}  // namespace
+
+int qf_set_batch_config(qf_ctx* ctx, int n_starts, int slots, int wg_per_cu) {
+  if (!ctx) return QF_EINVAL;
+  if (n_starts < 1 || n_starts > 16) return fail(ctx, QF_EINVAL, "n_starts must be in 1..16");
+  if (slots == 0) {
+    ctx->batch_cfg[n_starts][0] = ctx->batch_cfg[n_starts][1] = 0;
+    return QF_OK;
+  }
+  if ((slots != 8 && slots != 16) || slots < n_starts)
+    return fail(ctx, QF_EINVAL, "slots must be 8 or 16 and at least n_starts");
+  DeviceGuard dg(ctx->device);
+  if (wg_per_cu < 1 || wg_per_cu > batch_wg_per_cu_max(slots))
+    return fail(ctx, QF_EINVAL, "wg_per_cu must be in 1..%d for %d slots", batch_wg_per_cu_max(slots), slots);
+  ctx->batch_cfg[n_starts][0] = slots;
+  ctx->batch_cfg[n_starts][1] = wg_per_cu;
+  return QF_OK;
+}
+
 int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, const int32_t* gate_offsets,
                          const int32_t* locations, const void* targets, const void* init_gates, int n_starts,
                          double tol, const qf_options* opt, void* workspace, size_t ws_bytes, void* out_gates,
@@ -1899,7 +1970,6 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   if (out_gates != init_gates)
     QF_HIP(ctx, hipMemcpyAsync(out_gates, init_gates, gate_bytes, hipMemcpyDeviceToDevice, st));
   int32_t* queue = reinterpret_cast<int32_t*>(ws + L.queue);
-  QF_HIP(ctx, launch_fill_i32(st, queue, 0, 1));
 
   BatchArgs a{};
   a.n_blocks = n_blocks;
@@ -1922,8 +1992,14 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   a.out_sweeps = reinterpret_cast<int32_t*>(ws + L.sweeps);
   a.queue = queue;
   a.kinds = o.gate_kinds ? reinterpret_cast<const int32_t*>(ws + L.kinds) : nullptr;
-  // grid <= min(groups, kBatchMaxGrid), the count the scratch was sized for
-  const int grid = batch_grid(o.precision, L.groups);
+  // Hexes per workgroup and workgroups per CU: tuned once per number of
+  // starts on the caller's own first blocks, unless set (qf_set_batch_config).
+  if (!ctx->batch_cfg[n_starts][0]) {
+    if ((rc = tune_batch(ctx, a, n_blocks, n_starts, out_gates, init_gates, gate_bytes))) return rc;
+  }
+  const int slots = ctx->batch_cfg[n_starts][0];
+  const int grid = batch_grid(slots, ctx->batch_cfg[n_starts][1], batch_groups(n_blocks, n_starts, slots));
+  QF_HIP(ctx, launch_fill_i32(st, queue, 0, 1));
   const bool timed = stats && stats->timing;
   hipEvent_t ev[2] = {nullptr, nullptr};
   struct EvFree {
@@ -1938,7 +2014,7 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
     QF_HIP(ctx, hipEventCreate(&ev[1]));
     QF_HIP(ctx, hipEventRecord(ev[0], st));
   }
-  QF_HIP(ctx, launch_batch(st, o.precision, grid, a));
+  QF_HIP(ctx, launch_batch(st, slots, grid, a));
   if (timed) QF_HIP(ctx, hipEventRecord(ev[1], st));
 
   std::vector<int32_t> best(n_blocks), status(n_blocks), sweeps(n_blocks);
@@ -1971,6 +2047,8 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
     if (timed) QF_HIP(ctx, hipEventElapsedTime(&kms, ev[0], ev[1]));
     stats->sweep_ms = kms;
     stats->pass_tcols = 0;
+    stats->batch_slots = slots;
+    stats->batch_wg_per_cu = ctx->batch_cfg[n_starts][1];
     stats->elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return QF_OK;

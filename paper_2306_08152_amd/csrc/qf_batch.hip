@@ -16,15 +16,15 @@
 // the exit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qf_device.h"
 #include "qf_internal.h"
 #include "qf_termination.h"
 
 namespace qf {
 
-constexpr int kBSlots = 16;                    // hexes (instantiations) per workgroup
 constexpr int kBLanes = 16;                    // lanes per hex
-constexpr int kBThreads = kBSlots * kBLanes;   // four wavefronts
 constexpr int kBNmax = 16;                     // largest builder side (n <= 4)
 
 // Left product by a 4x4 gate (A) and right product (B) on one hex's N x N
@@ -161,20 +161,27 @@ __device__ inline double hex_cost(const cx<Q>* X, uint32_t N, int c) {
 // saves nothing there and would need FP64 re-evaluations of the cost below
 // recheck_below (measured: 2.18 s against 1.91 s for the 4096-block
 // workload); QF_C64 requests run this kernel too.
-__global__ __launch_bounds__(kBThreads) void k_batch(BatchDev d) {
+//
+// SLOTS hexes (instantiations) per workgroup: 16 (four wavefronts) or 8 (two);
+// the runtime's tuner picks it, and the workgroups per CU, per number of
+// starts.  Every hex computes the same sums in the same order whatever the
+// choice (only the idle steps of a workgroup's shorter blocks differ), so
+// the results are bitwise independent of it.
+template <int SLOTS>
+__global__ __launch_bounds__(SLOTS* kBLanes) void k_batch(BatchDev d) {
   using R = double;
-  __shared__ __align__(16) cx<R> Xs[kBSlots][kBNmax * kBNmax];
-  __shared__ cd Us[kBSlots][16];   // u_old of the gate being updated
-  __shared__ cd PUs[kBSlots][16];  // its partial trace, then u_new
-  __shared__ int flags_sh[kBSlots];
-  __shared__ int p_sh[kBSlots];
+  __shared__ __align__(16) cx<R> Xs[SLOTS][kBNmax * kBNmax];
+  __shared__ cd Us[SLOTS][16];   // u_old of the gate being updated
+  __shared__ cd PUs[SLOTS][16];  // its partial trace, then u_new
+  __shared__ int flags_sh[SLOTS];
+  __shared__ int p_sh[SLOTS];
   __shared__ int grp_sh;
   const int t = threadIdx.x, h = t / kBLanes, i = t % kBLanes;
   const int r = hex_row(i), c = i & 3;
   const qf_options& o = d.opt;
   cx<R>* X = Xs[h];
   // Fresh FP64 builder of each hex for the final costs, in global scratch.
-  cd* Y = d.scratch + ((size_t)blockIdx.x * kBSlots + h) * (kBNmax * kBNmax);
+  cd* Y = d.scratch + ((size_t)blockIdx.x * SLOTS + h) * (kBNmax * kBNmax);
   // Largest per-hex value over the workgroup (v uniform within each hex).
   auto wg_max = [&](int v) -> int {
     __syncthreads();
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(kBThreads) void k_batch(BatchDev d) {
     __syncthreads();
     int m = p_sh[0];
 #pragma unroll
-    for (int k = 1; k < kBSlots; ++k) m = max(m, p_sh[k]);
+    for (int k = 1; k < SLOTS; ++k) m = max(m, p_sh[k]);
     return m;
   };
 
@@ -360,32 +367,51 @@ __global__ __launch_bounds__(kBThreads) void k_batch(BatchDev d) {
   }
 }
 
-size_t batch_scratch_entries(int grid) { return (size_t)grid * kBSlots * kBNmax * kBNmax; }
-
-int batch_groups(int n_blocks, int S) {
-  const int B = kBSlots / S;
+int batch_groups(int n_blocks, int S, int slots) {
+  const int B = slots / S;
   return (n_blocks + B - 1) / B;
 }
 
-int batch_grid(int precision, int n_groups) {
-  int dev = 0, cus = 256, per = 1;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)precision;  // one kernel for both precisions (complex128 builders)
-  const void* fn = reinterpret_cast<const void*>(&k_batch);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBThreads, 0) != hipSuccess || per < 1) per = 1;
-  int g = cus * per;
-  if (g > kBatchMaxGrid) g = kBatchMaxGrid;
-  return g < n_groups ? g : n_groups;
+int batch_max_grid(int slots) { return kBatchMaxHexes / slots; }
+
+size_t batch_scratch_entries(int n_blocks, int S) {
+  size_t hexes = 0;
+  for (int slots : {8, 16})
+    if (slots >= S)
+      hexes = std::max(hexes, (size_t)std::min(batch_groups(n_blocks, S, slots), batch_max_grid(slots)) * slots);
+  return hexes * kBNmax * kBNmax;
 }
 
-hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs& a) {
+template <int SLOTS>
+static const void* batch_fn() {
+  return reinterpret_cast<const void*>(&k_batch<SLOTS>);
+}
+
+int batch_wg_per_cu_max(int slots) {
+  int per = 1;
+  const void* fn = slots == 8 ? batch_fn<8>() : batch_fn<16>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, slots * kBLanes, 0) != hipSuccess || per < 1) per = 1;
+  return per;
+}
+
+int batch_grid(int slots, int wg_per_cu, int n_groups) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int g = cus * std::max(1, wg_per_cu);
+  g = std::min(g, batch_max_grid(slots));
+  return std::min(g, n_groups);
+}
+
+hipError_t launch_batch(hipStream_t st, int slots, int grid, const BatchArgs& a) {
+  if (slots != 8 && slots != 16) return hipErrorInvalidValue;
+  if (a.S < 1 || a.S > slots) return hipErrorInvalidValue;
   BatchDev d;
   d.n_blocks = a.n_blocks;
   d.S = a.S;
-  d.B = kBSlots / a.S;
-  d.n_groups = batch_groups(a.n_blocks, a.S);
-  if (grid < 1 || grid > kBatchMaxGrid || grid > d.n_groups) return hipErrorInvalidValue;
+  d.B = slots / a.S;
+  d.n_groups = batch_groups(a.n_blocks, a.S, slots);
+  if (grid < 1 || grid > batch_max_grid(slots) || grid > d.n_groups) return hipErrorInvalidValue;
   d.order = a.order;
   d.blk_n = a.blk_n;
   d.gate_off = a.gate_off;
@@ -404,8 +430,10 @@ hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs
   d.out_sweeps = a.out_sweeps;
   d.queue = a.queue;
   d.kinds = a.kinds;
-  (void)precision;
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBThreads), 0, st, d);
+  if (slots == 8)
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(8 * kBLanes), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(16 * kBLanes), 0, st, d);
   return hipGetLastError();
 }
 

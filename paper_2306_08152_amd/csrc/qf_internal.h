@@ -192,7 +192,7 @@ struct BatchArgs {
   qf_options opt;
   double* hist;             // device, n_blocks x S x ring
   int ring;
-  double* scratch;          // device, batch_scratch_entries(grid) c128 entries
+  double* scratch;          // device, batch_scratch_entries(n_blocks, S) c128 entries
   double* out_cost;         // device, n_blocks x S
   int32_t* out_best;        // device, n_blocks
   int32_t* out_status;      // device, n_blocks
@@ -200,12 +200,15 @@ struct BatchArgs {
   int32_t* queue;           // device, 1 (zero before launch)
   const int32_t* kinds;     // device, total_gates gate kinds (nullptr = all general U(4))
 };
-// Quads of one wavefront hold (block, start) pairs: 16 / S blocks per group
-// of work; at most kBatchMaxGrid workgroups, each with its own FP64 scratch.
-constexpr int kBatchMaxGrid = 2048;
-int batch_groups(int n_blocks, int S);
-int batch_grid(int precision, int n_groups);  // workgroups to launch (device occupancy)
-size_t batch_scratch_entries(int grid);       // c128 scratch entries for `grid` workgroups
+// A workgroup of `slots` hexes (8 or 16, each one (block, start)) takes
+// slots / S blocks per group of work; at most kBatchMaxHexes hexes in a
+// launch, each with its own FP64 scratch.
+constexpr int kBatchMaxHexes = 32768;
+int batch_groups(int n_blocks, int S, int slots);
+int batch_max_grid(int slots);
+int batch_wg_per_cu_max(int slots);                   // occupancy limit of the kernel
+int batch_grid(int slots, int wg_per_cu, int n_groups);  // workgroups to launch
+size_t batch_scratch_entries(int n_blocks, int S);    // c128 scratch entries for every slots choice
 
 // Gradient (qf_grad.hip).
 hipError_t launch_grad_finish(hipStream_t st, const double* envP, const double* gates, const double* trace, int n,
@@ -213,7 +216,7 @@ hipError_t launch_grad_finish(hipStream_t st, const double* envP, const double* 
 hipError_t launch_su4_expm(hipStream_t st, const double* theta, int count, double* gates);
 hipError_t launch_su4_vjp(hipStream_t st, const double* theta, const double* grad_gates, int count,
                           double* dtheta);
-hipError_t launch_batch(hipStream_t st, int precision, int grid, const BatchArgs& a);
+hipError_t launch_batch(hipStream_t st, int slots, int grid, const BatchArgs& a);
 size_t resident_lds_bytes(int n, int precision);
 
 

@@ -205,3 +205,50 @@ def test_batch_full_size_sampled(qf, precision):
                 assert abs(O.cost(pr.target, gb[s], pr.locs, pr.n) - res.costs[b, s]) <= 1e-12, (b, s)
     frac = float(np.mean(res.status == 0))
     assert frac > 0.5, frac
+
+
+@pytest.mark.parametrize("n_starts", [3, 8])
+def test_batch_launch_shapes_bitwise_equal(qf, n_starts):
+    """The tuner of the batched launch (hexes per workgroup, workgroups per
+    CU) changes no result: the tuned run and runs forced to each shape give
+    bitwise the same costs, sweeps, statuses, best starts and gates, and the
+    tuned shape is one of the candidates.  Blocks of uneven gate counts, so
+    a workgroup's blocks idle through each other's steps differently in
+    every shape."""
+    probs = mixed_blocks(91 + n_starts, 40, n_starts)
+    cuda = torch.device("cuda")
+    qf.set_batch_config(cuda, n_starts, 0)  # tune on this call
+    ref = run_batch(qf, probs, 1e-8, precision=0)
+    assert (ref.slots, ref.wg_per_cu) in {(16, 1), (8, 1), (8, 2)}
+    try:
+        for slots, per in ((16, 1), (8, 1), (8, 2)):
+            qf.set_batch_config(cuda, n_starts, slots, per)
+            r = run_batch(qf, probs, 1e-8, precision=0)
+            assert (r.slots, r.wg_per_cu) == (slots, per)
+            assert np.array_equal(r.costs, ref.costs)
+            assert np.array_equal(r.sweeps, ref.sweeps)
+            assert np.array_equal(r.status, ref.status)
+            assert np.array_equal(r.best, ref.best)
+            assert torch.equal(r.gates, ref.gates)
+    finally:
+        qf.set_batch_config(cuda, n_starts, 0)
+
+
+def test_batch_in_place_gates(qf):
+    """out_gates == init_gates: the tuner cannot restore trial output, so the
+    call takes the default shape untimed; the results equal a run into a
+    separate buffer."""
+    probs = mixed_blocks(97, 12, 2)
+    cuda = torch.device("cuda")
+    qf.set_batch_config(cuda, 2, 0)
+    targets = [dev(p.target) for p in probs]
+    gates = [dev(p.init_gates) for p in probs]
+    bn, go, lf, tf, gf = qf.pack_batch(targets, [p.locs for p in probs], gates)
+    sep = qf.instantiate_batch(bn, go, lf, tf, gf, 2, tol=1e-8)
+    qf.set_batch_config(cuda, 2, 0)
+    g_in = gf.clone()
+    inp = qf.instantiate_batch(bn, go, lf, tf, g_in, 2, tol=1e-8, out_gates=g_in)
+    assert (inp.slots, inp.wg_per_cu) == (16, 1)
+    assert torch.equal(inp.gates, sep.gates)
+    assert np.array_equal(inp.costs, sep.costs)
+    qf.set_batch_config(cuda, 2, 0)
