@@ -678,6 +678,7 @@ __device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvD
 
 template <typename R>
 __global__ __launch_bounds__(kEnvThreads) void k_env(const cx<R>* __restrict__ X, EnvDev d) {
+  __builtin_amdgcn_s_setprio(3);  // as in k_fused: beside other groups' passes
   env_body<R>(X, d, blockIdx.x);
 }
 
