@@ -143,7 +143,7 @@ int resolve_mode(int n, const qf_options& o) {
 struct Layout {
   size_t X = 0, R = 0, gates = 0, uold = 0, partials = 0, counters = 0, costs = 0, trace = 0,
          frozen = 0, locs = 0, kinds = 0, hist = 0, flags = 0, cur = 0, fin = 0, sync = 0, info = 0, histo = 0,
-         uold2 = 0, ops2 = 0, partials2 = 0;
+         uold2 = 0, ops2 = 0, partials2 = 0, ywarm = 0;
   size_t total = 0;
   int ring = 2;
 };
@@ -174,6 +174,7 @@ Layout make_layout(int n, int p, int S, const qf_options& o, int mode, int histo
     }
   }
   L.gates = take((size_t)S * p * 16 * 16);
+  L.ywarm = take((size_t)S * p * 2 * 16 * 16);  // warm starts of the FP64 updates, per (start, gate, half)
   L.costs = take((size_t)S * 8);
   L.locs = take((size_t)p * 2 * 4);
   L.kinds = take((size_t)p * 4);
@@ -599,6 +600,8 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
     ea.partials = reinterpret_cast<double*>(ws + L.partials) + (size_t)q.s0 * nwg_stride * 32;
     ea.counters = reinterpret_cast<int32_t*>(ws + L.counters) + q.s0;
     ea.nwg = (int)env_workgroups(n, q.ns);
+    ea.ywstride = (int64_t)p * 32;
+    ea.ywarm = reinterpret_cast<double*>(ws + L.ywarm) + (size_t)q.s0 * ea.ywstride * 2;
   }
 
   KernelTimer timer;
@@ -904,6 +907,9 @@ int run_streaming(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs,
   if (timer.on) QF_HIP(ctx, hipEventRecord(timer.s0, st));
   while (decision == kContinue) {
     ++i;
+    // the FP64 updates start from their gate's previous rotation, cold in
+    // the first sweep and once every kWarmPeriod sweeps
+    for (int gi = 0; gi < 2 * kMaxGroups; ++gi) grp[gi].ea.warm = ((i - 1) % kWarmPeriod) != 0;
     if ((rc = sweep())) return rc;
     if (o.reset_iter > 0 && i % o.reset_iter == 0) {
       if ((rc = build_builder(ctx, n, V, p, locs, gates, gstride, S, prec, X))) return rc;
@@ -986,6 +992,7 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
   a.history_out = history_rows > 0 ? reinterpret_cast<double*>(ws + L.histo) : nullptr;
   a.history_rows = history_rows;
   a.kinds = o.gate_kinds ? reinterpret_cast<const int32_t*>(ws + L.kinds) : nullptr;
+  a.ywarm = reinterpret_cast<double*>(ws + L.ywarm);
   QF_HIP(ctx, launch_fill_i32(st, a.sync, 0, 16));
   QF_HIP(ctx, launch_fill_i32(st, a.out_info, 0, 16));
   int ok = 0;
@@ -1020,8 +1027,8 @@ int run_resident(qf_ctx* ctx, int n, const void* V, int p, int S, double tol, co
 
 // Workspace layout of qf_instantiate_batch.
 struct BatchLayout {
-  size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, kinds = 0, hist = 0, scratch = 0, cost = 0,
-         best = 0, status = 0, sweeps = 0, queue = 0;
+  size_t order = 0, blk_n = 0, gate_off = 0, tgt_off = 0, locs = 0, kinds = 0, hist = 0, scratch = 0, ywarm = 0,
+         cost = 0, best = 0, status = 0, sweeps = 0, queue = 0;
   size_t total = 0;
   int ring = 2;
 };
@@ -1044,6 +1051,7 @@ BatchLayout make_batch_layout(int n_blocks, int total_gates, int S, const qf_opt
   L.ring = std::max(2, o.long_diff_count + 1);
   L.hist = take(nb * S * L.ring * 8);
   L.scratch = take(batch_scratch_entries(n_blocks, S) * 16);
+  L.ywarm = take((size_t)total_gates * S * 2 * 16 * 16);
   L.cost = take(nb * S * 8);
   L.best = take(nb * 4);
   L.status = take(nb * 4);
@@ -1986,6 +1994,7 @@ int qf_instantiate_batch(qf_ctx* ctx, int n_blocks, const int32_t* block_n, cons
   a.hist = reinterpret_cast<double*>(ws + L.hist);
   a.ring = L.ring;
   a.scratch = reinterpret_cast<double*>(ws + L.scratch);
+  a.ywarm = reinterpret_cast<double*>(ws + L.ywarm);
   a.out_cost = reinterpret_cast<double*>(ws + L.cost);
   a.out_best = reinterpret_cast<int32_t*>(ws + L.best);
   a.out_status = reinterpret_cast<int32_t*>(ws + L.status);

@@ -99,6 +99,7 @@ struct BatchDev {
   int32_t* out_best, *out_status, *out_sweeps;
   int32_t* queue;           // work counter (zero before launch)
   const int32_t* kinds;     // gate kinds over all gates (nullptr = all general U(4))
+  cd* ywarm;                // per (gate, start, half) the FP64 update's last rotation Y
 };
 
 // Per-hex problem description.
@@ -109,6 +110,7 @@ struct HexJob {
   const int32_t* locs;  // this block's locations
   const cd* V;          // this block's target
   cd* g;                // this start's gates (p x 16)
+  cd* y;                // this start's warm-start rotations (p x 2 x 16)
   const int32_t* kinds; // this block's gate kinds (nullptr = all general U(4))
 };
 
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(SLOTS* kBLanes) void k_batch(BatchDev d) {
     jb.locs = d.locs + 2 * (size_t)d.gate_off[jb.b];
     jb.V = d.V + (jb.valid ? d.tgt_off[jb.b] : 0);
     jb.g = d.gates + ((size_t)d.gate_off[jb.b] * d.S + (size_t)jb.s * jb.p) * 16;
+    jb.y = d.ywarm + ((size_t)d.gate_off[jb.b] * d.S + (size_t)jb.s * jb.p) * 32;
     jb.kinds = d.kinds ? d.kinds + d.gate_off[jb.b] : nullptr;
     const int pmax = wg_max(jb.p);
     double* hist = d.hist + ((size_t)jb.b * d.S + jb.s) * d.ring;
@@ -271,7 +274,13 @@ __global__ __launch_bounds__(SLOTS* kBLanes) void k_batch(BatchDev d) {
             const cd e = env_entry(P, U, half, r, c);
             const cd urc = U[4 * r + c];
             cd un = urc;
-            if (!frozen) optimize_gate_f64_hex(e, U[4 * c + r], urc, r, c, o.beta, un);
+            // warm start from this gate's rotation of the previous sweep
+            // (same half); cold in the first sweep and every kWarmPeriod-th
+            cd* yp = jb.y + 32 * g + 16 * half + 4 * r + c;
+            cd yv = *yp;
+            const bool warm = ((it - 1) % kWarmPeriod) != 0;
+            if (!frozen) optimize_gate_f64_hex(e, U[4 * c + r], urc, r, c, o.beta, un, &yv, warm);
+            *yp = yv;
             PUs[h][4 * r + c] = un;
             jb.g[16 * g + 4 * r + c] = un;
           } else if (i < 4) {  // restricted kinds: the quad form on lanes 0..3, lane i = row i
@@ -430,6 +439,8 @@ hipError_t launch_batch(hipStream_t st, int slots, int grid, const BatchArgs& a)
   d.out_sweeps = a.out_sweeps;
   d.queue = a.queue;
   d.kinds = a.kinds;
+  d.ywarm = reinterpret_cast<cd*>(a.ywarm);
+  if (!d.ywarm) return hipErrorInvalidValue;
   if (slots == 8)
     hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(8 * kBLanes), 0, st, d);
   else

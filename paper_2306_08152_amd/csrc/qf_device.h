@@ -442,24 +442,53 @@ __device__ __forceinline__ double hex_round(cd& m, cd& y, int c) {
 
 // m: this lane's entry (r, c) of M (overwritten); keep: entry (r, c) of the
 // result for a zero M; unew: entry (r, c) of the maximiser of Re Tr(M u).
-// Same results and return codes as nearest_unitary_f64_quad.
-__device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& unew) {
+// Same results and return codes as nearest_unitary_f64_quad when y_io is
+// null.
+//
+// Warm start (y_io non-null): y_io holds entry (r, c) of the accumulated
+// rotation Y of an earlier update of the same gate.  With warm set, the
+// Jacobi step starts from that Y (M Y for M, Y for the rotation): any
+// unitary start gives the same orthogonalised columns and so the same
+// maximiser up to round-off, and where consecutive environments of a gate
+// are alike M Y is nearly column-orthogonal already, so fewer rounds run.
+// The new Y is written back (the identity for a zero or a non-finite M).
+// Callers start cold now and then so that the round-off of Y's accumulated
+// rotations stays at a few ulps.
+constexpr int kWarmPeriod = 16;  // a gate's updates start cold once in this many sweeps
+
+__device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& unew, cd* y_io = nullptr,
+                                              bool warm = false) {
   double amax = fmax(fabs(m.re), fabs(m.im));
   double bad = (finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0;
   amax = hex_max(amax);
   bad = hex_max(bad);
-  if (bad != 0.0) {
-    const double nan = __builtin_nan("");
-    unew = mk(nan, nan);
-    return 2;
-  }
-  if (!(amax >= 1e-300)) {
+  if (bad != 0.0 || !(amax >= 1e-300)) {
+    if (y_io) *y_io = mk(c == r ? 1.0 : 0.0, 0.0);  // the next warm start is a cold one
+    if (bad != 0.0) {
+      const double nan = __builtin_nan("");
+      unew = mk(nan, nan);
+      return 2;
+    }
     unew = keep;
     return 1;
   }
   const double inv = rcp_nr(amax);
   m = scale(m, inv);
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
+  const int base = (int)(__lane_id() & ~15u);
+  if (y_io && warm) {
+    // M <- M Y: row r of M from the quad, column c of Y from the four quads
+    y = *y_io;
+    cd mr[4];
+    quad_gather(m, mr);
+    cd acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int src = base + hex_lane(k, c);
+      cmac(acc, mr[k], mk(__shfl(y.re, src, 64), __shfl(y.im, src, 64)));
+    }
+    m = acc;
+  }
   for (int sweep = 0; sweep < 30; ++sweep) {
     double rel = hex_round<1, kQuadXor1>(m, y, c);
     rel = fmax(rel, hex_round<2, kQuadXor2>(m, y, c));
@@ -506,7 +535,7 @@ __device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& 
   // c of X from the quad that holds it.
   cd yr[4];
   quad_gather(y, yr);
-  const int base = (int)(__lane_id() & ~15u);
+  if (y_io) *y_io = y;
   cd a = mk(0.0, 0.0);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -538,10 +567,11 @@ __device__ __forceinline__ cd env_entry(const cd* P, const cd* uold, int half, i
 // Hex form of OptimizeGate (Sec. III-A-1, Eq. opt_u; beta of Sec. III-A-2):
 // lane (r, c) passes E[r][c], u_old[c][r] and u_old[r][c] and receives
 // u_new[r][c]; bitwise the quad form's result.
-__device__ inline void optimize_gate_f64_hex(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew) {
+__device__ inline void optimize_gate_f64_hex(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew,
+                                             cd* y_io = nullptr, bool warm = false) {
   const double we = 1.0 - beta;  // exact 1 for beta = 0
   cd m = axpbyx(e, we, conj(uold_cr), beta);
-  nearest_unitary_f64_hex(m, uold_rc, r, c, unew);
+  nearest_unitary_f64_hex(m, uold_rc, r, c, unew, y_io, warm);
 }
 
 // ---------------------------------------------------------------- gate kinds

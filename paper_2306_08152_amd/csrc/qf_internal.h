@@ -106,6 +106,13 @@ struct EnvArgs {
   int kind;               // qf_gate_kind of the updated gate (update mode)
   int nwg;                // workgroups per start; 0 = env_workgroups(n, S)
   int64_t uold_stride = 16;  // complex entries between consecutive starts' u_old
+  // Warm starts of the general U(4) update (update mode, optional): start
+  // s at ywarm + ywstride * s complex entries, gate g and half h at
+  // 32 g + 16 h from there; warm = 0 starts cold (and stores the new
+  // rotation).
+  double* ywarm = nullptr;
+  int64_t ywstride = 0;
+  int warm = 0;
 };
 // Workgroups per start of the partial trace: at least env_min_workgroups(n)
 // (more than one for n >= 15); env_workgroups(n, S) spreads a launch of S
@@ -175,6 +182,7 @@ struct ResidentArgs {
   double* history_out;    // optional (rows x S)
   int32_t history_rows;
   const int32_t* kinds;   // device, p gate kinds (nullptr = all general U(4))
+  double* ywarm;          // c128 S x p x 2 x 16: warm starts of the FP64 updates
 };
 hipError_t launch_resident(hipStream_t st, const ResidentArgs& a, int* ok_coresident);
 
@@ -193,6 +201,7 @@ struct BatchArgs {
   double* hist;             // device, n_blocks x S x ring
   int ring;
   double* scratch;          // device, batch_scratch_entries(n_blocks, S) c128 entries
+  double* ywarm;            // device, total_gates x S x 2 x 16 c128: the FP64 update's warm starts
   double* out_cost;         // device, n_blocks x S
   int32_t* out_best;        // device, n_blocks
   int32_t* out_status;      // device, n_blocks

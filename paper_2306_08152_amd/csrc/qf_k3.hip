@@ -453,6 +453,7 @@ constexpr uint32_t kEnv8Threads = 1024;
 constexpr uint32_t kEnv8Lanes = kEnv8Threads / 64;  // rest lanes per entry
 template <typename R>
 __global__ __launch_bounds__(kEnv8Threads) void k_env8(const cx<R>* __restrict__ X, Pass8Geom g, Env8Args a) {
+  __builtin_amdgcn_s_setprio(3);  // beside other groups' passes (stream groups)
   __shared__ cd red[kEnv8Threads];
   __shared__ cd P[64], U[64];
   __shared__ int frz;

@@ -577,7 +577,7 @@ __device__ __forceinline__ void env2_body(const cx<R>* __restrict__ X, const Env
   constexpr uint32_t LP = kEnv2Threads / E;
   static_assert(LP >= 1, "one thread per entry at least");
   __shared__ cd red[kEnv2Threads];
-  __shared__ cd uF[16], uS[16], unF[16], unS[16], P[16];
+  __shared__ cd uF[16], uS[16], unF[16], unS[16], P[16], yF[16], yS[16];
   __shared__ cd Msh[16 << (M - 2)];
   __shared__ int last, frz;
   const Pair2Geom& g = d.g;
@@ -593,6 +593,10 @@ __device__ __forceinline__ void env2_body(const cx<R>* __restrict__ X, const Env
     uS[t - 16] = reinterpret_cast<const cd*>(aS.gates)[(int64_t)s * aS.gstride + 16 * (int64_t)aS.gidx + t - 16];
   else if (t == 32)
     frz = (d.frozen && d.frozen[s]) ? 1 : 0;
+  else if (t >= 64 && t < 80)
+    ywarm_fetch(aF, s, t - 64, yF);
+  else if (t >= 80 && t < 96)
+    ywarm_fetch(aS, s, t - 80, yS);
   // T[a][b] = sum over rests r of X[(r, a), (r, b)]
   const uint32_t e = t & (E - 1u), lane = t / E;
   const uint32_t ro = dep_union(g, e / V), co = dep_union(g, e & (V - 1u));
@@ -663,7 +667,7 @@ __device__ __forceinline__ void env2_body(const cx<R>* __restrict__ X, const Env
     P[t] = sum;
   }
   __syncthreads();
-  env_finish(d.dF, s, P, uF, frz != 0, t, unF);
+  env_finish(d.dF, s, P, uF, frz != 0, t, unF, yF);
   __syncthreads();
   // S's partial trace after F's update: P_S = Tr_{U\S}[A_F T B_F] with
   // (A_F, B_F) = (u_F^dagger, u_F') in the first half, (u_F', u_F^dagger) in
@@ -700,7 +704,7 @@ __device__ __forceinline__ void env2_body(const cx<R>* __restrict__ X, const Env
     P[t] = sum;
   }
   __syncthreads();
-  env_finish(d.dS, s, P, uS, frz != 0, t, unS);
+  env_finish(d.dS, s, P, uS, frz != 0, t, unS, yS);
   __syncthreads();
   // the pass's operands: (A, B) = (u^dagger, u') per gate in the first half,
   // (u', u^dagger) in the second; x <- A_S A_F x B_F B_S

@@ -260,7 +260,11 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
           const cd ucr = gates[16 * g + 4 * c + r], urc = gates[16 * g + 4 * r + c];
           const cd e = env_entry(L.red, gates + 16 * g, half, r, c);
           cd unew = urc;
-          if (!frozen) optimize_gate_f64_hex(e, ucr, urc, r, c, o.beta, unew);
+          // warm start from this gate's rotation of the previous sweep
+          cd* yp = reinterpret_cast<cd*>(a.ywarm) + ((size_t)s * a.p + g) * 32 + 16 * half + 4 * r + c;
+          cd yv = *yp;
+          if (!frozen) optimize_gate_f64_hex(e, ucr, urc, r, c, o.beta, unew, &yv, ((i - 1) % kWarmPeriod) != 0);
+          *yp = yv;
           gates[16 * g + 4 * r + c] = unew;
           const cd udc = conj(ucr);  // (u_old^dagger)[r][c]
           const cd Av = sel(half == 0, udc, unew), Bv = sel(half == 0, unew, udc);

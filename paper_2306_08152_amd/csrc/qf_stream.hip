@@ -605,16 +605,18 @@ hipError_t launch_build_init(hipStream_t st, int precision, const void* V, void*
 template <typename R>
 __device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvDev& d, uint32_t wg) {
   __shared__ cd red[kEnvThreads];
-  __shared__ cd u_sh[16];
+  __shared__ cd u_sh[16], y_sh[16];
   __shared__ int last, frz;
   const uint32_t t = threadIdx.x;
   const uint32_t s = wg / d.nwg;
   const uint32_t w = wg - s * d.nwg;
-  // Gate update: fetch the old gate and the frozen flag now, so their latency
-  // hides under the partial trace (the reduction's barriers publish them).
+  // Gate update: fetch the old gate, the frozen flag and the warm start now,
+  // so their latency hides under the partial trace (the reduction's
+  // barriers publish them).
   if (d.a.do_update && t < 16)
     u_sh[t] = reinterpret_cast<const cd*>(d.a.gates)[(int64_t)s * d.a.gstride + 16 * (int64_t)d.a.gidx + t];
   if (t == 16) frz = (d.a.do_update && d.a.frozen && d.a.frozen[s]) ? 1 : 0;
+  if (t >= 32 && t < 48) ywarm_fetch(d.a, s, t - 32, y_sh);
   const uint32_t ij = t & 15u, i = ij >> 2, j = ij & 3u;
   const uint32_t ro = local_off(i, d.b0, d.b1), co = local_off(j, d.b0, d.b1);
   const cx<R>* Xs = X + (size_t)s * d.N * d.N;
@@ -643,7 +645,7 @@ __device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvD
     __syncthreads();
   }
   if (d.nwg == 1) {
-    env_finish(d, s, red, u_sh, frz != 0, t);
+    env_finish(d, s, red, u_sh, frz != 0, t, nullptr, y_sh);
     return;
   }
   cd* part = reinterpret_cast<cd*>(d.a.partials) + ((size_t)s * d.nwg + w) * 16;
@@ -673,7 +675,7 @@ __device__ __forceinline__ void env_body(const cx<R>* __restrict__ X, const EnvD
   }
   __syncthreads();
   if (t == 0) __hip_atomic_store(&d.a.counters[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  env_finish(d, s, red, u_sh, frz != 0, t);
+  env_finish(d, s, red, u_sh, frz != 0, t, nullptr, y_sh);
 }
 
 template <typename R>

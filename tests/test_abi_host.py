@@ -85,25 +85,27 @@ def test_workspace_size_layout(lib):
 
 
 def test_batch_workspace_size(lib):
-    """Batched layout: descriptors, history ring per (block, start), and an
+    """Batched layout: descriptors, history ring per (block, start), an
     FP64 scratch builder (16 x 16) per hex (16 lanes, one instantiation) of
-    each launched workgroup, which the complex128 kernel's fresh FP64
-    re-evaluations use."""
+    the largest launch any shape (8 or 16 hexes per workgroup) can make,
+    which the complex128 kernel's fresh FP64 re-evaluations use, and a 4 x 4
+    warm-start rotation per (gate, start, half of a sweep)."""
     I32 = ctypes.c_int32
     bn = (I32 * 3)(3, 4, 2)
     go = (I32 * 4)(0, 5, 17, 18)
     o = _opts(lib)
     ws = lib.qf_batch_workspace_size(3, bn, go, 8, ctypes.byref(o))
     ring = o.long_diff_count + 1
-    groups = 2  # two blocks of 8 starts per wavefront of 16 quads
-    assert ws >= 3 * 8 * ring * 8 + groups * 16 * 256 * 16
-    assert ws <= 3 * 8 * ring * 8 + groups * 16 * 256 * 16 + 8192
-    # more blocks than the workgroup cap: scratch stops growing
+    hexes = 2 * 16  # 16 hexes per workgroup hold two blocks of 8 starts: 2 workgroups
+    ywarm = 18 * 8 * 2 * 16 * 16
+    assert ws >= 3 * 8 * ring * 8 + hexes * 256 * 16 + ywarm
+    assert ws <= 3 * 8 * ring * 8 + hexes * 256 * 16 + ywarm + 8192
+    # more blocks than a launch has hexes: scratch stops growing
     big = 1 << 16
     bnb = (I32 * big)(*([3] * big))
     gob = (I32 * (big + 1))(*range(big + 1))
     wsb = lib.qf_batch_workspace_size(big, bnb, gob, 1, ctypes.byref(o))
-    assert wsb < big * ring * 8 + 2048 * 16 * 256 * 16 + (4 << 20)
+    assert wsb < big * ring * 8 + 32768 * 256 * 16 + big * 2 * 16 * 16 + (4 << 20)
     # invalid -> 0
     assert lib.qf_batch_workspace_size(3, bn, go, 17, ctypes.byref(o)) == 0
     assert lib.qf_batch_workspace_size(3, bn, go, 0, ctypes.byref(o)) == 0
