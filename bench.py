@@ -265,7 +265,8 @@ def u3cx_workload(qf, torch) -> dict:
 def k3_workload(qf, torch) -> dict:
     """Three-qubit gates: n = 10 brick-wall of 8 x 8 gates (6 layers, 16
     gates), 8 starts, 5 sweeps with the plateau tests off, both precisions
-    (start-sweeps/s and the time of one gate update: environment + pass);
+    (start-sweeps/s and the time of one gate update: environment + pass,
+    over the whole call and, from a 25-sweep call, without its fixed work);
     then a reachable n = 6 target (6 gates, 4 starts) to tol 1e-8."""
     import qfinputs as I
     n, S, K = 10, 8, 5
@@ -277,13 +278,20 @@ def k3_workload(qf, torch) -> dict:
     out = {}
     for prec, tag in ((1, "c64"), (0, "c128")):
         qf.instantiate3(V, pr.locs, g, max_iter=1, precision=prec, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        qf.instantiate3(V, pr.locs, g, max_iter=K, precision=prec, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dts = {}
+        for k in (K, 5 * K):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qf.instantiate3(V, pr.locs, g, max_iter=k, precision=prec, **kw)
+            torch.cuda.synchronize()
+            dts[k] = time.perf_counter() - t0
+        dt = dts[K]
         out[f"k3_n10_p{pr.n_gates}_s{S}_{tag}_start_sweeps_per_s"] = round(S * K / dt, 2)
         out[f"k3_n10_p{pr.n_gates}_s{S}_{tag}_us_per_gate_update"] = round(1e6 * dt / (K * 2 * pr.n_gates), 1)
+        # the same without the call's fixed work (builder construction, final
+        # FP64 costs): the extra 4K sweeps of the longer call
+        out[f"k3_n10_p{pr.n_gates}_s{S}_{tag}_us_per_gate_update_steady"] = round(
+            1e6 * (dts[5 * K] - dts[K]) / (4 * K * 2 * pr.n_gates), 1)
     small = I.k3_problem(39, 6, 4, 4)
     Vs, gs = torch.from_numpy(small.target).to("cuda"), torch.from_numpy(small.init_gates).to("cuda")
     qf.instantiate3(Vs, small.locs, gs, tol=1e-8)

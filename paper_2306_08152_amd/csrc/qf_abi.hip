@@ -1524,7 +1524,7 @@ int qf_instantiate_noalloc(qf_ctx* ctx, int n, const void* target, int n_gates, 
 // ------------------------------------------------------- three-qubit gates
 
 struct Layout3 {
-  size_t X = 0, R = 0, gates = 0, uold = 0, costs = 0, trace = 0, frozen = 0, total = 0;
+  size_t X = 0, R = 0, gates = 0, uold = 0, costs = 0, trace = 0, frozen = 0, ywarm = 0, total = 0;
 };
 
 Layout3 make_layout3(int n, int p, int S, int precision) {
@@ -1543,6 +1543,7 @@ Layout3 make_layout3(int n, int p, int S, int precision) {
   L.costs = take((size_t)S * 8);
   L.trace = take((size_t)S * 16);
   L.frozen = take((size_t)S * 4);
+  L.ywarm = take((size_t)S * p * 2 * 64 * 16);  // warm starts of the FP64 updates, per (start, gate, half)
   L.total = off;
   return L;
 }
@@ -1627,6 +1628,8 @@ int run_streaming3(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs
     q.ea.gstride = gstride;
     q.ea.uold = uold + (size_t)q.s0 * 64 * 2;
     q.ea.frozen = frozen + q.s0;
+    q.ea.ywstride = (int64_t)p * 128;
+    q.ea.ywarm = reinterpret_cast<double*>(ws + L.ywarm) + (size_t)q.s0 * q.ea.ywstride * 2;
   }
   auto update = [&](Group3& q, int g, int half, hipEvent_t after_env) -> int {
     q.ea.half = half;
@@ -1713,6 +1716,8 @@ int run_streaming3(qf_ctx* ctx, int n, const void* V, int p, const int32_t* locs
   int32_t decision = o.max_iter <= 0 ? kStopMaxIter : kContinue;
   while (decision == kContinue) {
     ++i;
+    // warm-started FP64 updates, cold in the first sweep and every kWarmPeriod-th
+    for (int gi = 0; gi < kMaxGroups; ++gi) grp[gi].ea.warm = ((i - 1) % kWarmPeriod) != 0;
     if ((rc = sweep())) return rc;
     if (o.reset_iter > 0 && i % o.reset_iter == 0) {
       if ((rc = build(prec, X))) return rc;

@@ -78,6 +78,12 @@ struct Env8Args {
   double* uold;              // S x 64 complex: u_old as used (for the pass)
   const int32_t* frozen;     // per start, nullptr = none
   double* env_out;           // S x 64 complex partial traces when do_update == 0
+  // warm starts of the update (optional): start s at ywarm + ywstride * s
+  // complex entries, gate g and half h at 128 g + 64 h, lane r + 8c holding
+  // entry (r, c); warm = 0 starts cold
+  double* ywarm = nullptr;
+  int64_t ywstride = 0;
+  int warm = 0;
 };
 hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8Geom& g, const Env8Args& a);
 hipError_t launch_optimize8(hipStream_t st, int count, const double* env, const double* uold, double beta,

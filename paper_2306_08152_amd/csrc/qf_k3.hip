@@ -361,21 +361,33 @@ __device__ __forceinline__ double oct_round(cd& m, cd& y, int c) {
 // m: entry (r, c) of M (overwritten); keep: entry (r, c) of the result for a
 // zero M.  Result entry (r, c) of the maximiser of Re Tr(M u); codes as the
 // 4 x 4 forms (0 computed, 1 zero M, 2 non-finite M).  All 64 lanes active,
-// lane = r + 8c.
-__device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew) {
+// lane = r + 8c.  y_io / warm: the warm start of the hex form (entry (r, c)
+// of the gate's previous rotation in, the new one out; the identity after a
+// zero or non-finite M).
+__device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew, cd* y_io = nullptr,
+                                              bool warm = false) {
   const double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
   const double bad = oct_wavemax((finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0);
-  if (bad != 0.0) {
-    const double nan = __builtin_nan("");
-    unew = mk(nan, nan);
-    return 2;
-  }
-  if (!(amax >= 1e-300)) {
+  if (bad != 0.0 || !(amax >= 1e-300)) {
+    if (y_io) *y_io = mk(c == r ? 1.0 : 0.0, 0.0);
+    if (bad != 0.0) {
+      const double nan = __builtin_nan("");
+      unew = mk(nan, nan);
+      return 2;
+    }
     unew = keep;
     return 1;
   }
   m = scale(m, rcp_nr(amax));
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
+  if (y_io && warm) {
+    // M <- M Y: row r of M from lanes r + 8k, column c of Y from lanes k + 8c
+    y = *y_io;
+    cd acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cmac(acc, shfl_cd(m, r + 8 * k), shfl_cd(y, k + 8 * c));
+    m = acc;
+  }
   for (int sweep = 0; sweep < 30; ++sweep) {
     double rel = oct_round<1>(m, y, c);
     rel = fmax(rel, oct_round<2>(m, y, c));
@@ -433,14 +445,16 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
     cmac(a, yrj, conj(xcj));
   }
   unew = a;
+  if (y_io) *y_io = y;
   return 0;
 }
 
 // Lane (r, c) passes E[r][c], u_old[c][r], u_old[r][c]; receives u_new[r][c]
 // for M = (1 - beta) E + beta u_old^dagger (Eq. opt_u; beta of Sec. III-A-2).
-__device__ inline void optimize_gate_f64_oct(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew) {
+__device__ inline void optimize_gate_f64_oct(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew,
+                                             cd* y_io = nullptr, bool warm = false) {
   cd m = axpbyx(e, 1.0 - beta, conj(uold_cr), beta);
-  nearest_unitary_f64_oct(m, uold_rc, r, c, unew);
+  nearest_unitary_f64_oct(m, uold_rc, r, c, unew, y_io, warm);
 }
 
 // ------------------------------------------------------------------ k_env8
@@ -462,6 +476,12 @@ __global__ __launch_bounds__(kEnv8Threads) void k_env8(const cx<R>* __restrict__
   const cd* gsrc = reinterpret_cast<const cd*>(a.gates) + (int64_t)s * a.gstride + 64 * (int64_t)a.gidx;
   if (a.do_update && t < 64) U[t] = gsrc[t];
   if (t == 64) frz = (a.do_update && a.frozen && a.frozen[s]) ? 1 : 0;
+  // the warm start (this gate's rotation of the previous sweep, same half),
+  // fetched under the partial trace; lane r + 8c holds entry (r, c)
+  cd* yw = a.ywarm ? reinterpret_cast<cd*>(a.ywarm) + (size_t)s * a.ywstride + 128 * (size_t)a.gidx + 64 * a.half
+                   : nullptr;
+  cd yv = mk(0.0, 0.0);
+  if (yw && a.do_update && t < 64) yv = yw[t];
   const uint32_t ij = t & 63u, i = ij >> 3, j = ij & 7u, rl = t >> 6;
   const uint32_t ro = local_off8(i, g.b), co = local_off8(j, g.b);
   const uint32_t nrest = g.N >> 3;
@@ -507,7 +527,8 @@ __global__ __launch_bounds__(kEnv8Threads) void k_env8(const cx<R>* __restrict__
   }
   const cd urc = U[8 * r + c];
   cd un = urc;
-  if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un);
+  if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un, yw ? &yv : nullptr, a.warm != 0);
+  if (yw) yw[t] = yv;
   reinterpret_cast<cd*>(a.uold)[64 * (size_t)s + rc] = urc;
   reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 64 * (int64_t)a.gidx + rc] = un;
 }

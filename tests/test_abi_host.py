@@ -118,11 +118,12 @@ def test_batch_workspace_size(lib):
 
 def test_workspace_size3_layout(lib):
     """Three-qubit gates: S builders of N^2 entries (plus an FP64 rebuild
-    copy each for complex64), S x p gates of 8 x 8 complex128, and small
-    per-start state; sizes outside n in [3, 14] are refused."""
+    copy each for complex64), S x p gates of 8 x 8 complex128, their
+    warm-start rotations (two 8 x 8 complex128 per gate and start), and
+    small per-start state; sizes outside n in [3, 14] are refused."""
     n, p, S = 10, 16, 8
     N = 1 << n
-    gates = S * p * 64 * 16
+    gates = S * p * 64 * 16 * 3
     o = _opts(lib, precision=nat.QF_C128)
     ws = lib.qf_workspace_size3(n, p, S, ctypes.byref(o))
     assert S * N * N * 16 + gates <= ws <= S * N * N * 16 + gates + (1 << 16)
