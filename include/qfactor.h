@@ -301,7 +301,7 @@ int qf_instantiate(qf_ctx* ctx, int n, const void* target, int n_gates, const in
  * QF_EWORKSPACE before any device work.  For circuits of about 5n gates
  * it holds, in complex64 / complex128 builders: n = 10 with up to 2 / 3
  * starts, n = 9 with 10 / 15,
- * n = 8 with 42 / 63, and every resident problem (n <= 6); no n >= 11
+ * n = 8 with 40 / 62, and every resident problem (n <= 6); no n >= 11
  * problem fits.  qf_workspace_size gives the exact need.  All calls on
  * one device share the array, so calls that overlap on a device (several
  * host threads, or contexts on different streams) race and must be
