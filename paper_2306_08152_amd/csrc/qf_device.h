@@ -440,18 +440,97 @@ __device__ __forceinline__ double hex_round(cd& m, cd& y, int c) {
   return j.large;
 }
 
+// Sum over all 16 lanes of a hex group; bitwise the same in every lane.
+__device__ __forceinline__ double hex_sum(double v) { return hex_colsum(quad_sum(v)); }
+
+// Newton form of the nearest-unitary step.  The maximiser of Re Tr(M u) over
+// unitary u is Q^dagger, Q the unitary polar factor of M (M = Q H, H
+// Hermitian positive semidefinite).  For a nonsingular M, Q is the limit of
+// the scaled Newton iteration of Higham ("Computing the polar decomposition
+// -- with applications", SIAM J. Sci. Stat. Comput. 7, 1986):
+//   X_0 = M,  X_{k+1} = (z_k X_k + X_k^{-dagger} / z_k) / 2,
+// with the Frobenius-norm scaling z_k = (|X_k^-1|_F / |X_k|_F)^(1/2).  Each
+// step keeps the singular vectors and maps every singular value s to
+// (z s + 1 / (z s)) / 2, so the iteration converges quadratically once they
+// are near 1.  In the hex layout each lane forms its own cofactor C[r][c]
+// (the signed determinant of the 3 x 3 minor without row r and column c):
+// X^{-dagger}[r][c] = conj(C[r][c]) / conj(det X), and det X is the sum of
+// X[r][c] C[r][c] over the 16 lanes divided by 4 (each row's Laplace
+// expansion gives it once).  dist = |X|_F^2 + |X^-1|_F^2 - 8, the sum of
+// (s - 1/s)^2 over the singular values, measures the distance from
+// unitarity: steps are scaled while dist > 1e-2, and the iteration ends
+// with the step taken at dist <= 1e-14 (every |s - 1| is then below 5e-8,
+// and the step leaves it near 1e-15).  Every decision is taken on hex sums,
+// bitwise the same in all 16 lanes.
+// Cramer's rule is accurate only for a well-conditioned X (the polar
+// factor's error grows like the squared condition number times the unit
+// roundoff), so the form is taken only when |M|_F^2 |M^-1|_F^2 < 1e6; for
+// other M, and if 10 steps have not converged, it returns false and the
+// caller takes the Jacobi form.
+constexpr double kPolarCond2 = 1e6;
+constexpr double kPolarScaleAbove = 1e-2;
+constexpr double kPolarDone = 1e-14;
+constexpr int kPolarMaxSteps = 10;
+
+// x: this lane's entry (r, c) of M, entries at most 1 in magnitude; base:
+// the group's first lane.  On success q is entry (r, c) of Q.
+__device__ inline bool polar_newton_hex(cd x, int r, int c, int base, cd& q) {
+  int src[9];  // lanes of the minor's entries, rows and columns ascending
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) src[3 * i + j] = base + hex_lane(i + (i >= r ? 1 : 0), j + (j >= c ? 1 : 0));
+  const double sgn = ((r + c) & 1) ? -1.0 : 1.0;
+  for (int step = 0; step < kPolarMaxSteps; ++step) {
+    cd a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = mk(__shfl(x.re, src[k], 64), __shfl(x.im, src[k], 64));
+    const cd m0 = mulx(a[4], a[8]) - mulx(a[5], a[7]);
+    const cd m1 = mulx(a[3], a[8]) - mulx(a[5], a[6]);
+    const cd m2 = mulx(a[3], a[7]) - mulx(a[4], a[6]);
+    const cd cof = scale(mulx(a[0], m0) - mulx(a[1], m1) + mulx(a[2], m2), sgn);
+    const cd p = mulx(x, cof);
+    const double nx = hex_sum(nrm2x(x));
+    const double nc = hex_sum(nrm2x(cof));
+    const cd det = mk(0.25 * hex_sum(p.re), 0.25 * hex_sum(p.im));
+    const double d2 = nrm2x(det);
+    if (step == 0 && !(nx * nc < kPolarCond2 * d2)) return false;  // also a zero or non-finite det
+    const double inv_d2 = rcp_nr(d2);
+    const double nxi = nc * inv_d2;  // |X^-1|_F^2
+    const double dist = (nx + nxi) - 8.0;
+    double z = 1.0, zi = 1.0;
+    if (dist > kPolarScaleAbove) {
+      // z = (nxi / nx)^(1/4) and 1 / z from hardware estimates: any positive
+      // scaling keeps the limit, and the last steps are unscaled
+      const double t = __builtin_amdgcn_rsq(nxi * __builtin_amdgcn_rcp(nx));
+      z = __builtin_amdgcn_rsq(t);
+      zi = t * z;
+    }
+    const cd w = scale(det, 0.5 * zi * inv_d2);  // conj(C) w = X^{-dagger} / (2 z)
+    const double hz = 0.5 * z;
+    x = mk(fma(hz, x.re, fma(cof.re, w.re, cof.im * w.im)), fma(hz, x.im, fma(cof.re, w.im, -(cof.im * w.re))));
+    if (dist <= kPolarDone) {
+      q = x;
+      return true;
+    }
+  }
+  return false;
+}
+
 // m: this lane's entry (r, c) of M (overwritten); keep: entry (r, c) of the
 // result for a zero M; unew: entry (r, c) of the maximiser of Re Tr(M u).
-// Same results and return codes as nearest_unitary_f64_quad when y_io is
-// null.
+// The Newton form above runs first; where it declines, a one-sided Jacobi
+// step in the hex layout takes over, with the same results and return
+// codes as nearest_unitary_f64_quad when y_io is null.
 //
 // Warm start (y_io non-null): y_io holds entry (r, c) of the accumulated
-// rotation Y of an earlier update of the same gate.  With warm set, the
-// Jacobi step starts from that Y (M Y for M, Y for the rotation): any
-// unitary start gives the same orthogonalised columns and so the same
-// maximiser up to round-off, and where consecutive environments of a gate
-// are alike M Y is nearly column-orthogonal already, so fewer rounds run.
-// The new Y is written back (the identity for a zero or a non-finite M).
+// rotation Y of the gate's last Jacobi update.  With warm set, the Jacobi
+// step starts from that Y (M Y for M, Y for the rotation): any unitary start
+// gives the same orthogonalised columns and so the same maximiser up to
+// round-off, and where consecutive environments of a gate are alike M Y is
+// nearly column-orthogonal already, so fewer rounds run.  The new Y is
+// written back; the identity after a Newton update and for a zero or a
+// non-finite M.
 // Callers start cold now and then so that the round-off of Y's accumulated
 // rotations stays at a few ulps.
 constexpr int kWarmPeriod = 16;  // a gate's updates start cold once in this many sweeps
@@ -476,6 +555,16 @@ __device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& 
   m = scale(m, inv);
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
   const int base = (int)(__lane_id() & ~15u);
+  {
+    cd q;
+    if (polar_newton_hex(m, r, c, base, q)) {
+      if (y_io) *y_io = y;
+      // u_new[r][c] = conj(Q[c][r])
+      const int src = base + hex_lane(c, r);
+      unew = conj(mk(__shfl(q.re, src, 64), __shfl(q.im, src, 64)));
+      return 0;
+    }
+  }
   if (y_io && warm) {
     // M <- M Y: row r of M from the quad, column c of Y from the four quads
     y = *y_io;
@@ -566,7 +655,8 @@ __device__ __forceinline__ cd env_entry(const cd* P, const cd* uold, int half, i
 
 // Hex form of OptimizeGate (Sec. III-A-1, Eq. opt_u; beta of Sec. III-A-2):
 // lane (r, c) passes E[r][c], u_old[c][r] and u_old[r][c] and receives
-// u_new[r][c]; bitwise the quad form's result.
+// u_new[r][c]; the quad form's result up to round-off (bitwise where the
+// Newton form declines and y_io is null).
 __device__ inline void optimize_gate_f64_hex(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew,
                                              cd* y_io = nullptr, bool warm = false) {
   const double we = 1.0 - beta;  // exact 1 for beta = 0

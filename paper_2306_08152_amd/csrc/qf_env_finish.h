@@ -75,8 +75,8 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
 }
 
 // The general U(4) update on the 16 lanes of a hex (lane i = entry
-// (hex_row(i), i & 3)); bitwise the quad form's result in about two thirds of
-// its time.
+// (hex_row(i), i & 3)): the Newton polar form, or the hex Jacobi form
+// (bitwise the quad form's result) where that declines.
 // y_sh: the warm-start rotation (row-major, LDS) when a.ywarm is set,
 // fetched at kernel start by ywarm_fetch.
 __device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,

@@ -218,6 +218,39 @@ def test_optimize_gate_vs_lapack(qf):
     assert np.all(np.isnan(got[1]))
 
 
+def test_optimize_gate_condition_sweep(qf):
+    """The update for environments whose condition number sweeps 1 .. 1e7
+    (squared Frobenius condition number |M|_F^2 |M^-1|_F^2 from about 16 to
+    1e15), across the point where the hex form hands over from the Newton
+    polar iteration (|M|_F^2 |M^-1|_F^2 < 1e6) to the Jacobi SVD: unitary to
+    1e-12, the polar factor to the condition-number bound of the LAPACK
+    comparison, the attained value the nuclear norm, on both sides alike."""
+    rng = np.random.default_rng(7)
+    envs = []
+    for k in range(96):
+        lo = -7.0 * k / 95.0  # smallest singular value 1 .. 1e-7
+        s = np.sort(10.0 ** rng.uniform(lo, 0.0, 4))[::-1]
+        s[0], s[-1] = 1.0, 10.0 ** lo
+        E = I.haar_unitary(rng, 4) @ np.diag(s) @ I.haar_unitary(rng, 4)
+        envs.append(E * 10.0 ** rng.uniform(-3, 3))
+    E = np.stack(envs)
+    U0 = np.stack([I.haar_unitary(rng, 4) for _ in range(96)])
+    got = host(qf.optimize_gate(dev(E), dev(U0), 0.0))
+    c2 = []
+    for k in range(96):
+        ref = O.optimize_gate(E[k], U0[k], 0.0)
+        assert np.abs(got[k].conj().T @ got[k] - np.eye(4)).max() < 1e-12, k
+        sv = np.linalg.svd(E[k], compute_uv=False)
+        kappa = sv[0] / sv[-1]
+        c2.append(np.sum(sv ** 2) * np.sum(sv ** -2.0))
+        assert np.abs(got[k] - ref).max() < max(1e-12, 1e-14 * kappa) * 10, (k, kappa)
+        Mn = E[k] / np.abs(E[k]).max()
+        svn = np.linalg.svd(Mn, compute_uv=False)
+        assert abs(np.real(np.trace(Mn @ got[k])) - svn.sum()) <= 1e-12 * svn.sum(), k
+    c2 = np.asarray(c2)
+    assert (c2 < 1e5).sum() >= 10 and (c2 > 1e7).sum() >= 10  # both forms ran
+
+
 @pytest.mark.parametrize("n", [3, 7, 10])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_update_gate_steps(qf, n, dtype):
