@@ -358,12 +358,115 @@ __device__ __forceinline__ double oct_round(cd& m, cd& y, int c) {
   return j.large;
 }
 
+// Sum over the 64 lanes; bitwise the same in every lane (each level adds a
+// pair of lanes that differ in one bit, so the two see the same operands).
+__device__ __forceinline__ double oct_wavesum(double v) {
+  v += dpp_quad<kQuadXor1>(v);
+  v += dpp_quad<kQuadXor2>(v);
+  v += dpp_xor4(v);
+  v += dpp_quad<kRowRor8>(v);
+  v += swz_xor<16>(v);
+  return v + __shfl_xor(v, 32, 64);
+}
+// A wave-uniform lane's value (lane in an SGPR).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Newton form of the 8 x 8 nearest-unitary step: the scaled Newton polar
+// iteration of the hex form (Higham 1986; X <- (z X + X^{-dagger} / z) / 2,
+// z = (|X^-1|_F / |X|_F)^(1/2)), with X^-1 from Gauss-Jordan elimination with
+// partial pivoting on [X | I] across the wavefront: in step k the pivot row
+// p_k is the unused row of largest |X[r][k]|, every other row (used or not)
+// loses its column-k component, and no rows are swapped, so X^-1[k][c] is
+// entry (p_k, c) of the right half.  dist = |X|_F^2 + |X^-1|_F^2 - 16, the
+// sum of (s - 1/s)^2 over the singular values: scaled steps while dist >
+// 1e-2, and the step taken at dist <= 4e-14 is the last (every |s - 1| is
+// below 1e-7 there, about 5e-15 after the step).  The pivoted elimination is
+// accurate to about the condition number times the unit roundoff; the form
+// is taken for |M|_F^2 |M^-1|_F^2 < 1e8 and otherwise (or if 12 steps have
+// not converged, or a pivot vanishes) returns false for the Jacobi form.
+// All decisions are on wave-uniform values.  x: entry (r, c) of M (entries at
+// most 1 in magnitude), lane r + 8c; q: entry (r, c) of the polar factor.
+constexpr double kPolar8Cond2 = 1e8;
+constexpr double kPolar8ScaleAbove = 1e-2;
+constexpr double kPolar8Done = 4e-14;
+constexpr int kPolar8MaxSteps = 12;
+
+__device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
+  const int grp = 8 * c;  // first lane of this lane's column group
+  for (int step = 0; step < kPolar8MaxSteps; ++step) {
+    cd a = x, b = mk(r == c ? 1.0 : 0.0, 0.0);
+    int piv[8];
+    unsigned used = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const cd col = shfl_cd(a, r + 8 * k);  // entry (r, k) of the left half
+      const double mag = ((used >> r) & 1u) ? -1.0 : nrm2x(col);
+      // the largest over the eight rows (every group holds the same column),
+      // then the lowest row that attains it, from group 0's ballot bits
+      double mx = fmax(mag, dpp_quad<kQuadXor1>(mag));
+      mx = fmax(mx, dpp_quad<kQuadXor2>(mx));
+      mx = fmax(mx, dpp_xor4(mx));
+      const unsigned long long hit = __ballot(mag == mx) & 0xFFull;
+      if (hit == 0) {  // a non-finite column
+        ok = false;
+        break;
+      }
+      const int p = __builtin_ctzll(hit);
+      const cd pv = mk(readlane_d(col.re, p), readlane_d(col.im, p));
+      const double pv2 = nrm2x(pv);
+      if (!(pv2 > 1e-280)) {
+        ok = false;
+        break;
+      }
+      const double ip = rcp_nr(pv2);
+      const cd inv = mk(pv.re * ip, -(pv.im * ip));  // 1 / pv
+      const cd pa = mulx(shfl_cd(a, grp + p), inv);
+      const cd pb = mulx(shfl_cd(b, grp + p), inv);
+      const bool prow = r == p;
+      const cd ua = a - mulx(col, pa), ub = b - mulx(col, pb);
+      a = sel(prow, pa, ua);
+      b = sel(prow, pb, ub);
+      used |= 1u << p;
+      piv[k] = p;
+    }
+    if (!ok) return false;
+    int pc = piv[0];  // pivot row of column c
+#pragma unroll
+    for (int j = 1; j < 8; ++j) pc = (c == j) ? piv[j] : pc;
+    const cd xi = conj(shfl_cd(b, pc + 8 * r));  // X^{-dagger}[r][c] = conj(X^-1[c][r])
+    const double nx = oct_wavesum(nrm2x(x));
+    const double nxi = oct_wavesum(nrm2x(b));
+    if (step == 0 && !(nx * nxi < kPolar8Cond2)) return false;
+    const double dist = (nx + nxi) - 16.0;
+    double z = 1.0, zi = 1.0;
+    if (dist > kPolar8ScaleAbove) {
+      const double t = __builtin_amdgcn_rsq(nxi * __builtin_amdgcn_rcp(nx));
+      z = __builtin_amdgcn_rsq(t);
+      zi = t * z;
+    }
+    const double hz = 0.5 * z, hzi = 0.5 * zi;
+    x = mk(fma(hz, x.re, hzi * xi.re), fma(hz, x.im, hzi * xi.im));
+    if (dist <= kPolar8Done) {
+      q = x;
+      return true;
+    }
+  }
+  return false;
+}
+
 // m: entry (r, c) of M (overwritten); keep: entry (r, c) of the result for a
 // zero M.  Result entry (r, c) of the maximiser of Re Tr(M u); codes as the
 // 4 x 4 forms (0 computed, 1 zero M, 2 non-finite M).  All 64 lanes active,
-// lane = r + 8c.  y_io / warm: the warm start of the hex form (entry (r, c)
-// of the gate's previous rotation in, the new one out; the identity after a
-// zero or non-finite M).
+// lane = r + 8c.  The Newton form runs first; the one-sided Jacobi step where
+// it declines.  y_io / warm: the warm start of the hex form's Jacobi step
+// (entry (r, c) of the gate's previous rotation in, the new one out; the
+// identity after a Newton update and after a zero or non-finite M).
 __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew, cd* y_io = nullptr,
                                               bool warm = false) {
   const double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
@@ -380,6 +483,14 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
   }
   m = scale(m, rcp_nr(amax));
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
+  {
+    cd q;
+    if (polar_newton_oct(m, r, c, q)) {
+      if (y_io) *y_io = y;
+      unew = conj(shfl_cd(q, c + 8 * r));  // u_new[r][c] = conj(Q[c][r])
+      return 0;
+    }
+  }
   if (y_io && warm) {
     // M <- M Y: row r of M from lanes r + 8k, column c of Y from lanes k + 8c
     y = *y_io;

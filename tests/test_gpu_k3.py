@@ -5,8 +5,9 @@ whose k-qubit forms are pinned in test_oracle_pins.py.
 Tolerances: complex128 sweeps follow the oracle's trajectory update by update
 (gates to 1e-9 after a few sweeps, costs to 1e-10); complex64 builders to
 1e-5 in the costs (1e-4 in the gates after three sweeps), with the 8 x 8
-products on the matrix cores for n >= 8; the 8 x 8 update is unitary to 1e-12 and attains the nuclear
-norm to 1e-12 relative."""
+products on the matrix cores for n >= 8; the 8 x 8 update (Newton polar
+iteration, Jacobi SVD for ill-conditioned environments) is unitary to 1e-12
+and attains the nuclear norm to 1e-12 relative."""
 import numpy as np
 import pytest
 
@@ -70,6 +71,39 @@ def test_optimize_gate3_vs_oracle(qf):
     got = host(qf.optimize_gate3(dev(Z), dev(U0[:2]), 0.0))
     np.testing.assert_array_equal(got[0], U0[0])
     assert np.all(np.isnan(got[1]))
+
+
+def test_optimize_gate3_condition_sweep(qf):
+    """The 8 x 8 update for environments whose condition number sweeps 1 ..
+    1e7 (|M|_F^2 |M^-1|_F^2 from 64 to beyond 1e14), across the point where
+    the update hands over from the Newton polar iteration (< 1e8) to the
+    Jacobi SVD: unitary to 1e-12, the polar factor to the condition-number
+    bound of the LAPACK comparison, the attained value the nuclear norm, on
+    both sides alike."""
+    rng = np.random.default_rng(3300)
+    envs = []
+    for k in range(64):
+        lo = -7.0 * k / 63.0  # smallest singular value 1 .. 1e-7
+        s = np.sort(10.0 ** rng.uniform(lo, 0.0, 8))[::-1]
+        s[0], s[-1] = 1.0, 10.0 ** lo
+        E = I.haar_unitary(rng, 8) @ np.diag(s) @ I.haar_unitary(rng, 8)
+        envs.append(E * 10.0 ** rng.uniform(-3, 3))
+    E = np.stack(envs)
+    U0 = np.stack([I.haar_unitary(rng, 8) for _ in range(64)])
+    got = host(qf.optimize_gate3(dev(E), dev(U0), 0.0))
+    c2 = []
+    for k in range(64):
+        ref = O.optimize_gate(E[k], U0[k], 0.0)
+        assert np.abs(got[k].conj().T @ got[k] - np.eye(8)).max() < 1e-12, k
+        sv = np.linalg.svd(E[k], compute_uv=False)
+        kappa = sv[0] / sv[-1]
+        c2.append(np.sum(sv ** 2) * np.sum(sv ** -2.0))
+        assert np.abs(got[k] - ref).max() < max(1e-12, 1e-14 * kappa) * 10, (k, kappa)
+        Mn = E[k] / np.abs(E[k]).max()
+        svn = np.linalg.svd(Mn, compute_uv=False)
+        assert abs(np.real(np.trace(Mn @ got[k])) - svn.sum()) <= 1e-12 * svn.sum(), k
+    c2 = np.asarray(c2)
+    assert (c2 < 1e7).sum() >= 10 and (c2 > 1e9).sum() >= 10  # both forms ran
 
 
 @pytest.mark.parametrize("n,layers,S,sweeps", [(5, 4, 2, 3), (7, 4, 2, 2)])
