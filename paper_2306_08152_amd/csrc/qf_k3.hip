@@ -376,29 +376,54 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
-// Newton form of the 8 x 8 nearest-unitary step: the scaled Newton polar
-// iteration of the hex form (Higham 1986; X <- (z X + X^{-dagger} / z) / 2,
-// z = (|X^-1|_F / |X|_F)^(1/2)), with X^-1 from Gauss-Jordan elimination with
-// partial pivoting on [X | I] across the wavefront: in step k the pivot row
-// p_k is the unused row of largest |X[r][k]|, every other row (used or not)
-// loses its column-k component, and no rows are swapped, so X^-1[k][c] is
-// entry (p_k, c) of the right half.  dist = |X|_F^2 + |X^-1|_F^2 - 16, the
-// sum of (s - 1/s)^2 over the singular values: scaled steps while dist >
-// 1e-2, and the step taken at dist <= 4e-14 is the last (every |s - 1| is
-// below 1e-7 there, about 5e-15 after the step).  The pivoted elimination is
-// accurate to about the condition number times the unit roundoff; the form
-// is taken for |M|_F^2 |M^-1|_F^2 < 1e8 and otherwise (or if 12 steps have
-// not converged, or a pivot vanishes) returns false for the Jacobi form.
-// All decisions are on wave-uniform values.  x: entry (r, c) of M (entries at
-// most 1 in magnitude), lane r + 8c; q: entry (r, c) of the polar factor.
+// Newton form of the 8 x 8 nearest-unitary step: the unitary polar factor Q
+// of M (M = Q H) by the scaled Newton iteration of the hex form (Higham 1986;
+// X <- (z X + X^{-dagger} / z) / 2, z = (|X^-1|_F / |X|_F)^(1/2)) while X is
+// far from unitary, and by the Newton-Schulz iteration X <- X (3 I - X^dagger
+// X) / 2 once |X^dagger X - I|_F < 1/2 (Higham's hybrid; there every singular
+// value s has |s^2 - 1| < 1/2, and the step maps s^2 - 1 = d to (d^3 - 3 d^2)
+// / 4, quadratic convergence with two matrix products and no inverse).  X
+// starts at M scaled to |X|_F^2 = 8.  Newton steps take X^-1 from
+// Gauss-Jordan elimination with partial pivoting on [X | I] across the
+// wavefront: in step k the pivot row p_k is the unused row of largest
+// |X[r][k]|, every other row (used or not) loses its column-k component, and
+// no rows are swapped, so X^-1[k][c] is entry (p_k, c) of the right half.
+// The Newton-Schulz step taken at |X^dagger X - I|_F <= 1e-8 is the last
+// (after it every |s - 1| is near 1e-16).  The first Newton step checks
+// |M|_F^2 |M^-1|_F^2 < 1e8 (the pivoted elimination is accurate to about the
+// condition number times the unit roundoff); an ill-conditioned M, a
+// vanishing pivot or 16 steps without convergence return false for the
+// Jacobi form.  All decisions are on wave-uniform values.  x: entry (r, c)
+// of M (entries at most 1 in magnitude), lane r + 8c; q: entry (r, c) of Q.
 constexpr double kPolar8Cond2 = 1e8;
-constexpr double kPolar8ScaleAbove = 1e-2;
-constexpr double kPolar8Done = 4e-14;
-constexpr int kPolar8MaxSteps = 12;
+constexpr double kPolar8SchulzBelow = 0.25;  // |X^dagger X - I|_F^2
+constexpr double kPolar8Done = 1e-16;        // |X^dagger X - I|_F^2 of the last step
+constexpr int kPolar8MaxSteps = 16;
 
 __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
   const int grp = 8 * c;  // first lane of this lane's column group
+  x = scale(x, rsqrt_nr(oct_wavesum(nrm2x(x)) * 0.125));
+  bool checked = false;
   for (int step = 0; step < kPolar8MaxSteps; ++step) {
+    // G = X^dagger X: G[r][c] = sum_k conj(X[k][r]) X[k][c]
+    cd g = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cmac(g, conj(shfl_cd(x, k + 8 * r)), shfl_cd(x, grp + k));
+    const double off = nrm2x(mk(g.re - (r == c ? 1.0 : 0.0), g.im));
+    const double g2 = oct_wavesum(off);
+    if (g2 < kPolar8SchulzBelow) {
+      // X <- X H, H = (3 I - G) / 2: entry (r, c) = sum_k X[r][k] H[k][c]
+      const cd h = mk((r == c ? 1.5 : 0.0) - 0.5 * g.re, -0.5 * g.im);
+      cd y = mk(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cmac(y, shfl_cd(x, r + 8 * k), shfl_cd(h, grp + k));
+      x = y;
+      if (g2 <= kPolar8Done) {
+        q = x;
+        return true;
+      }
+      continue;
+    }
     cd a = x, b = mk(r == c ? 1.0 : 0.0, 0.0);
     int piv[8];
     unsigned used = 0;
@@ -442,20 +467,14 @@ __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
     const cd xi = conj(shfl_cd(b, pc + 8 * r));  // X^{-dagger}[r][c] = conj(X^-1[c][r])
     const double nx = oct_wavesum(nrm2x(x));
     const double nxi = oct_wavesum(nrm2x(b));
-    if (step == 0 && !(nx * nxi < kPolar8Cond2)) return false;
-    const double dist = (nx + nxi) - 16.0;
-    double z = 1.0, zi = 1.0;
-    if (dist > kPolar8ScaleAbove) {
-      const double t = __builtin_amdgcn_rsq(nxi * __builtin_amdgcn_rcp(nx));
-      z = __builtin_amdgcn_rsq(t);
-      zi = t * z;
-    }
+    if (!checked && !(nx * nxi < kPolar8Cond2)) return false;
+    checked = true;
+    // z = (nxi / nx)^(1/4) and 1 / z from hardware estimates (any positive
+    // scaling keeps the limit)
+    const double t = __builtin_amdgcn_rsq(nxi * __builtin_amdgcn_rcp(nx));
+    const double z = __builtin_amdgcn_rsq(t), zi = t * z;
     const double hz = 0.5 * z, hzi = 0.5 * zi;
     x = mk(fma(hz, x.re, hzi * xi.re), fma(hz, x.im, hzi * xi.im));
-    if (dist <= kPolar8Done) {
-      q = x;
-      return true;
-    }
   }
   return false;
 }
