@@ -395,28 +395,42 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // vanishing pivot or 16 steps without convergence return false for the
 // Jacobi form.  All decisions are on wave-uniform values.  x: entry (r, c)
 // of M (entries at most 1 in magnitude), lane r + 8c; q: entry (r, c) of Q.
+// xs: 128 entries of LDS owned by this wavefront, through which the lanes
+// exchange entries (each lane stores its own at its lane index and loads
+// the ones it needs, one 16-byte load per entry instead of four lane
+// permutes).  Only this wavefront touches xs, and a wavefront's LDS
+// instructions execute in issue order, so loads issued after the stores see
+// them and the next stores cannot overtake them; the wave barriers keep the
+// compiler from moving the accesses across.
 constexpr double kPolar8Cond2 = 1e8;
 constexpr double kPolar8SchulzBelow = 0.25;  // |X^dagger X - I|_F^2
 constexpr double kPolar8Done = 1e-16;        // |X^dagger X - I|_F^2 of the last step
 constexpr int kPolar8MaxSteps = 16;
 
-__device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
+__device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q, cd* xs) {
   const int grp = 8 * c;  // first lane of this lane's column group
+  const int t = r + 8 * c;
+  cd* bs = xs + 64;
   x = scale(x, rsqrt_nr(oct_wavesum(nrm2x(x)) * 0.125));
   bool checked = false;
   for (int step = 0; step < kPolar8MaxSteps; ++step) {
     // G = X^dagger X: G[r][c] = sum_k conj(X[k][r]) X[k][c]
+    __builtin_amdgcn_wave_barrier();
+    xs[t] = x;
+    __builtin_amdgcn_wave_barrier();
     cd g = mk(0.0, 0.0);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) cmac(g, conj(shfl_cd(x, k + 8 * r)), shfl_cd(x, grp + k));
+    for (int k = 0; k < 8; ++k) cmac(g, conj(xs[k + 8 * r]), xs[grp + k]);
     const double off = nrm2x(mk(g.re - (r == c ? 1.0 : 0.0), g.im));
     const double g2 = oct_wavesum(off);
     if (g2 < kPolar8SchulzBelow) {
       // X <- X H, H = (3 I - G) / 2: entry (r, c) = sum_k X[r][k] H[k][c]
       const cd h = mk((r == c ? 1.5 : 0.0) - 0.5 * g.re, -0.5 * g.im);
+      bs[t] = h;
+      __builtin_amdgcn_wave_barrier();
       cd y = mk(0.0, 0.0);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) cmac(y, shfl_cd(x, r + 8 * k), shfl_cd(h, grp + k));
+      for (int k = 0; k < 8; ++k) cmac(y, xs[r + 8 * k], bs[grp + k]);
       x = y;
       if (g2 <= kPolar8Done) {
         q = x;
@@ -430,7 +444,11 @@ __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const cd col = shfl_cd(a, r + 8 * k);  // entry (r, k) of the left half
+      __builtin_amdgcn_wave_barrier();
+      xs[t] = a;
+      bs[t] = b;
+      __builtin_amdgcn_wave_barrier();
+      const cd col = xs[r + 8 * k];  // entry (r, k) of the left half
       const double mag = ((used >> r) & 1u) ? -1.0 : nrm2x(col);
       // the largest over the eight rows (every group holds the same column),
       // then the lowest row that attains it, from group 0's ballot bits
@@ -451,8 +469,8 @@ __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
       }
       const double ip = rcp_nr(pv2);
       const cd inv = mk(pv.re * ip, -(pv.im * ip));  // 1 / pv
-      const cd pa = mulx(shfl_cd(a, grp + p), inv);
-      const cd pb = mulx(shfl_cd(b, grp + p), inv);
+      const cd pa = mulx(xs[grp + p], inv);
+      const cd pb = mulx(bs[grp + p], inv);
       const bool prow = r == p;
       const cd ua = a - mulx(col, pa), ub = b - mulx(col, pb);
       a = sel(prow, pa, ua);
@@ -464,7 +482,10 @@ __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
     int pc = piv[0];  // pivot row of column c
 #pragma unroll
     for (int j = 1; j < 8; ++j) pc = (c == j) ? piv[j] : pc;
-    const cd xi = conj(shfl_cd(b, pc + 8 * r));  // X^{-dagger}[r][c] = conj(X^-1[c][r])
+    __builtin_amdgcn_wave_barrier();
+    bs[t] = b;
+    __builtin_amdgcn_wave_barrier();
+    const cd xi = conj(bs[pc + 8 * r]);  // X^{-dagger}[r][c] = conj(X^-1[c][r])
     const double nx = oct_wavesum(nrm2x(x));
     const double nxi = oct_wavesum(nrm2x(b));
     if (!checked && !(nx * nxi < kPolar8Cond2)) return false;
@@ -486,7 +507,7 @@ __device__ inline bool polar_newton_oct(cd x, int r, int c, cd& q) {
 // it declines.  y_io / warm: the warm start of the hex form's Jacobi step
 // (entry (r, c) of the gate's previous rotation in, the new one out; the
 // identity after a Newton update and after a zero or non-finite M).
-__device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew, cd* y_io = nullptr,
+__device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& unew, cd* xs, cd* y_io = nullptr,
                                               bool warm = false) {
   const double amax = oct_wavemax(fmax(fabs(m.re), fabs(m.im)));
   const double bad = oct_wavemax((finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0);
@@ -504,7 +525,7 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
   cd y = mk(c == r ? 1.0 : 0.0, 0.0);
   {
     cd q;
-    if (polar_newton_oct(m, r, c, q)) {
+    if (polar_newton_oct(m, r, c, q, xs)) {
       if (y_io) *y_io = y;
       unew = conj(shfl_cd(q, c + 8 * r));  // u_new[r][c] = conj(Q[c][r])
       return 0;
@@ -582,9 +603,9 @@ __device__ inline int nearest_unitary_f64_oct(cd& m, cd keep, int r, int c, cd& 
 // Lane (r, c) passes E[r][c], u_old[c][r], u_old[r][c]; receives u_new[r][c]
 // for M = (1 - beta) E + beta u_old^dagger (Eq. opt_u; beta of Sec. III-A-2).
 __device__ inline void optimize_gate_f64_oct(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew,
-                                             cd* y_io = nullptr, bool warm = false) {
+                                             cd* xs, cd* y_io = nullptr, bool warm = false) {
   cd m = axpbyx(e, 1.0 - beta, conj(uold_cr), beta);
-  nearest_unitary_f64_oct(m, uold_rc, r, c, unew, y_io, warm);
+  nearest_unitary_f64_oct(m, uold_rc, r, c, unew, xs, y_io, warm);
 }
 
 // ------------------------------------------------------------------ k_env8
@@ -657,7 +678,8 @@ __global__ __launch_bounds__(kEnv8Threads) void k_env8(const cx<R>* __restrict__
   }
   const cd urc = U[8 * r + c];
   cd un = urc;
-  if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un, yw ? &yv : nullptr, a.warm != 0);
+  // the reduction buffer is free now: the update's lane exchanges use it
+  if (!frz) optimize_gate_f64_oct(e, U[8 * c + r], urc, r, c, a.beta, un, red, yw ? &yv : nullptr, a.warm != 0);
   if (yw) yw[t] = yv;
   reinterpret_cast<cd*>(a.uold)[64 * (size_t)s + rc] = urc;
   reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 64 * (int64_t)a.gidx + rc] = un;
@@ -681,8 +703,9 @@ __global__ __launch_bounds__(64) void k_optimize8(const cd* __restrict__ env, co
   const size_t s = blockIdx.x;
   const int t = (int)threadIdx.x, r = t & 7, c = t >> 3;
   const cd* u = uold + 64 * s;
+  __shared__ cd xs[128];
   cd un;
-  optimize_gate_f64_oct(env[64 * s + 8 * r + c], u[8 * c + r], u[8 * r + c], r, c, beta, un);
+  optimize_gate_f64_oct(env[64 * s + 8 * r + c], u[8 * c + r], u[8 * r + c], r, c, beta, un, xs);
   unew[64 * s + 8 * r + c] = un;
 }
 
