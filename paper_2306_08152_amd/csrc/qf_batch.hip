@@ -279,7 +279,8 @@ __global__ __launch_bounds__(SLOTS* kBLanes) void k_batch(BatchDev d) {
             cd* yp = jb.y + 32 * g + 16 * half + 4 * r + c;
             cd yv = *yp;
             const bool warm = ((it - 1) % kWarmPeriod) != 0;
-            if (!frozen) optimize_gate_f64_hex(e, U[4 * c + r], urc, r, c, o.beta, un, &yv, warm);
+            // the update's lane exchange overwrites P, which every lane has read
+            if (!frozen) optimize_gate_f64_hex(e, U[4 * c + r], urc, r, c, o.beta, un, PUs[h], &yv, warm);
             *yp = yv;
             PUs[h][4 * r + c] = un;
             jb.g[16 * g + 4 * r + c] = un;

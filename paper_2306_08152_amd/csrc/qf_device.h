@@ -472,19 +472,29 @@ constexpr double kPolarScaleAbove = 1e-2;
 constexpr double kPolarDone = 1e-14;
 constexpr int kPolarMaxSteps = 10;
 
-// x: this lane's entry (r, c) of M, entries at most 1 in magnitude; base:
-// the group's first lane.  On success q is entry (r, c) of Q.
-__device__ inline bool polar_newton_hex(cd x, int r, int c, int base, cd& q) {
-  int src[9];  // lanes of the minor's entries, rows and columns ascending
+// x: this lane's entry (r, c) of M, entries at most 1 in magnitude.  On
+// success q is entry (r, c) of Q.  xch: 16 entries of LDS owned by this hex
+// group during the call, through which its lanes exchange entries (each lane
+// stores its own at index hex_lane(r, c) and loads the nine of its minor, one
+// 16-byte load each instead of four lane permutes).  The 16 lanes are one
+// wavefront's, whose LDS instructions execute in issue order: loads issued
+// after the stores see them, and the next stores cannot overtake them; the
+// wave barriers keep the compiler from moving the accesses across.
+__device__ inline bool polar_newton_hex(cd x, int r, int c, cd& q, cd* xch) {
+  int src[9];  // indices of the minor's entries, rows and columns ascending
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) src[3 * i + j] = base + hex_lane(i + (i >= r ? 1 : 0), j + (j >= c ? 1 : 0));
+    for (int j = 0; j < 3; ++j) src[3 * i + j] = hex_lane(i + (i >= r ? 1 : 0), j + (j >= c ? 1 : 0));
+  const int own = hex_lane(r, c);
   const double sgn = ((r + c) & 1) ? -1.0 : 1.0;
   for (int step = 0; step < kPolarMaxSteps; ++step) {
+    __builtin_amdgcn_wave_barrier();
+    xch[own] = x;
+    __builtin_amdgcn_wave_barrier();
     cd a[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = mk(__shfl(x.re, src[k], 64), __shfl(x.im, src[k], 64));
+    for (int k = 0; k < 9; ++k) a[k] = xch[src[k]];
     const cd m0 = mulx(a[4], a[8]) - mulx(a[5], a[7]);
     const cd m1 = mulx(a[3], a[8]) - mulx(a[5], a[6]);
     const cd m2 = mulx(a[3], a[7]) - mulx(a[4], a[6]);
@@ -518,7 +528,8 @@ __device__ inline bool polar_newton_hex(cd x, int r, int c, int base, cd& q) {
 }
 
 // m: this lane's entry (r, c) of M (overwritten); keep: entry (r, c) of the
-// result for a zero M; unew: entry (r, c) of the maximiser of Re Tr(M u).
+// result for a zero M; unew: entry (r, c) of the maximiser of Re Tr(M u);
+// xch: the hex group's 16 LDS entries for the Newton form (overwritten).
 // The Newton form above runs first; where it declines, a one-sided Jacobi
 // step in the hex layout takes over, with the same results and return
 // codes as nearest_unitary_f64_quad when y_io is null.
@@ -535,7 +546,7 @@ __device__ inline bool polar_newton_hex(cd x, int r, int c, int base, cd& q) {
 // rotations stays at a few ulps.
 constexpr int kWarmPeriod = 16;  // a gate's updates start cold once in this many sweeps
 
-__device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& unew, cd* y_io = nullptr,
+__device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& unew, cd* xch, cd* y_io = nullptr,
                                               bool warm = false) {
   double amax = fmax(fabs(m.re), fabs(m.im));
   double bad = (finite_d(m.re) && finite_d(m.im)) ? 0.0 : 1.0;
@@ -557,7 +568,7 @@ __device__ inline int nearest_unitary_f64_hex(cd& m, cd keep, int r, int c, cd& 
   const int base = (int)(__lane_id() & ~15u);
   {
     cd q;
-    if (polar_newton_hex(m, r, c, base, q)) {
+    if (polar_newton_hex(m, r, c, q, xch)) {
       if (y_io) *y_io = y;
       // u_new[r][c] = conj(Q[c][r])
       const int src = base + hex_lane(c, r);
@@ -658,10 +669,10 @@ __device__ __forceinline__ cd env_entry(const cd* P, const cd* uold, int half, i
 // u_new[r][c]; the quad form's result up to round-off (bitwise where the
 // Newton form declines and y_io is null).
 __device__ inline void optimize_gate_f64_hex(cd e, cd uold_cr, cd uold_rc, int r, int c, double beta, cd& unew,
-                                             cd* y_io = nullptr, bool warm = false) {
+                                             cd* xch, cd* y_io = nullptr, bool warm = false) {
   const double we = 1.0 - beta;  // exact 1 for beta = 0
   cd m = axpbyx(e, we, conj(uold_cr), beta);
-  nearest_unitary_f64_hex(m, uold_rc, r, c, unew, y_io, warm);
+  nearest_unitary_f64_hex(m, uold_rc, r, c, unew, xch, y_io, warm);
 }
 
 // ---------------------------------------------------------------- gate kinds

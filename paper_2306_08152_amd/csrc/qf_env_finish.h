@@ -79,7 +79,7 @@ __device__ inline void env_finish_quad(const EnvDev& d, uint32_t s, const cd* P,
 // (bitwise the quad form's result) where that declines.
 // y_sh: the warm-start rotation (row-major, LDS) when a.ywarm is set,
 // fetched at kernel start by ywarm_fetch.
-__device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
+__device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, cd* P, const cd* u_sh, bool frozen,
                                       int i, cd* un_sh = nullptr, const cd* y_sh = nullptr) {
   const EnvArgs& a = d.a;
   const int r = hex_row(i), c = i & 3;
@@ -90,7 +90,8 @@ __device__ inline void env_finish_hex(const EnvDev& d, uint32_t s, const cd* P, 
   cd* yp = a.ywarm ? reinterpret_cast<cd*>(a.ywarm) + a.ywstride * (size_t)s + 32 * a.gidx + 16 * a.half + 4 * r + c
                    : nullptr;
   cd yv = y_sh ? y_sh[4 * r + c] : (yp ? *yp : mk(0.0, 0.0));
-  if (!frozen) optimize_gate_f64_hex(e, u_sh[4 * c + r], urc, r, c, a.beta, unew, yp ? &yv : nullptr, a.warm != 0);
+  // every lane has read P (env_entry) before the update's lane exchange overwrites it
+  if (!frozen) optimize_gate_f64_hex(e, u_sh[4 * c + r], urc, r, c, a.beta, unew, P, yp ? &yv : nullptr, a.warm != 0);
   if (yp) *yp = yv;
   reinterpret_cast<cd*>(a.uold)[a.uold_stride * (size_t)s + 4 * r + c] = urc;
   reinterpret_cast<cd*>(a.gates)[(int64_t)s * a.gstride + 16 * (int64_t)a.gidx + 4 * r + c] = unew;
@@ -105,7 +106,7 @@ __device__ __forceinline__ void ywarm_fetch(const EnvArgs& a, uint32_t s, uint32
 }
 
 // The finishing step of one start by the lanes it needs.
-__device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, const cd* P, const cd* u_sh, bool frozen,
+__device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, cd* P, const cd* u_sh, bool frozen,
                                           uint32_t t, cd* un_sh = nullptr, const cd* y_sh = nullptr) {
   if (d.a.do_update && d.a.kind == kKindU4) {
     if (t < 16) env_finish_hex(d, s, P, u_sh, frozen, (int)t, un_sh, d.a.ywarm ? y_sh : nullptr);

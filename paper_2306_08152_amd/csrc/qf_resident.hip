@@ -263,7 +263,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident(ResidentArgs a) {
           // warm start from this gate's rotation of the previous sweep
           cd* yp = reinterpret_cast<cd*>(a.ywarm) + ((size_t)s * a.p + g) * 32 + 16 * half + 4 * r + c;
           cd yv = *yp;
-          if (!frozen) optimize_gate_f64_hex(e, ucr, urc, r, c, o.beta, unew, &yv, ((i - 1) % kWarmPeriod) != 0);
+          // the partial trace is read (env_entry) before the update's lane exchange overwrites it
+          if (!frozen)
+            optimize_gate_f64_hex(e, ucr, urc, r, c, o.beta, unew, L.red, &yv, ((i - 1) % kWarmPeriod) != 0);
           *yp = yv;
           gates[16 * g + 4 * r + c] = unew;
           const cd udc = conj(ucr);  // (u_old^dagger)[r][c]

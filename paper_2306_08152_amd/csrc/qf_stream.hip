@@ -864,8 +864,10 @@ __global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict
   if (s >= count) return;  // whole hexes leave together
   const int r = hex_row(i), c = i & 3;
   const cd* u = uold + 16 * (size_t)s;
+  __shared__ cd xch[64];  // 16 entries per hex of the block
   cd un;
-  optimize_gate_f64_hex(env[16 * (size_t)s + 4 * r + c], u[4 * c + r], u[4 * r + c], r, c, beta, un);
+  optimize_gate_f64_hex(env[16 * (size_t)s + 4 * r + c], u[4 * c + r], u[4 * r + c], r, c, beta, un,
+                        xch + 16 * (threadIdx.x >> 4));
   unew[16 * (size_t)s + 4 * r + c] = un;
 }
 
