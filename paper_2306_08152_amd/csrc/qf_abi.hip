@@ -22,8 +22,10 @@ constexpr int kMaxGroups = 4;
 // Default stream groups of the three-qubit sweep: one.  Two to four
 // staggered groups were measured at n = 10, 8 starts and gave no overlap
 // (complex64 62.5 us per gate update with one group, 64.6-65.7 with more;
-// complex128 89.6-91.6 either way): every pass fills all CUs, so another
-// group's environment step cannot run beside it.
+// complex128 89.6-91.6 either way; with the Newton form of the 8 x 8 update,
+// steady state, complex64 41.6 against 44.7-46.6, complex128 60.8 against
+// 60.8-63.5): every pass fills all CUs, so another group's environment step
+// cannot run beside it.
 constexpr int kDefaultGroups3 = 1;
 
 struct qf_ctx {
