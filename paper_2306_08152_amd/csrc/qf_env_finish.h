@@ -105,7 +105,9 @@ __device__ __forceinline__ void ywarm_fetch(const EnvArgs& a, uint32_t s, uint32
     y_sh[k] = reinterpret_cast<const cd*>(a.ywarm)[a.ywstride * (size_t)s + 32 * a.gidx + 16 * a.half + k];
 }
 
-// The finishing step of one start by the lanes it needs.
+// The finishing step of one start by the lanes it needs.  P (LDS) is read
+// first and then serves the general update's lane exchange, so it is
+// overwritten.
 __device__ __forceinline__ void env_finish(const EnvDev& d, uint32_t s, cd* P, const cd* u_sh, bool frozen,
                                           uint32_t t, cd* un_sh = nullptr, const cd* y_sh = nullptr) {
   if (d.a.do_update && d.a.kind == kKindU4) {

@@ -700,10 +700,10 @@ hipError_t launch_env8(hipStream_t st, int precision, const void* X, const Pass8
 // One wavefront per environment, lane r + 8c = entry (r, c).
 __global__ __launch_bounds__(64) void k_optimize8(const cd* __restrict__ env, const cd* __restrict__ uold, double beta,
                                                   cd* __restrict__ unew) {
+  __shared__ cd xs[128];  // the update's lane exchange
   const size_t s = blockIdx.x;
   const int t = (int)threadIdx.x, r = t & 7, c = t >> 3;
   const cd* u = uold + 64 * s;
-  __shared__ cd xs[128];
   cd un;
   optimize_gate_f64_oct(env[64 * s + 8 * r + c], u[8 * c + r], u[8 * r + c], r, c, beta, un, xs);
   unew[64 * s + 8 * r + c] = un;

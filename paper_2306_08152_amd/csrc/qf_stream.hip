@@ -859,12 +859,12 @@ hipError_t launch_cost(hipStream_t st, int precision, const void* X, int n, int 
 __global__ __launch_bounds__(64) void k_optimize(int count, const cd* __restrict__ env,
                                                  const cd* __restrict__ uold, double beta,
                                                  cd* __restrict__ unew) {
+  __shared__ cd xch[64];  // the update's lane exchange, 16 entries per hex of the block
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = gt >> 4, i = gt & 15;
   if (s >= count) return;  // whole hexes leave together
   const int r = hex_row(i), c = i & 3;
   const cd* u = uold + 16 * (size_t)s;
-  __shared__ cd xch[64];  // 16 entries per hex of the block
   cd un;
   optimize_gate_f64_hex(env[16 * (size_t)s + 4 * r + c], u[4 * c + r], u[4 * r + c], r, c, beta, un,
                         xch + 16 * (threadIdx.x >> 4));
