@@ -228,9 +228,13 @@ struct Unit16T<double> {
 // workgroup walks tiles wg, wg + n_wg, ... < total; a tile's 16-byte units
 // are loaded in address order (8 per thread) and scattered into the LDS
 // image, the next tile's loads go out, P::run applies the products on the
-// image, and the units are gathered and stored in address order.  P::prep(s)
-// runs before the barrier that publishes the image (the operands of start s
-// into LDS).
+// image, and the units are gathered and stored in address order.  P::init
+// runs once before the first tile's loads (the two-gate pass stages its
+// operands in LDS there); P::prep(s) runs before the barrier that publishes
+// the image (the three-qubit pass's operands of start s into LDS).  Nothing
+// between the next tile's loads and its scatter waits on a global load:
+// vector memory loads and stores share one counter, so such a wait would
+// also wait for the next tile's loads in flight.
 template <typename R, int M, typename P>
 __device__ __forceinline__ void tile_loop(cx<R>* __restrict__ X, const Pair2Geom& g, uint32_t total, uint32_t wg,
                                           uint32_t n_wg, cx<R>* tile, P& prod) {
@@ -270,6 +274,7 @@ __device__ __forceinline__ void tile_loop(cx<R>* __restrict__ X, const Pair2Geom
 
   uint32_t tl = wg;
   if (tl >= total) return;
+  prod.init(wg, n_wg, total);
   uint32_t s;
   size_t origin;
   tile_origin(tl, s, origin);
@@ -326,21 +331,38 @@ __device__ __forceinline__ void tile_loop(cx<R>* __restrict__ X, const Pair2Geom
 // Two-gate products.  ops: per start the four 4x4 operands A_F, B_F, A_S,
 // B_S in the builder precision (64 entries, written by k_env2):
 // x <- A_S A_F x B_F B_S.
+constexpr uint32_t kPass2OpSlots = 8;  // tiles per workgroup whose operands are staged in LDS
 template <typename R, int M>
 struct Pair2Products {
   cx<R>* tile;
   const Pair2Geom& g;
   const cx<R>* __restrict__ ops;
+  cx<R>* opl;     // complex64: kPass2OpSlots x 64 operand entries in LDS, one slot per tile of the workgroup
+  uint32_t slot;  // slot of the current tile
+  // complex64: the operands of every tile this workgroup walks, staged in LDS
+  // at the start (their loads go out with the first tile's), so that the
+  // products read LDS and wait on no global load, which would also wait for
+  // the next tile's loads in flight
+  __device__ __forceinline__ void init(uint32_t wg, uint32_t n_wg, uint32_t total) {
+    if constexpr (sizeof(R) == 4) {
+      for (uint32_t q = threadIdx.x; q < kPass2OpSlots * 64; q += 256) {
+        const uint32_t tl = wg + (q >> 6) * n_wg;
+        if (tl < total) opl[q] = ops[(size_t)(tl / g.tiles_per_start) * 64 + (q & 63u)];
+      }
+    }
+  }
   __device__ __forceinline__ void prep(uint32_t) {}
   __device__ __forceinline__ void run(uint32_t s) {
     using C = Pair2Cfg<R, M>;
     const uint32_t t = threadIdx.x;
-    const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
     if constexpr (sizeof(R) == 4) {
+      const cx<R>* op = opl + 64 * slot;
+      ++slot;
       pair2_phase_mfma<M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
       __syncthreads();
       pair2_phase_mfma<M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
     } else {
+      const cx<R>* op = ops + (size_t)__builtin_amdgcn_readfirstlane(s) * 64;
       if (t < C::kActive) pair2_phase<R, M>(tile, g, g.f_idx, g.o_f, op, op + 16, t);
       __syncthreads();
       if (t < C::kActive) pair2_phase<R, M>(tile, g, g.s_idx, g.o_s, op + 32, op + 48, t);
@@ -352,7 +374,8 @@ template <typename R, int M>
 __global__ __launch_bounds__(256, 4) void k_pass2(cx<R>* __restrict__ X, Pair2Geom g, uint32_t total,
                                                   const cx<R>* __restrict__ ops) {
   __shared__ cx<R> tile[Pair2Cfg<R, M>::kLds];
-  Pair2Products<R, M> prod{tile, g, ops};
+  __shared__ cx<R> opl[sizeof(R) == 4 ? kPass2OpSlots * 64 : 1];
+  Pair2Products<R, M> prod{tile, g, ops, opl, 0u};
   tile_loop<R, M>(X, g, total, blockIdx.x, gridDim.x, tile, prod);
 }
 
@@ -368,6 +391,7 @@ static hipError_t launch_pass2_t(hipStream_t st, void* X, int S, const Pair2Geom
   if (g.wlog != Pair2Cfg<R, M>::kWlog || g.m != (uint32_t)M) return hipErrorInvalidValue;
   const uint32_t total = (uint32_t)S * g.tiles_per_start;
   const uint32_t tpw = g.tiles_per_wg ? g.tiles_per_wg : kPass2TilesPerWG;
+  if (sizeof(R) == 4 && tpw > kPass2OpSlots) return hipErrorInvalidValue;
   const uint32_t grid = (total + tpw - 1) / tpw;
   return launch_k(k_pass2<R, M>, dim3(grid), dim3(256), 0u, st, ev, reinterpret_cast<cx<R>*>(X), g, total,
                   reinterpret_cast<const cx<R>*>(ops));
@@ -471,6 +495,7 @@ struct Pass3Products {
   const Pair2Geom& g;
   Operand A, B;
   uint32_t s_have;
+  __device__ __forceinline__ void init(uint32_t, uint32_t, uint32_t) {}
   // operands of start s in variant order, once per start
   __device__ __forceinline__ void prep(uint32_t s) {
     if (s == s_have) return;
