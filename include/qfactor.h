@@ -327,6 +327,14 @@ int qf_instantiate_noalloc(qf_ctx* ctx, int n, const void* target, int n_gates, 
  * Returns QF_EINVAL for other values. */
 int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile);
 
+/* Tiles each workgroup of the two-gate pass walks (two consecutive gate
+ * updates of Alg. 1 in one builder pass) for builders of n qubits in
+ * `precision`: 1, 2, 4 or 8 (the next tile's loads in flight under the
+ * current tile's products), or 0 = forget the choice (the next
+ * qf_instantiate times the candidates again).  Every value gives bitwise the
+ * same builder.  Returns QF_EINVAL for other values or n outside [4, 16]. */
+int qf_set_pass2_tiles(qf_ctx* ctx, int precision, int n, int tiles);
+
 /* Three-qubit gates (Sec. III: the environment and the update of Eq. opt_u
  * hold for gates of any size; the k = 3 gate-set variant of Sec. III-A-3).
  * qf_instantiate for a circuit whose every gate is an 8 x 8 unitary on three

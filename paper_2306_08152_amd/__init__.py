@@ -16,7 +16,7 @@ from .hipbuild import build as build_library, lib_path  # noqa: F401
 _API = ("build", "apply_gate", "environment", "optimize_gate", "update_gate", "cost", "instantiate",
         "default_options", "workspace_size", "Result", "instantiate_batch", "pack_batch",
         "batch_workspace_size", "BatchResult", "gradient", "cost_fn", "su4_gates", "su4_vjp", "su4",
-        "lbfgs", "lbfgs_options", "LbfgsResult", "set_pass_tile", "set_batch_config", "delete_gates", "DeletionResult",
+        "lbfgs", "lbfgs_options", "LbfgsResult", "set_pass_tile", "set_pass2_tiles", "set_batch_config", "delete_gates", "DeletionResult",
         "instantiate3", "optimize_gate3", "cost_of_gates")
 
 

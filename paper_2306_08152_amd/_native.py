@@ -20,7 +20,7 @@ EXPORTED = [
     "qf_update_gate", "qf_cost", "qf_instantiate", "qf_batch_workspace_size", "qf_instantiate_batch",
     "qf_gradient_workspace_size", "qf_gradient", "qf_su4_gates", "qf_su4_vjp", "qf_lbfgs_options_default",
     "qf_lbfgs_workspace_size", "qf_lbfgs", "qf_set_pass_tile", "qf_delete_gates_workspace_size", "qf_delete_gates",
-    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3", "qf_instantiate_noalloc", "qf_set_batch_config",
+    "qf_workspace_size3", "qf_instantiate3", "qf_optimize_gate3", "qf_instantiate_noalloc", "qf_set_batch_config", "qf_set_pass2_tiles",
 ]
 QF_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
@@ -149,6 +149,7 @@ _SIGS = {
     "qf_lbfgs_options_default": (None, [ctypes.POINTER(QfLbfgsOptions)]),
     "qf_set_pass_tile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "qf_set_batch_config": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "qf_set_pass2_tiles": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "qf_delete_gates_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(QfOptions)]),
     "qf_delete_gates": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _I32P, _VP, _VP, ctypes.c_int,

@@ -84,6 +84,13 @@ def set_pass_tile(device, precision: int, n: int, gate_class: int, tile: int) ->
     nat.check(nat.load().qf_set_pass_tile(ctx, precision, n, gate_class, tile), ctx)
 
 
+def set_pass2_tiles(device, precision: int, n: int, tiles: int) -> None:
+    """Fix the tiles per workgroup of the two-gate pass for (precision, n):
+    1, 2, 4 or 8; 0 = tune again (qf_set_pass2_tiles)."""
+    ctx = _ctx(device)
+    nat.check(nat.load().qf_set_pass2_tiles(ctx, precision, n, tiles), ctx)
+
+
 def set_batch_config(device, n_starts: int, slots: int, wg_per_cu: int = 1) -> None:
     """Fix the batched launch's shape for n_starts starts per block: slots
     (8 or 16) instantiations per workgroup, wg_per_cu workgroups per CU;

@@ -1280,6 +1280,16 @@ int qf_set_pass_tile(qf_ctx* ctx, int precision, int n, int gate_class, int tile
   return QF_OK;
 }
 
+int qf_set_pass2_tiles(qf_ctx* ctx, int precision, int n, int tiles) {
+  if (!ctx) return QF_EINVAL;
+  if (precision != QF_C128 && precision != QF_C64) return fail(ctx, QF_EINVAL, "unknown precision");
+  if (n < 4 || n > 16) return fail(ctx, QF_EINVAL, "n=%d outside [4, 16]", n);
+  if (tiles != 0 && tiles != 1 && tiles != 2 && tiles != 4 && tiles != 8)
+    return fail(ctx, QF_EINVAL, "tiles %d not supported", tiles);
+  ctx->tuned_pass2[precision == QF_C64][n] = tiles;
+  return QF_OK;
+}
+
 size_t qf_workspace_size(int n, int n_gates, int n_starts, const qf_options* opt) {
   qf_options o;
   if (opt)

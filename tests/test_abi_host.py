@@ -152,6 +152,7 @@ def test_null_context_is_rejected_before_device_work(lib):
                                None) == nat.QF_EINVAL
     assert lib.qf_optimize_gate3(None, 1, None, None, 0.0, None) == nat.QF_EINVAL
     assert lib.qf_optimize_gate(None, 1, None, None, 0.0, None) == nat.QF_EINVAL
+    assert lib.qf_set_pass2_tiles(None, 1, 10, 4) == nat.QF_EINVAL
     assert lib.qf_destroy(None) == nat.QF_EINVAL
     ctx = ctypes.c_void_p()
     assert lib.qf_create(None, 0, None) == nat.QF_EINVAL

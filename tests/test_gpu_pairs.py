@@ -143,6 +143,38 @@ def test_pairs_with_gate_kinds_match_oracle(qf):
     assert np.abs(host(res.all_gates) - ref.all_gates).max() <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_pass2_tiles_bitwise_equal(qf, precision):
+    """Every tiles-per-workgroup count of the two-gate pass (1, 2, 4, 8: the
+    complex64 form stages the operands of each workgroup's tiles in LDS by
+    their order) gives bitwise the same gates and costs over two sweeps of
+    n = 10 with 16 starts, and the first two starts' costs follow the oracle."""
+    import torch
+    cuda = torch.device("cuda", 0)
+    pr = I.config3(n_starts=16)
+    sweeps = 2
+    kw = dict(tol=1e-300, mode=2, max_iter=sweeps, precision=precision, diff_tol_r=0.0, long_diff_count=0,
+              history_rows=sweeps + 1, gate_pairs=2)
+    V, g = dev(pr.target), dev(pr.init_gates)
+    runs = []
+    try:
+        for tiles in (1, 2, 4, 8):
+            qf.set_pass2_tiles(cuda, precision, 10, tiles)
+            runs.append(qf.instantiate(V, pr.locs, g, **kw))
+    finally:
+        qf.set_pass2_tiles(cuda, precision, 10, 0)
+    for r in runs[1:]:
+        assert np.array_equal(host(r.all_gates), host(runs[0].all_gates))
+        assert np.array_equal(r.costs, runs[0].costs)
+    # the oracle on the first two starts (each start's sweeps are independent)
+    ref = O.instantiate(pr.target, pr.init_gates[:2], pr.locs, 10, tol=1e-300,
+                        opt=O.Options(max_iter=sweeps, diff_tol_r=0.0, long_diff_count=0))
+    tol = C128_TOL if precision == 0 else C64_TOL
+    assert np.abs(runs[0].history[:, :2] - ref.history).max() <= tol
+    with pytest.raises(Exception):
+        qf.set_pass2_tiles(cuda, precision, 10, 3)
+
+
 def test_pairs_timing_counts_units(qf):
     """The timing run counts one pass and one environment launch per update
     unit (a pair or a single gate) and gives bitwise the default schedule's
